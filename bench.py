@@ -1,0 +1,175 @@
+"""Benchmark of the gfx950 hierarchical slope-intercept Hough vote.
+
+One step = one full detection (edge staging from a binary image resident in
+HBM, then the level-synchronous vote of both passes down to the finest
+level, with every detected cell's voters kept on the device) of the
+1024x1024 segment workload: 32 segments of length U[200, 1000] px, 1-2 px
+thick, 2% salt noise, seed 0, T = 120, depth 10, 4-bit corner code variant.
+
+Prints one JSON line.  ``value`` is line-region code tests per second
+(code tests = E + 4 * sum of the votes of the regions that split, summed
+over both passes), images per second is reported beside it.  ``roofline``
+prices the dominant kernel (the per-level vote/compaction launch) against
+MI355X HBM bandwidth: its algorithmic bytes per step divided by its summed
+launch duration, measured with HIP events on the library's stream during
+the timed steps.  ``cpu_baseline`` times the CPU oracle on the same image.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def alg_bytes(stats_by_pass, detected_votes_by_pass, E):
+    """Algorithmic bytes of the vote/compaction launches of one detection.
+
+    Per pass: level 0 reads the coordinates of every line (8 B, the root
+    list is implicit); every deeper level reads a 4 B id plus 8 B of
+    coordinates per (parent, line) entry; every entry written to a kept
+    child's list costs 4 B.  With L_l the summed votes of the regions split
+    at level l and L_D the summed votes of the detected cells:
+        8 E + sum_{1<=l<D} 12 L_l + sum_{1<=l<=D} 4 L_l."""
+    total = 0
+    for p, st in stats_by_pass.items():
+        D = len(st) - 1
+        if D < 1 or st[0]["split"] == 0:
+            continue
+        L = [int(st[l]["entries"]) for l in range(D)] + [int(detected_votes_by_pass[p])]
+        total += 8 * E + sum(12 * L[l] for l in range(1, D)) + sum(4 * L[l] for l in range(1, D + 1))
+    return total
+
+
+def cpu_baseline(image, W, H, T, depth, budget_s=12.0):
+    import oracle
+    x, y = oracle.edge_points(image)
+    runs, t_total, tests = 0, 0.0, 0
+    while t_total < budget_s or runs == 0:
+        t0 = time.perf_counter()
+        r = oracle.detect(x, y, W, H, T, depth)
+        t_total += time.perf_counter() - t0
+        tests += r.code_tests()
+        runs += 1
+        if runs >= 50:
+            break
+    return {"value": tests / t_total, "unit": "code tests/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full benchmark image (both passes), {runs} run(s), "
+                      f"{t_total:.1f} s single-threaded C oracle",
+            "seconds_per_image": t_total / runs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="seg1024")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--variant", default="code", choices=["code", "circle"])
+    ap.add_argument("--wide", action="store_true", help="64-bit corner compares")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload, args.seed)
+    img = torch.from_numpy(w.image).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    ctx = HoughHier(threshold=w.threshold, max_depth=w.max_depth, variant=args.variant,
+                    membership=True, device=0, stream=stream, wide_compare=args.wide,
+                    timing=True)
+
+    def step():
+        r = ctx.detect(image=img, width=w.width, height=w.height)
+        return r
+
+    for _ in range(args.warmup):
+        step().free()
+    torch.cuda.synchronize(dev)
+
+    lat = []
+    vote_ms = decide_ms = total_ms = 0.0
+    vote_launches = 0
+    info = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        r = step()
+        lat.append(time.perf_counter() - t0)
+        tm = r.timing()
+        vote_ms += tm["vote_ms"]
+        decide_ms += tm["decide_ms"]
+        total_ms += tm["total_ms"]
+        vote_launches += tm["vote_launches"]
+        info = r.info
+        r.free()
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t_start
+
+    # one more detection, outside the timed region, for the statistics
+    r = step()
+    stats = {p: r.stats(p) for p in (0, 1)}
+    det_votes = {p: int(r.cells(p)["votes"].astype(np.int64).sum()) for p in (0, 1)}
+    r.free()
+    E = int(info["n_points"])
+    code_tests = int(info["code_tests"])
+    alg = alg_bytes(stats, det_votes, E)
+    achieved = alg / (vote_ms / args.steps / 1e3) / 1e9 if vote_ms > 0 else 0.0
+
+    ms_per_step = elapsed / args.steps * 1e3
+    out = {
+        "metric": "line-region code tests/s (plain, one image per call)",
+        "value": code_tests * args.steps / elapsed,
+        "unit": "code tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"int{info['compare_bits']}",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.width}x{w.height} binary image, seed {args.seed}, "
+                        f"T={w.threshold}, depth {info['depth']}, both passes, "
+                        f"{args.variant} variant, voters kept on device",
+            "E": E, "cells": sum(info["n_cells"]), "code_tests_per_image": code_tests,
+        },
+        "images_per_s": args.steps / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "kernel_ms_per_step": {"vote": vote_ms / args.steps, "decide": decide_ms / args.steps,
+                               "device_total": total_ms / args.steps},
+        "roofline": {"bound": "hbm", "kernel": "k_vote", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "alg_bytes_per_step": alg,
+                     "launches_per_step": vote_launches / args.steps},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w.image, w.width, w.height, w.threshold, w.max_depth)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

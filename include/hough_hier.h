@@ -1,0 +1,223 @@
+/*
+ * hough_hier.h -- C ABI of the MI355X (gfx950) hierarchical slope-intercept
+ * Hough vote of C. Singh and N. Bhatia, "A Fast Decision Technique for
+ * Hierarchical Hough Transform for Line Detection" (arXiv:1007.0547).
+ *
+ * What the library computes (per image and enabled pass):
+ *   - Sec. 1 and Sec. 3 (ALPHA/BETA): pass 0 maps each edge point (x, y) to
+ *     the parameter line b = y - x*m with |m| <= 1; pass 1 swaps the axes and
+ *     maps it to b = x - y*m.  Every edge point enters both passes.
+ *   - Sec. 3: a quadtree over the parameter space.  Level 0 is the whole
+ *     space m in [-1, 1], b in [-S, 2S] with S = 2^ceil(log2(max(W, H))).
+ *     Region (l, i, j) spans m in [-1 + 2i/2^l, -1 + 2(i+1)/2^l] and
+ *     b in [-S + 3S j/2^l, -S + 3S (j+1)/2^l]; east is +m, north is +b, and
+ *     its children are taken in the order quad1..quad4 = NE, NW, SW, SE.
+ *   - Sec. 2, getcode(): for every (region, line) pair a 4-bit code, one bit
+ *     per corner in the order NE, NW, SW, SE (NE leftmost), 1 when the corner
+ *     is below the line; a corner on the line counts as above.  Corners are
+ *     dyadic, so each bit is an exact integer compare with m and b scaled by
+ *     2^level.
+ *   - Sec. 3 pseudo-code (steps 5, 12.b, 12.v, 13): a line votes for a region
+ *     iff its code is neither 0000 nor 1111; a child only tests the lines
+ *     that voted for its parent; a region with votes > threshold splits, and
+ *     at the finest level (default ceil(log2 N)) it is reported as a
+ *     detected cell together with its voters (solution(), without removal).
+ *   - Sec. 2 / Sec. 3, comparison method of the paper's ref. [9]
+ *     (HH_VARIANT_CIRCLE): a line votes iff its distance from the region's
+ *     centre is at most the circumradius, distances measured in units where a
+ *     region is a square, as an exact integer inequality with no square root.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns hh_status; nothing throws or aborts across the ABI.
+ *     hough_hier_last_error() returns the text of the last failure on a
+ *     context.
+ *   - Point ids are positions in the input point list (for an image input:
+ *     rank in a row-major scan, y then x).  Ids are int32.
+ *   - Output cells are sorted by (pass, key), where key holds the quad digits
+ *     NE=0, NW=1, SW=2, SE=3 of the path from level 1 down, most significant
+ *     first (the paper's depth-first visiting order).  Each cell's voters are
+ *     ascending point ids.
+ *   - All GPU work of a call runs on the context's stream.  A call returns
+ *     when its result (cells, members, statistics) is complete on the device.
+ *   - A context is not thread-safe across concurrent calls; use one context
+ *     per thread, or serialise calls.
+ */
+#ifndef HOUGH_HIER_H
+#define HOUGH_HIER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define HH_API __attribute__((visibility("default")))
+#else
+#define HH_API
+#endif
+
+typedef struct hh_ctx hh_ctx;
+typedef struct hh_result hh_result;
+
+typedef enum {
+    HH_OK = 0,
+    HH_EINVAL = -1,      /* bad argument: null pointer, W or H < 1, point outside
+                            [0,W)x[0,H), threshold < 0, depth out of range, size limit */
+    HH_ENOMEM = -2,      /* device or host allocation failed                          */
+    HH_ECAPACITY = -3,   /* a size limit of the implementation was exceeded          */
+    HH_EDEVICE = -4,     /* HIP error, or the device is not a gfx950                  */
+    HH_EBUSY = -5,       /* no free slot                                              */
+    HH_ECANCELED = -6,
+    HH_EINTERNAL = -7    /* an internal consistency check failed                      */
+} hh_status;
+
+typedef enum {
+    HH_VARIANT_CODE = 0,     /* 4-bit corner code (Sec. 2)                    */
+    HH_VARIANT_CIRCLE = 1    /* circumscribed-circle test (comparison method) */
+} hh_variant;
+
+#define HH_PASS_0 1u         /* |m| <= 1 as given (ALPHA)                   */
+#define HH_PASS_1 2u         /* axes swapped (BETA)                         */
+
+/* hh_config.flags */
+#define HH_FLAG_WIDE_COMPARE 1   /* code variant: use 64-bit compares even where 32-bit
+                                    compares are provably exact                         */
+#define HH_FLAG_TIMING 2         /* record HIP events around every kernel launch; read them
+                                    with hough_hier_result_timing()                    */
+
+/* Limits: max(W, H) <= 16384, depth <= 15 and S * 2^depth <= 2^28 (keeps every
+ * scaled corner value inside 31 bits and the circle test inside 63 bits);
+ * number of points <= 2^31 - 1. */
+#define HH_MAX_SIDE 16384
+#define HH_MAX_DEPTH 15
+
+typedef struct {
+    int32_t threshold;        /* default T >= 0 for inputs that give threshold < 0     */
+    int32_t max_depth;        /* default depth: 0 = ceil(log2(max(W,H))), -1 = depth 0  */
+    uint32_t passes;          /* HH_PASS_0 | HH_PASS_1; 0 is taken as both              */
+    int32_t variant;          /* hh_variant                                             */
+    int32_t membership;       /* 1: keep each detected cell's voters; 0: counts only    */
+    int32_t device;           /* HIP device ordinal; the device must be a gfx950        */
+    void* stream;             /* hipStream_t for all work, or NULL for the null stream  */
+    int32_t flags;            /* HH_FLAG_*                                              */
+    int32_t reserved0;
+    uint64_t reserved1;
+} hh_config;
+
+typedef struct {
+    int32_t kind;             /* 0: point list (x, y, n_points); 1: binary image        */
+    int32_t width, height;    /* W, H >= 1                                              */
+    int32_t on_device;        /* 1: x, y, image are device pointers valid on the stream */
+    const int32_t* x;         /* kind 0: x[k] in [0, W)                                 */
+    const int32_t* y;         /* kind 0: y[k] in [0, H)                                 */
+    int64_t n_points;         /* kind 0: number of points (0 allowed)                   */
+    const uint8_t* image;     /* kind 1: H rows of W bytes, nonzero = edge pixel         */
+    int64_t row_stride;       /* kind 1: bytes between rows (>= W; 0 means W)            */
+    int32_t threshold;        /* T for this input; < 0 takes the context default        */
+    int32_t max_depth;        /* depth for this input: 0 = ceil(log2(max(W,H))),
+                                 -1 = depth 0, INT32_MIN takes the context default      */
+} hh_input;
+
+/* One detected finest-level cell.  member_off indexes the members array that
+ * hough_hier_result_members() returns with the same on_device value. */
+typedef struct {
+    int32_t i, j;             /* cell indices at the finest level                       */
+    int32_t votes;            /* number of voters (lines crossing the cell)             */
+    int32_t pass;             /* 0 or 1                                                 */
+    int64_t key;              /* quad-digit path key                                    */
+    int64_t member_off;       /* first voter in the members array, or -1 if not kept    */
+} hh_cell;
+
+/* Per-level statistics of one pass (level 0 = root). */
+typedef struct {
+    int64_t evaluated;        /* regions whose votes were counted                       */
+    int64_t votes;            /* sum of their votes (the paper's "number of votes")     */
+    int64_t split;            /* regions with votes > T below the finest level          */
+    int64_t detected;         /* regions with votes > T at the finest level             */
+    int64_t code_tests;       /* (region, line) codes computed at this level            */
+    int64_t entries;          /* summed votes of the regions split at this level        */
+} hh_level_stats;
+
+typedef struct {
+    int64_t n_points;         /* E                                                      */
+    int32_t width, height;
+    int32_t side_pow2;        /* S                                                      */
+    int32_t depth;            /* finest level                                           */
+    int32_t threshold;
+    uint32_t passes;
+    int64_t n_cells[2];       /* detected cells per pass                                */
+    int64_t code_tests;       /* summed over levels and passes                          */
+    int64_t member_slots;     /* length of the device members array                     */
+    int32_t compare_bits;     /* 32 or 64: width of the corner compares used            */
+    int32_t reserved;
+} hh_result_info;
+
+/* Kernel timings of one call (HH_FLAG_TIMING), from HIP events recorded on
+ * the context's stream around each launch; zero without the flag. */
+typedef struct {
+    int32_t vote_launches;    /* per-level vote/compaction kernel launches          */
+    int32_t decide_launches;  /* per-level split-decision kernel launches           */
+    double vote_ms;           /* summed duration of the vote/compaction launches    */
+    double decide_ms;         /* summed duration of the split-decision launches     */
+    double extract_ms;        /* edge staging (image inputs)                        */
+    double total_ms;          /* first to last event of the call                    */
+    int64_t vote_entries;     /* (parent, line) entries read by the vote launches   */
+    int64_t vote_written;     /* entries written by the vote launches               */
+} hh_timing;
+
+/* Create a context on cfg->device.  Checks the device is a gfx950.
+ * Errors: HH_EINVAL (cfg or out NULL, bad defaults), HH_EDEVICE. */
+HH_API hh_status hough_hier_create(const hh_config* cfg, hh_ctx** out);
+
+/* Destroy a context and release all its device memory, including the memory
+ * of results not yet freed (those handles must not be used afterwards).
+ * NULL is accepted. */
+HH_API void hough_hier_destroy(hh_ctx* ctx);
+
+/* Text of the last error on ctx (never NULL; empty if none). */
+HH_API const char* hough_hier_last_error(const hh_ctx* ctx);
+
+/* Run the hierarchical vote (Sec. 3) on one input: edge staging (image
+ * inputs), then levels 0 .. depth-1 for every enabled pass.  Inputs are
+ * borrowed for the duration of the call.  On HH_OK *out owns the result;
+ * release it with hough_hier_result_free().
+ * Errors: HH_EINVAL (see hh_status; also for device point lists with a point
+ * out of range), HH_ENOMEM, HH_EDEVICE, HH_EINTERNAL. */
+HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
+
+/* Cells of one pass (0 or 1), sorted by key.  on_device = 1 returns a device
+ * pointer (member_off indexes the device members array); on_device = 0 copies
+ * to host memory owned by the result (member_off indexes the host members
+ * array).  A pass that was not enabled has no cells.
+ * Errors: HH_EINVAL, HH_EDEVICE. */
+HH_API hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_device,
+                                  const hh_cell** cells, int64_t* n);
+
+/* Voters of the detected cells.  on_device = 1: the device list buffer
+ * (length *n; slots not referenced by any cell are unspecified);
+ * on_device = 0: a compact host array, cells in (pass, key) order.
+ * Both stay valid until hough_hier_result_free().  Errors: HH_EINVAL
+ * (membership was not kept), HH_EDEVICE. */
+HH_API hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int32_t** ids,
+                                    int64_t* n);
+
+/* Host per-level statistics of one pass: *n_levels = depth + 1 entries. */
+HH_API hh_status hough_hier_result_stats(const hh_result* res, int32_t pass,
+                                  const hh_level_stats** levels, int32_t* n_levels);
+
+/* Sizes and parameters of a result. */
+HH_API hh_status hough_hier_result_info(const hh_result* res, hh_result_info* info);
+
+/* Kernel timings of the call that produced res (see hh_timing). */
+HH_API hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timing);
+
+/* Release a result (its device memory returns to the context).  NULL is
+ * accepted. */
+HH_API void hough_hier_result_free(hh_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOUGH_HIER_H */

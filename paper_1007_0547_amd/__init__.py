@@ -1,0 +1,293 @@
+"""Python binding of the gfx950 hierarchical slope-intercept Hough vote.
+
+A thin ctypes layer over ``libhough_hier.so`` (C ABI in
+``include/hough_hier.h``): it marshals arguments and results, nothing else.
+Every step of the vote runs in the library's HIP kernels.  PyTorch is used
+only to hand over device memory (``torch.Tensor.data_ptr()``) and streams.
+
+Importing this package requires the built library; build it with
+``python -c "import __graft_entry__ as g; g.build()"`` (or
+``python paper_1007_0547_amd/_build.py``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["HoughHier", "Result", "HHError", "CELL_DTYPE", "STATS_DTYPE", "LIB_PATH",
+           "status_name", "library"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhough_hier.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python paper_1007_0547_amd/_build.py)")
+
+_lib = C.CDLL(LIB_PATH)
+
+STATUS = {0: "HH_OK", -1: "HH_EINVAL", -2: "HH_ENOMEM", -3: "HH_ECAPACITY", -4: "HH_EDEVICE",
+          -5: "HH_EBUSY", -6: "HH_ECANCELED", -7: "HH_EINTERNAL"}
+INT32_MIN = -(1 << 31)
+
+
+def status_name(s: int) -> str:
+    return STATUS.get(int(s), str(s))
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{status_name(status)}: {msg}" if msg else status_name(status))
+        self.status = int(status)
+
+
+class _Config(C.Structure):
+    _fields_ = [("threshold", C.c_int32), ("max_depth", C.c_int32), ("passes", C.c_uint32),
+                ("variant", C.c_int32), ("membership", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p), ("flags", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_uint64)]
+
+
+class _Input(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("on_device", C.c_int32), ("x", C.c_void_p), ("y", C.c_void_p),
+                ("n_points", C.c_int64), ("image", C.c_void_p), ("row_stride", C.c_int64),
+                ("threshold", C.c_int32), ("max_depth", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("width", C.c_int32), ("height", C.c_int32),
+                ("side_pow2", C.c_int32), ("depth", C.c_int32), ("threshold", C.c_int32),
+                ("passes", C.c_uint32), ("n_cells", C.c_int64 * 2), ("code_tests", C.c_int64),
+                ("member_slots", C.c_int64), ("compare_bits", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Timing(C.Structure):
+    _fields_ = [("vote_launches", C.c_int32), ("decide_launches", C.c_int32),
+                ("vote_ms", C.c_double), ("decide_ms", C.c_double), ("extract_ms", C.c_double),
+                ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64)]
+
+
+CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),
+                       ("key", np.int64), ("member_off", np.int64)])
+STATS_DTYPE = np.dtype([("evaluated", np.int64), ("votes", np.int64), ("split", np.int64),
+                        ("detected", np.int64), ("code_tests", np.int64), ("entries", np.int64)])
+assert CELL_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 48
+
+_p = C.c_void_p
+_lib.hough_hier_create.restype = C.c_int
+_lib.hough_hier_create.argtypes = [C.POINTER(_Config), C.POINTER(_p)]
+_lib.hough_hier_destroy.restype = None
+_lib.hough_hier_destroy.argtypes = [_p]
+_lib.hough_hier_last_error.restype = C.c_char_p
+_lib.hough_hier_last_error.argtypes = [_p]
+_lib.hough_hier_detect.restype = C.c_int
+_lib.hough_hier_detect.argtypes = [_p, C.POINTER(_Input), C.POINTER(_p)]
+_lib.hough_hier_result_cells.restype = C.c_int
+_lib.hough_hier_result_cells.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int64)]
+_lib.hough_hier_result_members.restype = C.c_int
+_lib.hough_hier_result_members.argtypes = [_p, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int64)]
+_lib.hough_hier_result_stats.restype = C.c_int
+_lib.hough_hier_result_stats.argtypes = [_p, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int32)]
+_lib.hough_hier_result_info.restype = C.c_int
+_lib.hough_hier_result_info.argtypes = [_p, C.POINTER(_Info)]
+_lib.hough_hier_result_timing.restype = C.c_int
+_lib.hough_hier_result_timing.argtypes = [_p, C.POINTER(_Timing)]
+_lib.hough_hier_result_free.restype = None
+_lib.hough_hier_result_free.argtypes = [_p]
+
+
+def library() -> C.CDLL:
+    """The loaded ``libhough_hier.so``."""
+    return _lib
+
+
+def _is_torch_cuda(t) -> bool:
+    return hasattr(t, "is_cuda") and bool(t.is_cuda)
+
+
+def _host_array(a, dtype) -> np.ndarray:
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Result:
+    """A detection result; owns device memory until :meth:`free`."""
+
+    def __init__(self, ctx: "HoughHier", handle: int):
+        self._ctx = ctx
+        self._h = C.c_void_p(handle)
+        inf = _Info()
+        self._check(_lib.hough_hier_result_info(self._h, C.byref(inf)))
+        self.info = {k: (list(getattr(inf, k)) if k == "n_cells" else getattr(inf, k))
+                     for k, _ in _Info._fields_ if k != "reserved"}
+
+    def _check(self, s):
+        if s != 0:
+            raise HHError(s, self._ctx.last_error())
+
+    def timing(self) -> dict:
+        """Kernel timings of the call (contexts created with ``timing=True``)."""
+        t = _Timing()
+        self._check(_lib.hough_hier_result_timing(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _Timing._fields_}
+
+    def cells(self, pass_: int) -> np.ndarray:
+        """Host copy of one pass's cells (structured array, ``CELL_DTYPE``);
+        ``member_off`` indexes :meth:`members`."""
+        ptr, n = C.c_void_p(), C.c_int64()
+        self._check(_lib.hough_hier_result_cells(self._h, pass_, 0, C.byref(ptr), C.byref(n)))
+        if n.value == 0:
+            return np.zeros(0, dtype=CELL_DTYPE)
+        buf = (C.c_char * (n.value * CELL_DTYPE.itemsize)).from_address(ptr.value)
+        return np.frombuffer(buf, dtype=CELL_DTYPE).copy()
+
+    def device_cells(self, pass_: int):
+        """``(device_pointer, count)`` of one pass's cells on the device."""
+        ptr, n = C.c_void_p(), C.c_int64()
+        self._check(_lib.hough_hier_result_cells(self._h, pass_, 1, C.byref(ptr), C.byref(n)))
+        return (ptr.value or 0), n.value
+
+    def members(self) -> np.ndarray:
+        """Host copy of all voters, compact, cells in (pass, key) order."""
+        ptr, n = C.c_void_p(), C.c_int64()
+        self._check(_lib.hough_hier_result_members(self._h, 0, C.byref(ptr), C.byref(n)))
+        if n.value == 0:
+            return np.zeros(0, dtype=np.int32)
+        buf = (C.c_int32 * n.value).from_address(ptr.value)
+        return np.frombuffer(buf, dtype=np.int32).copy()
+
+    def device_members(self):
+        """``(device_pointer, slots)`` of the device voter buffer."""
+        ptr, n = C.c_void_p(), C.c_int64()
+        self._check(_lib.hough_hier_result_members(self._h, 1, C.byref(ptr), C.byref(n)))
+        return (ptr.value or 0), n.value
+
+    def stats(self, pass_: int) -> np.ndarray:
+        """Per-level statistics (``STATS_DTYPE``), level 0 first."""
+        ptr, n = C.c_void_p(), C.c_int32()
+        self._check(_lib.hough_hier_result_stats(self._h, pass_, C.byref(ptr), C.byref(n)))
+        if n.value == 0:
+            return np.zeros(0, dtype=STATS_DTYPE)
+        buf = (C.c_char * (n.value * STATS_DTYPE.itemsize)).from_address(ptr.value)
+        return np.frombuffer(buf, dtype=STATS_DTYPE).copy()
+
+    def stats_array(self, pass_: int) -> np.ndarray:
+        """Statistics as an int64 array of shape (depth + 1, 6)."""
+        s = self.stats(pass_)
+        return s.view(np.int64).reshape(len(s), 6) if len(s) else np.zeros((0, 6), np.int64)
+
+    def free(self):
+        if self._h:
+            _lib.hough_hier_result_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._ctx._h:
+                self.free()
+        except Exception:
+            pass
+
+
+class HoughHier:
+    """A context on one gfx950 device (``hough_hier_create``)."""
+
+    def __init__(self, threshold: int = 0, max_depth: int = 0, passes: int = 3,
+                 variant: str = "code", membership: bool = True, device: int = 0,
+                 stream=None, wide_compare: bool = False, timing: bool = False):
+        cfg = _Config()
+        cfg.threshold = int(threshold)
+        cfg.max_depth = int(max_depth)
+        cfg.passes = int(passes)
+        cfg.variant = {"code": 0, "circle": 1}[variant]
+        cfg.membership = 1 if membership else 0
+        cfg.device = int(device)
+        cfg.stream = self._stream_handle(stream)
+        cfg.flags = (1 if wide_compare else 0) | (2 if timing else 0)
+        h = C.c_void_p()
+        s = _lib.hough_hier_create(C.byref(cfg), C.byref(h))
+        if s != 0:
+            raise HHError(s, "hough_hier_create failed")
+        self._h = h
+
+    @staticmethod
+    def _stream_handle(stream) -> Optional[int]:
+        if stream is None:
+            return None
+        if isinstance(stream, int):
+            return stream
+        return int(stream.cuda_stream)   # torch.cuda.Stream
+
+    def last_error(self) -> str:
+        if not self._h:
+            return ""
+        return (_lib.hough_hier_last_error(self._h) or b"").decode()
+
+    def detect(self, x=None, y=None, *, image=None, width: int, height: int,
+               threshold: int = -1, max_depth: Optional[int] = None) -> Result:
+        """Run the vote on a point list ``(x, y)`` or a binary ``image``
+        (H x W, nonzero = edge).  Torch device tensors are passed as device
+        pointers; anything else is copied from host memory."""
+        inp = _Input()
+        inp.width, inp.height = int(width), int(height)
+        inp.threshold = int(threshold)
+        inp.max_depth = INT32_MIN if max_depth is None else int(max_depth)
+        keep = []
+        if image is not None:
+            inp.kind = 1
+            if _is_torch_cuda(image):
+                assert image.dtype.itemsize == 1 and image.dim() == 2
+                inp.on_device = 1
+                inp.image = image.data_ptr()
+                inp.row_stride = int(image.stride(0))
+                keep.append(image)
+            else:
+                img = _host_array(image, np.uint8)
+                inp.on_device = 0
+                inp.image = img.ctypes.data
+                inp.row_stride = int(img.strides[0])
+                keep.append(img)
+        else:
+            inp.kind = 0
+            if _is_torch_cuda(x):
+                assert x.is_contiguous() and y.is_contiguous()
+                assert str(x.dtype) == "torch.int32" and str(y.dtype) == "torch.int32"
+                inp.on_device = 1
+                inp.x, inp.y = x.data_ptr(), y.data_ptr()
+                inp.n_points = int(x.numel())
+                keep += [x, y]
+            else:
+                hx, hy = _host_array(x, np.int32), _host_array(y, np.int32)
+                if hx.shape != hy.shape:
+                    raise ValueError("x and y must have the same length")
+                inp.on_device = 0
+                inp.x, inp.y = hx.ctypes.data, hy.ctypes.data
+                inp.n_points = int(hx.size)
+                keep += [hx, hy]
+        out = C.c_void_p()
+        s = _lib.hough_hier_detect(self._h, C.byref(inp), C.byref(out))
+        if s != 0:
+            raise HHError(s, self.last_error())
+        return Result(self, out.value)
+
+    def close(self):
+        if self._h:
+            _lib.hough_hier_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,157 @@
+// C ABI of the hierarchical Hough vote library (declarations and contracts in
+// include/hough_hier.h).  Every entry point converts internal errors into an
+// hh_status and records the message on the context.
+#include <exception>
+#include <new>
+#include <string>
+
+#include "hh_engine.hpp"
+
+namespace {
+
+hh_status fail(hh_ctx* ctx, hh_status s, const std::string& msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+template <typename F>
+hh_status guarded(hh_ctx* ctx, F&& f)
+{
+    try {
+        return f();
+    } catch (const hh::Error& e) {
+        return fail(ctx, e.status, e.what);
+    } catch (const std::bad_alloc&) {
+        return fail(ctx, HH_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(ctx, HH_EINTERNAL, e.what());
+    } catch (...) {
+        return fail(ctx, HH_EINTERNAL, "unknown error");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+hh_status hough_hier_create(const hh_config* cfg, hh_ctx** out)
+{
+    if (!cfg || !out) return HH_EINVAL;
+    *out = nullptr;
+    if (cfg->threshold < 0 || cfg->max_depth < -1 || cfg->max_depth > HH_MAX_DEPTH ||
+        (cfg->variant != HH_VARIANT_CODE && cfg->variant != HH_VARIANT_CIRCLE) ||
+        (cfg->passes & ~(HH_PASS_0 | HH_PASS_1)) != 0 || (cfg->membership != 0 && cfg->membership != 1))
+        return HH_EINVAL;
+    try {
+        return hh::engine_create(cfg, out);
+    } catch (...) {
+        return HH_EINTERNAL;
+    }
+}
+
+void hough_hier_destroy(hh_ctx* ctx)
+{
+    try {
+        hh::engine_destroy(ctx);
+    } catch (...) {
+    }
+}
+
+const char* hough_hier_last_error(const hh_ctx* ctx)
+{
+    if (!ctx) return "";
+    return ctx->last_error.c_str();
+}
+
+hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!in || !out) return fail(ctx, HH_EINVAL, "input and output pointers must not be NULL");
+    *out = nullptr;
+    ctx->last_error.clear();
+    return guarded(ctx, [&] { return hh::engine_detect(ctx, in, out); });
+}
+
+hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_device, const hh_cell** cells,
+                                  int64_t* n)
+{
+    if (!res || !cells || !n || (pass != 0 && pass != 1)) return HH_EINVAL;
+    *cells = nullptr;
+    *n = 0;
+    int64_t before = 0;
+    bool enabled = false;
+    for (int t = 0; t < res->n_trees; ++t) {
+        if (res->tree_pass[t] == pass) {
+            enabled = true;
+            break;
+        }
+        before += res->info.n_cells[res->tree_pass[t]];
+    }
+    if (!enabled) return HH_OK;
+    const int64_t count = res->info.n_cells[pass];
+    if (on_device) {
+        if (count > 0) *cells = res->cells.as<const hh_cell>() + before;
+        *n = count;
+        return HH_OK;
+    }
+    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_copy(res); });
+    if (s != HH_OK) return s;
+    if (count > 0) *cells = res->host_cells.data() + before;
+    *n = count;
+    return HH_OK;
+}
+
+hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int32_t** ids, int64_t* n)
+{
+    if (!res || !ids || !n) return HH_EINVAL;
+    *ids = nullptr;
+    *n = 0;
+    if (!res->have_members) return fail(res->ctx, HH_EINVAL, "membership was not kept");
+    if (on_device) {
+        *ids = res->members ? res->members.as<const int32_t>() : nullptr;
+        *n = res->info.member_slots;
+        return HH_OK;
+    }
+    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_copy(res); });
+    if (s != HH_OK) return s;
+    *ids = res->host_members.data();
+    *n = (int64_t)res->host_members.size();
+    return HH_OK;
+}
+
+hh_status hough_hier_result_stats(const hh_result* res, int32_t pass, const hh_level_stats** levels,
+                                  int32_t* n_levels)
+{
+    if (!res || !levels || !n_levels || (pass != 0 && pass != 1)) return HH_EINVAL;
+    *levels = res->stats[pass].empty() ? nullptr : res->stats[pass].data();
+    *n_levels = (int32_t)res->stats[pass].size();
+    return HH_OK;
+}
+
+hh_status hough_hier_result_info(const hh_result* res, hh_result_info* info)
+{
+    if (!res || !info) return HH_EINVAL;
+    *info = res->info;
+    return HH_OK;
+}
+
+hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timing)
+{
+    if (!res || !timing) return HH_EINVAL;
+    *timing = res->timing;
+    return HH_OK;
+}
+
+void hough_hier_result_free(hh_result* res)
+{
+    if (!res) return;
+    try {
+        (void)hipSetDevice(res->ctx->device);
+        res->ctx->live_results.erase(res);
+        delete res;
+    } catch (...) {
+    }
+}
+
+}  // extern "C"

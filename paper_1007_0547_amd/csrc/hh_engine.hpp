@@ -1,0 +1,114 @@
+// Host engine of the hierarchical Hough vote: device memory pool, context,
+// and the level-synchronous driver behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/hough_hier.h"
+#include "hh_types.hpp"
+
+namespace hh {
+
+// Caching allocator over hipMalloc.  Sizes are rounded up to one of eight
+// steps per power of two; freed blocks wait in per-size free lists and are
+// handed out again without a hipMalloc.  All users of one pool work on one
+// stream, so reuse is ordered by the stream.
+class DevicePool {
+public:
+    ~DevicePool();
+    void* alloc(size_t bytes);
+    void release(void* p);
+    void trim();
+    size_t live_bytes() const { return live_; }
+    size_t cached_bytes() const { return cached_; }
+
+private:
+    static size_t round_size(size_t bytes);
+    std::unordered_map<size_t, std::vector<void*>> free_;
+    std::unordered_map<void*, size_t> size_of_;
+    size_t live_ = 0, cached_ = 0;
+};
+
+// A pool block that returns to its pool on destruction.
+class DevBuf {
+public:
+    DevBuf() = default;
+    DevBuf(DevicePool* pool, size_t bytes);
+    ~DevBuf() { reset(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept;
+    void reset();
+    template <typename T> T* as() const { return static_cast<T*>(ptr_); }
+    void* get() const { return ptr_; }
+    size_t bytes() const { return bytes_; }
+    explicit operator bool() const { return ptr_ != nullptr; }
+
+private:
+    DevicePool* pool_ = nullptr;
+    void* ptr_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+struct Error {
+    hh_status status;
+    std::string what;
+};
+
+}  // namespace hh
+
+struct hh_result {
+    hh_ctx* ctx = nullptr;
+    hh_result_info info{};
+    int32_t n_trees = 0;
+    int32_t tree_pass[2] = {-1, -1};
+    std::vector<hh_level_stats> stats[2];
+    hh::DevBuf cells;          // all cells, (pass, key) order
+    int64_t n_cells_total = 0;
+    hh::DevBuf members;        // device voter lists referenced by cells
+    hh::DevBuf members_owner2; // second buffer kept alive when cells reference it
+    bool have_members = false;
+    hh_timing timing{};
+    // lazily filled host copies
+    bool host_ready = false;
+    std::vector<hh_cell> host_cells;
+    std::vector<int32_t> host_members;
+};
+
+struct hh_ctx {
+    hh_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    hh::DevicePool pool;
+    int cu_count = 0;
+    // pinned host staging
+    hh::LevelTotals* h_totals = nullptr;
+    hh::TreeDesc* h_trees = nullptr;
+    int64_t* h_scalar = nullptr;
+    uint32_t* h_error = nullptr;
+    // small device scratch: tickets, error word, totals, scalar
+    hh::DevBuf d_small;
+    // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
+    // then three per level (vote start, vote end = decide start, decide end)
+    std::vector<hipEvent_t> events;
+    // results not yet freed; destroyed with the context
+    std::unordered_set<hh_result*> live_results;
+};
+
+namespace hh {
+
+hh_status engine_create(const hh_config* cfg, hh_ctx** out);
+void engine_destroy(hh_ctx* ctx);
+hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
+hh_status engine_host_copy(hh_result* res);
+
+}  // namespace hh

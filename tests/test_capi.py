@@ -1,0 +1,79 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+function ``include/hough_hier.h`` declares, and rejects bad arguments before
+touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hough_hier.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"HH_API\s+[\w\s\*]+?\b(hough_hier_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("hough_hier_create", "hough_hier_destroy", "hough_hier_detect",
+              "hough_hier_result_cells", "hough_hier_result_members", "hough_hier_result_stats",
+              "hough_hier_result_info", "hough_hier_result_free", "hough_hier_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1007_0547_amd as hh
+    lib = hh.library()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    # nothing else with the prefix is exported by accident
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", hh.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted(set(re.findall(r"\b(hough_hier_\w+)\b", out)))
+    assert exported == declared_functions()
+
+
+def test_struct_layouts_match_header():
+    import paper_1007_0547_amd as hh
+    assert C.sizeof(hh._Config) == 48
+    assert C.sizeof(hh._Input) == 64
+    assert hh.CELL_DTYPE.itemsize == 32
+    assert hh.STATS_DTYPE.itemsize == 48
+
+
+def test_null_arguments_and_bad_config():
+    import paper_1007_0547_amd as hh
+    lib = hh.library()
+    h = C.c_void_p()
+    assert lib.hough_hier_create(None, C.byref(h)) == -1
+    cfg = hh._Config()
+    assert lib.hough_hier_create(C.byref(cfg), None) == -1
+    for field, bad in (("threshold", -1), ("max_depth", 16), ("max_depth", -2), ("variant", 2),
+                       ("passes", 4), ("membership", 2)):
+        cfg = hh._Config()
+        setattr(cfg, field, bad)
+        assert lib.hough_hier_create(C.byref(cfg), C.byref(h)) == -1, field
+    lib.hough_hier_destroy(None)
+    assert lib.hough_hier_last_error(None) == b""
+    assert lib.hough_hier_detect(None, None, None) == -1
+    p, n = C.c_void_p(), C.c_int64()
+    assert lib.hough_hier_result_cells(None, 0, 0, C.byref(p), C.byref(n)) == -1
+    assert lib.hough_hier_result_members(None, 0, C.byref(p), C.byref(n)) == -1
+    n32 = C.c_int32()
+    assert lib.hough_hier_result_stats(None, 0, C.byref(p), C.byref(n32)) == -1
+    assert lib.hough_hier_result_info(None, None) == -1
+    lib.hough_hier_result_free(None)
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1007_0547_amd as hh
+    with pytest.raises(hh.HHError) as e:
+        hh.HoughHier(threshold=1)
+    assert e.value.status == -4
