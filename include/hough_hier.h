@@ -194,13 +194,23 @@ HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** 
 HH_API hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_device,
                                   const hh_cell** cells, int64_t* n);
 
-/* Voters of the detected cells.  on_device = 1: the device list buffer
- * (length *n; slots not referenced by any cell are unspecified);
- * on_device = 0: a compact host array, cells in (pass, key) order.
- * Both stay valid until hough_hier_result_free().  Errors: HH_EINVAL
- * (membership was not kept), HH_EDEVICE. */
+/* Point ids of the voters of the detected cells (ascending within a cell).
+ * on_device = 1: a device array of *n slots in the layout of the device
+ * cells' member_off (slots no cell references are unspecified), made on the
+ * first request; on_device = 0: a compact host array, cells in (pass, key)
+ * order.  Both stay valid until hough_hier_result_free().
+ * Errors: HH_EINVAL (membership was not kept), HH_EDEVICE. */
 HH_API hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int32_t** ids,
                                     int64_t* n);
+
+/* The voters as the kernels left them, with no conversion: a device array of
+ * *n entries in the layout of the device cells' member_off.  *entry_bytes = 4:
+ * each entry is an edge point packed as x | y << 16 (image inputs; ascending
+ * packed value = ascending id); *entry_bytes = 8: (id << 32) | packed point
+ * (point-list inputs).  Valid until hough_hier_result_free().
+ * Errors: HH_EINVAL (membership was not kept). */
+HH_API hh_status hough_hier_result_member_points(const hh_result* res, const void** entries, int64_t* n,
+                                          int32_t* entry_bytes);
 
 /* Host per-level statistics of one pass: *n_levels = depth + 1 entries. */
 HH_API hh_status hough_hier_result_stats(const hh_result* res, int32_t pass,

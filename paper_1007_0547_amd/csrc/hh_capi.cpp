@@ -91,7 +91,7 @@ hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_devic
     if (!enabled) return HH_OK;
     const int64_t count = res->info.n_cells[pass];
     if (on_device) {
-        if (count > 0) *cells = res->cells.as<const hh_cell>() + before;
+        if (count > 0) *cells = reinterpret_cast<const hh_cell*>(res->cells) + before;
         *n = count;
         return HH_OK;
     }
@@ -109,7 +109,9 @@ hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int
     *n = 0;
     if (!res->have_members) return fail(res->ctx, HH_EINVAL, "membership was not kept");
     if (on_device) {
-        *ids = res->members ? res->members.as<const int32_t>() : nullptr;
+        hh_status s = guarded(res->ctx, [&] { return hh::engine_device_ids(res); });
+        if (s != HH_OK) return s;
+        *ids = res->dev_ids ? res->dev_ids.as<const int32_t>() : nullptr;
         *n = res->info.member_slots;
         return HH_OK;
     }
@@ -117,6 +119,19 @@ hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int
     if (s != HH_OK) return s;
     *ids = res->host_members.data();
     *n = (int64_t)res->host_members.size();
+    return HH_OK;
+}
+
+hh_status hough_hier_result_member_points(const hh_result* res, const void** entries, int64_t* n,
+                                         int32_t* entry_bytes)
+{
+    if (!res || !entries || !n || !entry_bytes) return HH_EINVAL;
+    *entries = nullptr;
+    *n = 0;
+    *entry_bytes = res->entry_bytes;
+    if (!res->have_members) return fail(res->ctx, HH_EINVAL, "membership was not kept");
+    *entries = res->members;
+    *n = res->info.member_slots;
     return HH_OK;
 }
 

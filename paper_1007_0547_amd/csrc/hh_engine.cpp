@@ -1,11 +1,15 @@
 // Level-synchronous driver of the hierarchical Hough vote on one gfx950.
 //
 // One call runs every enabled pass of one image as a separate quadtree; the
-// trees share every launch.  Per level l (0 .. depth-1): a fill kernel
-// clears the level's look-back words, k_vote counts and compacts the child
-// voter lists, k_decide applies the threshold and writes the level-(l+1)
-// region table (or the detected cells at the finest level), and the host
-// reads the level's totals to size level l+1.
+// trees share every launch.  The host enqueues the whole call without
+// waiting: edge staging, the root setup, then per level l (0 .. depth-1) the
+// vote/compaction launch, the one-workgroup scan of its decision totals and
+// the launch that writes the next level's regions (or the detected cells).
+// Level sizes stay on the device (LevelInfo records in the call's arena);
+// the host waits once, at the end, and reads the level records, the tree
+// records (the per-pass statistics follow from them) and the error word.  If
+// a level did not fit the arena the call is run again with a larger arena
+// (sizes learnt this way are kept for the next calls on the context).
 #include "hh_engine.hpp"
 
 #include <algorithm>
@@ -112,11 +116,6 @@ void DevBuf::reset()
 
 namespace {
 
-constexpr size_t kErrorOff = 64;     // uint32 error word in d_small
-constexpr size_t kTotalsOff = 128;   // LevelTotals in d_small
-constexpr size_t kScalarOff = 192;   // int64 scratch in d_small
-constexpr size_t kSmallBytes = 256;
-
 void check(hipError_t e, const char* what)
 {
     if (e != hipSuccess) {
@@ -125,21 +124,12 @@ void check(hipError_t e, const char* what)
     }
 }
 
-uint32_t* d_error(hh_ctx* c) { return reinterpret_cast<uint32_t*>(c->d_small.as<char>() + kErrorOff); }
-LevelTotals* d_totals(hh_ctx* c)
-{
-    return reinterpret_cast<LevelTotals*>(c->d_small.as<char>() + kTotalsOff);
-}
-int64_t* d_scalar(hh_ctx* c) { return reinterpret_cast<int64_t*>(c->d_small.as<char>() + kScalarOff); }
-
 int ceil_log2(int64_t n)
 {
     int d = 0;
     while (((int64_t)1 << d) < n) ++d;
     return d;
 }
-
-int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 void sync(hh_ctx* c) { check(hipStreamSynchronize(c->stream), "hipStreamSynchronize"); }
 
@@ -155,11 +145,47 @@ double elapsed(hh_ctx* c, int a, int b)
     return ms;
 }
 
-void fetch_totals(hh_ctx* c)
+// Fixed part of an arena: level records, tree records, error word, scratch,
+// then the cells.  Everything before the cells is copied back in one piece.
+struct FixedLayout {
+    int64_t info, rec, error, scalar, head_bytes, cells, bytes;
+};
+
+FixedLayout fixed_layout(int32_t n_trees, int64_t cells_cap)
 {
-    check(hipMemcpyAsync(c->h_totals, d_totals(c), sizeof(LevelTotals), hipMemcpyDeviceToHost, c->stream),
-          "copy level totals");
-    sync(c);
+    FixedLayout f{};
+    int64_t off = 0;
+    f.info = off;
+    off += align256((int64_t)(kMaxLevels + 1) * (int64_t)sizeof(LevelInfo));
+    f.rec = off;
+    off += align256((int64_t)n_trees * kMaxLevels * kRecCh * 8);
+    f.error = off;
+    off += 256;
+    f.scalar = off;
+    off += 256;
+    f.head_bytes = off;
+    f.cells = off;
+    off += align256(cells_cap * (int64_t)sizeof(Cell));
+    f.bytes = off;
+    return f;
+}
+
+Arena carve(char* base, const FixedLayout& f, int32_t n_trees, int64_t cells_cap, int64_t half_cap,
+            int32_t entry_bytes)
+{
+    Arena a{};
+    a.info = reinterpret_cast<LevelInfo*>(base + f.info);
+    a.rec = reinterpret_cast<int64_t*>(base + f.rec);
+    a.error = reinterpret_cast<uint32_t*>(base + f.error);
+    a.scalar = reinterpret_cast<int64_t*>(base + f.scalar);
+    a.cells = reinterpret_cast<Cell*>(base + f.cells);
+    a.cells_cap = cells_cap;
+    a.half[0] = base + f.bytes;
+    a.half[1] = a.half[0] + half_cap;
+    a.half_cap = half_cap;
+    a.n_trees = n_trees;
+    a.entry_bytes = entry_bytes;
+    return a;
 }
 
 }  // namespace
@@ -184,21 +210,15 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
             throw Error{HH_EDEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950"};
         ctx->cu_count = prop.multiProcessorCount;
-        check(hipHostMalloc((void**)&ctx->h_totals, sizeof(LevelTotals), hipHostMallocDefault),
-              "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_trees, 2 * sizeof(TreeDesc), hipHostMallocDefault),
-              "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_scalar, 64 * sizeof(int64_t), hipHostMallocDefault),
-              "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_error, sizeof(uint32_t), hipHostMallocDefault),
+        ctx->grid = std::max(1, ctx->cu_count) * 8;
+        const FixedLayout f = fixed_layout(kMaxTrees, 0);
+        check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
+        check(hipHostMalloc((void**)&ctx->h_trees, kMaxTrees * sizeof(TreeDesc), hipHostMallocDefault),
               "hipHostMalloc");
         if (cfg->flags & HH_FLAG_TIMING) {
-            ctx->events.resize(3 + 3 * kMaxLevels, nullptr);
+            ctx->events.resize(3 + 4 * kMaxLevels, nullptr);
             for (auto& e : ctx->events) check(hipEventCreate(&e), "hipEventCreate");
         }
-        ctx->d_small = DevBuf(&ctx->pool, kSmallBytes);
-        check(launch_fill_u64(ctx->d_small.as<uint64_t>(), kSmallBytes / 8, 0, ctx->stream), "fill");
-        sync(ctx.get());
     } catch (const Error& e) {
         engine_destroy(ctx.release());
         return e.status;
@@ -216,11 +236,8 @@ void engine_destroy(hh_ctx* ctx)
     ctx->events.clear();
     for (hh_result* r : ctx->live_results) delete r;
     ctx->live_results.clear();
-    ctx->d_small.reset();
-    if (ctx->h_totals) (void)hipHostFree(ctx->h_totals);
+    if (ctx->h_fixed) (void)hipHostFree(ctx->h_fixed);
     if (ctx->h_trees) (void)hipHostFree(ctx->h_trees);
-    if (ctx->h_scalar) (void)hipHostFree(ctx->h_scalar);
-    if (ctx->h_error) (void)hipHostFree(ctx->h_error);
     delete ctx;
 }
 
@@ -265,6 +282,34 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
     return p;
 }
 
+// After an arena overflow: estimate the sizes the call needs from the level
+// records it left (levels before the failure are complete) and grow the
+// context's sizes.  A full tree doubles its list length per level.
+void grow_sizes(hh_ctx* ctx, const LevelInfo* info, int32_t n_trees, int32_t dmax, int32_t entry_bytes)
+{
+    int64_t need_half = 0, need_cells = 0;
+    int last = -1;
+    for (int l = 0; l <= dmax && l < kMaxLevels; ++l) {
+        if (info[l].P <= 0) break;
+        last = l;
+        const int64_t Pp = l ? info[l - 1].P : 0, Lp = l ? info[l - 1].L : 0;
+        const LevelLayout y = level_layout(nullptr, l, Pp, Lp, info[l].P, info[l].L, n_trees, entry_bytes);
+        const LevelLayout nx = level_layout(nullptr, l + 1, info[l].P, info[l].L, 0, 0, n_trees, entry_bytes);
+        need_half = std::max({need_half, y.end, nx.end});
+        if (l + 1 == dmax) need_cells = std::max(need_cells, 4 * info[l].P);
+    }
+    const int64_t growth = last >= 0 ? ((int64_t)1 << std::max(0, dmax - 1 - last)) : 4;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        total_b = (size_t)1 << 40;
+    }
+    const int64_t half_limit = (int64_t)((double)total_b * 0.4);
+    const int64_t want = need_half * growth + need_half / 4;
+    ctx->half_cap = std::min(std::max(ctx->half_cap * 2, want), std::max(half_limit, ctx->half_cap));
+    ctx->cells_cap = std::max(ctx->cells_cap * 2, need_cells + need_cells / 4);
+}
+
 }  // namespace
 
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
@@ -276,92 +321,69 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     DevicePool* pool = &ctx->pool;
     check(hipSetDevice(ctx->device), "hipSetDevice");
     const Plan plan = make_plan(ctx, in);
-
-    // clear tickets, error word and totals
-    check(launch_fill_u64(ctx->d_small.as<uint64_t>(), kSmallBytes / 8, 0, st), "fill");
     const bool timing = !ctx->events.empty();
-    hh_timing& tm = res->timing;
-    mark(ctx, 0);
 
-    // ---- edge staging
-    DevBuf xb, yb, imgb, sync0;
+    // ---- validate the input form; bring host data to the device
+    DevBuf hx, hy, himg, tcount, tpre;
     const int32_t* dx = nullptr;
     const int32_t* dy = nullptr;
-    int64_t E = 0;
+    const uint8_t* dimg = nullptr;
+    int64_t dstride = 0, n_pix = 0, E_host = -1;
+    int32_t entry_bytes = 4;
     if (in->kind == 0) {
         if (in->n_points < 0 || in->n_points > INT32_MAX) throw Error{HH_EINVAL, "bad n_points"};
-        E = in->n_points;
-        if (E > 0 && (!in->x || !in->y)) throw Error{HH_EINVAL, "x and y must not be NULL"};
+        E_host = in->n_points;
+        entry_bytes = 8;   // point lists keep their own ids (duplicates and any order allowed)
+        if (E_host > 0 && (!in->x || !in->y)) throw Error{HH_EINVAL, "x and y must not be NULL"};
         if (in->on_device) {
             dx = in->x;
             dy = in->y;
-            check(launch_validate(dx, dy, E, plan.W, plan.H, d_error(ctx), st), "validate");
         } else {
-            for (int64_t k = 0; k < E; ++k)
+            for (int64_t k = 0; k < E_host; ++k)
                 if (in->x[k] < 0 || in->x[k] >= plan.W || in->y[k] < 0 || in->y[k] >= plan.H)
                     throw Error{HH_EINVAL, "point " + std::to_string(k) + " outside the image"};
-            xb = DevBuf(pool, (size_t)std::max<int64_t>(E, 1) * 4);
-            yb = DevBuf(pool, (size_t)std::max<int64_t>(E, 1) * 4);
-            if (E > 0) {
-                check(hipMemcpyAsync(xb.get(), in->x, (size_t)E * 4, hipMemcpyHostToDevice, st), "copy x");
-                check(hipMemcpyAsync(yb.get(), in->y, (size_t)E * 4, hipMemcpyHostToDevice, st), "copy y");
+            hx = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
+            hy = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
+            if (E_host > 0) {
+                check(hipMemcpyAsync(hx.get(), in->x, (size_t)E_host * 4, hipMemcpyHostToDevice, st), "copy x");
+                check(hipMemcpyAsync(hy.get(), in->y, (size_t)E_host * 4, hipMemcpyHostToDevice, st), "copy y");
             }
-            dx = xb.as<int32_t>();
-            dy = yb.as<int32_t>();
+            dx = hx.as<int32_t>();
+            dy = hy.as<int32_t>();
         }
+        res->points = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
     } else if (in->kind == 1) {
         if (!in->image) throw Error{HH_EINVAL, "image must not be NULL"};
         const int64_t stride = in->row_stride ? in->row_stride : plan.W;
         if (stride < plan.W) throw Error{HH_EINVAL, "row_stride < width"};
-        const int64_t n_pix = (int64_t)plan.W * plan.H;
-        const uint8_t* img = in->image;
-        int64_t dstride = stride;
+        n_pix = (int64_t)plan.W * plan.H;
+        dimg = in->image;
+        dstride = stride;
         if (!in->on_device) {
-            imgb = DevBuf(pool, (size_t)n_pix);
-            check(hipMemcpy2DAsync(imgb.get(), (size_t)plan.W, in->image, (size_t)stride, (size_t)plan.W,
+            himg = DevBuf(pool, (size_t)n_pix);
+            check(hipMemcpy2DAsync(himg.get(), (size_t)plan.W, in->image, (size_t)stride, (size_t)plan.W,
                                    (size_t)plan.H, hipMemcpyHostToDevice, st),
                   "copy image");
-            img = imgb.as<uint8_t>();
+            dimg = himg.as<uint8_t>();
             dstride = plan.W;
         }
-        xb = DevBuf(pool, (size_t)n_pix * 4);
-        yb = DevBuf(pool, (size_t)n_pix * 4);
-        const int32_t n_tiles = (int32_t)cdiv(n_pix, kPixTile);
-        sync0 = DevBuf(pool, (size_t)(n_tiles + 1) * 8);
-        check(launch_fill_u64(sync0.as<uint64_t>(), n_tiles + 1, 0, st), "fill");
-        ExtractArgs ea{};
-        ea.image = img;
-        ea.row_stride = dstride;
-        ea.width = plan.W;
-        ea.height = plan.H;
-        ea.n_pix = n_pix;
-        ea.x = xb.as<int32_t>();
-        ea.y = yb.as<int32_t>();
-        ea.status = sync0.as<uint64_t>();
-        ea.ticket = reinterpret_cast<uint32_t*>(sync0.as<uint64_t>() + n_tiles);
-        ea.n_tiles = n_tiles;
-        ea.total = d_scalar(ctx);
-        ea.error = d_error(ctx);
-        check(launch_extract(ea, st), "extract");
-        mark(ctx, 1);
-        check(hipMemcpyAsync(ctx->h_scalar, d_scalar(ctx), 8, hipMemcpyDeviceToHost, st), "copy E");
-        sync(ctx);
-        E = ctx->h_scalar[0];
-        if (E > INT32_MAX) throw Error{HH_ECAPACITY, "more than 2^31-1 edge points"};
-        dx = xb.as<int32_t>();
-        dy = yb.as<int32_t>();
+        res->points = DevBuf(pool, (size_t)n_pix * 4);
+        const int64_t nt = cdiv(n_pix, kPixTile);
+        tcount = DevBuf(pool, (size_t)nt * 4);
+        tpre = DevBuf(pool, (size_t)nt * 8);
     } else {
         throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
     }
+    res->entry_bytes = entry_bytes;
+    uint32_t* xy = res->points.as<uint32_t>();
 
     // ---- trees (one per enabled pass)
     int32_t n_trees = 0;
     for (int p = 0; p < 2; ++p) {
         if (!(plan.passes & (1u << p))) continue;
         TreeDesc& t = ctx->h_trees[n_trees];
-        t.u = p == 0 ? dx : dy;   // pass 1 reads (x0, y0) as (y0, x0)
-        t.v = p == 0 ? dy : dx;
-        t.n_points = E;
+        t.xy_base = 0;
+        t.n_points = E_host;   // image inputs: set on the device once the edges are counted
         t.s_log2 = plan.s_log2;
         t.dmax = plan.dmax;
         t.threshold = plan.T;
@@ -372,162 +394,138 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
         ++n_trees;
     }
     res->n_trees = n_trees;
-    DevBuf d_trees(pool, sizeof(TreeDesc) * 2);
+    DevBuf d_trees(pool, sizeof(TreeDesc) * kMaxTrees);
     check(hipMemcpyAsync(d_trees.get(), ctx->h_trees, sizeof(TreeDesc) * n_trees, hipMemcpyHostToDevice, st),
           "copy trees");
-    const int64_t n_stats = (int64_t)n_trees * kMaxLevels * kNumStats;
-    DevBuf d_stats(pool, (size_t)n_stats * 8);
-    check(launch_fill_u64(d_stats.as<uint64_t>(), n_stats, 0, st), "fill");
+    const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
 
-    const bool root_votes = E > plan.T;   // every line crosses the root (code 0011)
-    int64_t n_cells_total = 0;
-    DevBuf cells, members, iota;
+    // ---- the call, repeated with a larger arena if a level overflowed
+    DevBuf arena;
+    Arena ar{};
+    FixedLayout fl{};
+    uint32_t err = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (attempt >= 8) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
+        fl = fixed_layout(n_trees, ctx->cells_cap);
+        const int64_t bytes = fl.bytes + 2 * ctx->half_cap;
+        arena.reset();
+        arena = DevBuf(pool, (size_t)bytes);
+        ar = carve(arena.as<char>(), fl, n_trees, ctx->cells_cap, ctx->half_cap, entry_bytes);
+        res->timing = hh_timing{};
+        hh_timing& tm = res->timing;
 
-    if (root_votes && plan.dmax > 0) {
-        // ---- level loop
-        int64_t P = n_trees;
-        int64_t L = (int64_t)n_trees * E;
-        DevBuf regions(pool, sizeof(Region) * (size_t)P);
-        int32_t n_tiles = (int32_t)cdiv(L, kTile);
-        DevBuf tile_first(pool, (size_t)n_tiles * 4);
-        iota = DevBuf(pool, (size_t)E * 4);
-        check(launch_init_level0(regions.as<Region>(), tile_first.as<int32_t>(), iota.as<int32_t>(), n_trees, E,
-                                 n_tiles, st),
-              "init level 0");
-        DevBuf list;   // level list buffer (level 0 uses iota)
-        const int32_t* list_ptr = iota.as<int32_t>();
+        mark(ctx, 0);
+        check(launch_clear(ar, n_rec, st), "clear");
+        if (in->kind == 0) {
+            check(launch_pack_points(dx, dy, E_host, plan.W, plan.H, xy, ar.error, st), "pack");
+        } else {
+            ExtractArgs ea{};
+            ea.image = dimg;
+            ea.row_stride = dstride;
+            ea.width = plan.W;
+            ea.height = plan.H;
+            ea.n_pix = n_pix;
+            ea.xy = xy;
+            ea.tile_count = tcount.as<int32_t>();
+            ea.tile_pre = tpre.as<int64_t>();
+            ea.n_tiles = (int32_t)cdiv(n_pix, kPixTile);
+            ea.total = ar.scalar;
+            check(launch_extract(ea, st), "extract");
+        }
+        mark(ctx, 1);
+        const int64_t work_bound = std::max<int64_t>(in->kind == 1 ? n_pix : E_host, 1);
+        check(launch_begin(ar, d_trees.as<TreeDesc>(), n_trees, E_host, plan.T, plan.dmax, 2 * work_bound, st),
+              "begin");
+        LevelArgs la{};
+        la.ar = ar;
+        la.trees = d_trees.as<TreeDesc>();
+        la.xy = xy;
+        la.keep_members = plan.membership ? 1 : 0;
         for (int l = 0; l < plan.dmax; ++l) {
-            const bool last = (l + 1 == plan.dmax);
-            n_tiles = (int32_t)cdiv(L, kTile);
-            const int32_t n_ptiles = (int32_t)cdiv(P, kBlock);
-            const bool write_out = !last || plan.membership;
-            DevBuf outb;
-            if (write_out) outb = DevBuf(pool, (size_t)L * 4 * 4);
-            DevBuf pstart(pool, (size_t)P * 4 * 8);
-            const int64_t n_sync = (int64_t)n_tiles * 4 + (int64_t)n_ptiles * 3 + 2;
-            DevBuf syncb(pool, (size_t)n_sync * 8);
-            uint64_t* sw = syncb.as<uint64_t>();
-            check(launch_fill_u64(sw, n_sync, 0, st), "fill");
-            DevBuf next_regions, next_tile_first, cellb;
-            int64_t next_tile_cap = 0;
-            if (!last) {
-                next_regions = DevBuf(pool, sizeof(Region) * (size_t)(4 * P));
-                next_tile_cap = cdiv(4 * L, kTile) + 1;
-                next_tile_first = DevBuf(pool, (size_t)next_tile_cap * 4);
-            } else {
-                cellb = DevBuf(pool, sizeof(Cell) * (size_t)(4 * P));
+            la.level = l;
+            la.write_out = (l + 1 < plan.dmax || plan.membership) ? 1 : 0;
+            mark(ctx, 3 + 4 * l);
+            check(launch_vote(la, plan.variant, plan.wide, ctx->grid, st), "vote");
+            mark(ctx, 4 + 4 * l);
+            check(launch_scan(la, st), "scan");
+            mark(ctx, 5 + 4 * l);
+            check(launch_emit(la, ctx->grid, st), "emit");
+            mark(ctx, 6 + 4 * l);
+        }
+        mark(ctx, 2);
+        check(hipMemcpyAsync(ctx->h_fixed, arena.get(), (size_t)fl.head_bytes, hipMemcpyDeviceToHost, st),
+              "copy level records");
+        sync(ctx);
+        err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + fl.error);
+        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
+        if (timing) {
+            tm.total_ms = elapsed(ctx, 0, 2);
+            tm.extract_ms = elapsed(ctx, 0, 1);
+            for (int l = 0; l < plan.dmax; ++l) {
+                tm.vote_ms += elapsed(ctx, 3 + 4 * l, 4 + 4 * l);
+                tm.decide_ms += elapsed(ctx, 4 + 4 * l, 6 + 4 * l);
             }
+            tm.vote_launches = plan.dmax;
+            tm.decide_launches = 2 * plan.dmax;
+        }
+        for (int l = 0; l < plan.dmax; ++l) {
+            tm.vote_entries += info[l].L;
+            if (l + 1 < plan.dmax || plan.membership) tm.vote_written += info[l].votes;
+        }
+        if ((err & kErrArena) && !(err & (kErrPointRange | kErrInternal | kErrLookback))) {
+            grow_sizes(ctx, info, n_trees, plan.dmax, entry_bytes);
+            continue;
+        }
+        break;
+    }
+    if (err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
+    if (err & kErrLookback) throw Error{HH_EINTERNAL, "a bounded wait timed out"};
+    if (err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
 
-            VoteArgs va{};
-            va.regions = regions.as<Region>();
-            va.n_regions = (int32_t)P;
-            va.tile_first = tile_first.as<int32_t>();
-            va.n_tiles = n_tiles;
-            va.list = list_ptr;
-            va.trees = d_trees.as<TreeDesc>();
-            va.n_entries = L;
-            va.level = l;
-            va.write_out = write_out ? 1 : 0;
-            va.out = write_out ? outb.as<int32_t>() : nullptr;
-            va.out_cap = L;
-            va.pstart = pstart.as<int64_t>();
-            va.status = sw;
-            va.ticket = reinterpret_cast<uint32_t*>(sw + (int64_t)n_tiles * 4 + (int64_t)n_ptiles * 3);
-            va.totals = d_totals(ctx);
-            va.error = d_error(ctx);
-            mark(ctx, 3 + 3 * l);
-            check(launch_vote(va, plan.variant, plan.wide, st), "vote");
-            mark(ctx, 4 + 3 * l);
+    const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
+    const int64_t* rec = reinterpret_cast<const int64_t*>(ctx->h_fixed + fl.rec);
+    const int64_t E = *reinterpret_cast<const int64_t*>(ctx->h_fixed + fl.scalar);
+    const bool root_votes = E > plan.T;   // every line crosses the root (code 0011)
 
-            DecideArgs da{};
-            da.regions = regions.as<Region>();
-            da.n_regions = (int32_t)P;
-            da.trees = d_trees.as<TreeDesc>();
-            da.level = l;
-            da.pstart = pstart.as<int64_t>();
-            da.out_cap = L;
-            da.status = sw + (int64_t)n_tiles * 4;
-            da.ticket = va.ticket + 2;   // next uint64 word
-            da.n_tiles = n_ptiles;
-            da.totals = d_totals(ctx);
-            da.next_regions = last ? nullptr : next_regions.as<Region>();
-            da.next_tile_first = last ? nullptr : next_tile_first.as<int32_t>();
-            da.next_tile_cap = next_tile_cap;
-            da.cells = last ? cellb.as<Cell>() : nullptr;
-            da.stats = d_stats.as<int64_t>();
-            da.keep_members = plan.membership ? 1 : 0;
-            da.error = d_error(ctx);
-            check(launch_decide(da, st), "decide");
-            mark(ctx, 5 + 3 * l);
-            fetch_totals(ctx);
-            const LevelTotals tot = *ctx->h_totals;
-            if (timing) {
-                tm.vote_ms += elapsed(ctx, 3 + 3 * l, 4 + 3 * l);
-                tm.decide_ms += elapsed(ctx, 4 + 3 * l, 5 + 3 * l);
-                tm.vote_launches += 1;
-                tm.decide_launches += 1;
-            }
-            tm.vote_entries += L;
-            if (write_out) tm.vote_written += tot.votes[0] + tot.votes[1] + tot.votes[2] + tot.votes[3];
-
-            if (last) {
-                n_cells_total = tot.n_cells;
-                cells = std::move(cellb);
-                if (write_out) members = std::move(outb);
-                res->info.member_slots = write_out ? 4 * L : 0;
-                break;
-            }
-            // advance to level l+1
-            list = std::move(outb);
-            list_ptr = list.as<int32_t>();
-            if (l == 0) iota.reset();
-            regions = std::move(next_regions);
-            tile_first = std::move(next_tile_first);
-            P = tot.n_next;
-            L = tot.len_next;
-            if (P == 0) break;
+    int64_t n_cells_total = 0;
+    if (plan.dmax > 0) {
+        const int D = plan.dmax;
+        n_cells_total = info[D].cells_base + info[D].cells;
+        res->cells = ar.cells;
+        if (plan.membership && info[D - 1].P > 0) {
+            const int64_t Pp = D >= 2 ? info[D - 2].P : 0, Lp = D >= 2 ? info[D - 2].L : 0;
+            const LevelLayout y = level_layout(ar.half[(D - 1) & 1], D - 1, Pp, Lp, info[D - 1].P,
+                                               info[D - 1].L, n_trees, entry_bytes);
+            res->members = y.out;
+            res->info.member_slots = 4 * info[D - 1].L;
         }
     } else if (root_votes) {
         // depth 0: the root is the finest region, every line votes for it
-        iota = DevBuf(pool, (size_t)E * 4);
-        DevBuf dummy_regions(pool, sizeof(Region) * 2);
-        DevBuf dummy_tiles(pool, 4 * 2);
-        check(launch_init_level0(dummy_regions.as<Region>(), dummy_tiles.as<int32_t>(), iota.as<int32_t>(),
-                                 n_trees, E, 1, st),
-              "init level 0");
-        std::vector<Cell> hc(n_trees);
+        res->extra = DevBuf(pool, 256 + (size_t)E * (size_t)entry_bytes);
+        Cell* dcells = res->extra.as<Cell>();
+        std::vector<Cell> hc((size_t)n_trees);
         for (int t = 0; t < n_trees; ++t) {
-            hc[t].i = 0;
-            hc[t].j = 0;
-            hc[t].votes = (int32_t)E;
-            hc[t].pass = res->tree_pass[t];
-            hc[t].key = 0;
-            hc[t].member_off = plan.membership ? 0 : -1;
+            hc[(size_t)t].i = 0;
+            hc[(size_t)t].j = 0;
+            hc[(size_t)t].votes = (int32_t)E;
+            hc[(size_t)t].pass = res->tree_pass[t];
+            hc[(size_t)t].key = 0;
+            hc[(size_t)t].member_off = plan.membership ? 0 : -1;
         }
-        cells = DevBuf(pool, sizeof(Cell) * n_trees);
-        check(hipMemcpyAsync(cells.get(), hc.data(), sizeof(Cell) * n_trees, hipMemcpyHostToDevice, st),
-              "copy cells");
+        check(hipMemcpyAsync(dcells, hc.data(), sizeof(Cell) * n_trees, hipMemcpyHostToDevice, st), "copy cells");
         n_cells_total = n_trees;
+        res->cells = dcells;
+        res->depth0 = true;
         if (plan.membership) {
-            members = std::move(iota);
+            // the root's voters are all points: ids 0..E-1
+            res->entry_bytes = 4;
+            res->dev_ids = DevBuf(pool, (size_t)std::max<int64_t>(E, 1) * 4);
+            check(launch_iota(res->dev_ids.as<int32_t>(), E, st), "iota");
+            res->members = xy;
             res->info.member_slots = E;
         }
         sync(ctx);
     }
-
-    // ---- statistics and error word
-    mark(ctx, 2);
-    std::vector<int64_t> hs((size_t)n_stats);
-    check(hipMemcpyAsync(hs.data(), d_stats.get(), (size_t)n_stats * 8, hipMemcpyDeviceToHost, st), "copy stats");
-    check(hipMemcpyAsync(ctx->h_error, d_error(ctx), 4, hipMemcpyDeviceToHost, st), "copy error");
-    sync(ctx);
-    if (timing) {
-        tm.total_ms = elapsed(ctx, 0, 2);
-        if (in->kind == 1) tm.extract_ms = elapsed(ctx, 0, 1);
-    }
-    if (*ctx->h_error & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
-    if (*ctx->h_error & kErrLookback) throw Error{HH_EINTERNAL, "look-back wait timed out"};
-    if (*ctx->h_error & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
 
     res->info.n_points = E;
     res->info.width = plan.W;
@@ -537,6 +535,9 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     res->info.threshold = plan.T;
     res->info.passes = plan.passes;
     res->info.compare_bits = (plan.variant == HH_VARIANT_CIRCLE || plan.wide) ? 64 : 32;
+
+    // per-pass statistics: level 0 is the root; level l+1 sums the parents of
+    // the tree at level l, delimited by the tree records
     int64_t code_tests = 0;
     for (int t = 0; t < n_trees; ++t) {
         const int p = res->tree_pass[t];
@@ -550,27 +551,51 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
             v[0].entries = E;
         }
         if (root_votes && plan.dmax == 0) v[0].detected = 1;
-        for (int l = 1; l <= plan.dmax; ++l) {
-            const int64_t* s = &hs[((size_t)t * kMaxLevels + l) * kNumStats];
-            v[l].evaluated = s[0];
-            v[l].votes = s[1];
-            v[l].split = s[2];
-            v[l].detected = s[3];
-            v[l].code_tests = s[4];
-            v[l].entries = s[5];
+        for (int l = 0; l < plan.dmax; ++l) {
+            const int64_t* r = rec + ((int64_t)t * kMaxLevels + l) * kRecCh;
+            if (r[0] < 0) continue;   // the tree had no parent at level l
+            int64_t nx[kRecCh] = {info[l].P, info[l].L, info[l + 1].P, info[l + 1].L, info[l + 1].cells,
+                                  info[l].votes};
+            for (int t2 = t + 1; t2 < n_trees; ++t2) {
+                const int64_t* r2 = rec + ((int64_t)t2 * kMaxLevels + l) * kRecCh;
+                if (r2[0] >= 0) {
+                    for (int c = 0; c < kRecCh; ++c) nx[c] = r2[c];
+                    break;
+                }
+            }
+            hh_level_stats& s = v[(size_t)l + 1];
+            s.evaluated = 4 * (nx[0] - r[0]);
+            s.code_tests = 4 * (nx[1] - r[1]);
+            s.split = nx[2] - r[2];
+            s.entries = nx[3] - r[3];
+            s.detected = nx[4] - r[4];
+            s.votes = nx[5] - r[5];
         }
         for (const auto& lv : v) code_tests += lv.code_tests;
-        res->info.n_cells[p] = v[plan.dmax].detected;
+        res->info.n_cells[p] = v[(size_t)plan.dmax].detected;
     }
     res->info.code_tests = code_tests;
     res->n_cells_total = n_cells_total;
     if (res->info.n_cells[0] + res->info.n_cells[1] != n_cells_total)
         throw Error{HH_EINTERNAL, "cell count does not match the statistics"};
-    res->cells = std::move(cells);
-    res->members = std::move(members);
+    res->arena = std::move(arena);
     res->have_members = plan.membership;
     ctx->live_results.insert(res.get());
     *out = res.release();
+    return HH_OK;
+}
+
+hh_status engine_device_ids(hh_result* res)
+{
+    if (res->dev_ids || !res->have_members) return HH_OK;
+    hh_ctx* ctx = res->ctx;
+    check(hipSetDevice(ctx->device), "hipSetDevice");
+    const int64_t slots = std::max<int64_t>(res->info.member_slots, 1);
+    res->dev_ids = DevBuf(&ctx->pool, (size_t)slots * 4);
+    check(launch_member_ids(res->cells, res->n_cells_total, nullptr, res->members, res->entry_bytes,
+                            res->points.as<uint32_t>(), res->info.n_points, res->dev_ids.as<int32_t>(), ctx->stream),
+          "member ids");
+    sync(ctx);
     return HH_OK;
 }
 
@@ -583,8 +608,8 @@ hh_status engine_host_copy(hh_result* res)
     const int64_t n = res->n_cells_total;
     res->host_cells.resize((size_t)n);
     if (n > 0)
-        check(hipMemcpyAsync(res->host_cells.data(), res->cells.get(), (size_t)n * sizeof(hh_cell),
-                             hipMemcpyDeviceToHost, st),
+        check(hipMemcpyAsync(res->host_cells.data(), res->cells, (size_t)n * sizeof(hh_cell), hipMemcpyDeviceToHost,
+                             st),
               "copy cells");
     sync(ctx);
     std::vector<int64_t> off((size_t)n);
@@ -596,14 +621,21 @@ hh_status engine_host_copy(hh_result* res)
     if (res->have_members && n > 0) {
         DevBuf d_off(&ctx->pool, (size_t)n * 8);
         DevBuf d_dst(&ctx->pool, (size_t)std::max<int64_t>(total, 1) * 4);
-        check(hipMemcpyAsync(d_off.get(), off.data(), (size_t)n * 8, hipMemcpyHostToDevice, st), "copy offsets");
-        check(launch_gather_members(res->cells.as<Cell>(), n, d_off.as<int64_t>(), res->members.as<int32_t>(),
-                                    d_dst.as<int32_t>(), st),
-              "gather members");
         res->host_members.resize((size_t)total);
-        check(hipMemcpyAsync(res->host_members.data(), d_dst.get(), (size_t)total * 4, hipMemcpyDeviceToHost, st),
-              "copy members");
-        sync(ctx);
+        if (res->depth0) {   // every point votes for the root: ids 0 .. E-1 per cell
+            for (int64_t c = 0; c < n; ++c)
+                for (int32_t k = 0; k < res->host_cells[(size_t)c].votes; ++k)
+                    res->host_members[(size_t)(off[(size_t)c] + k)] = k;
+        } else {
+            check(hipMemcpyAsync(d_off.get(), off.data(), (size_t)n * 8, hipMemcpyHostToDevice, st), "copy offsets");
+            check(launch_member_ids(res->cells, n, d_off.as<int64_t>(), res->members, res->entry_bytes,
+                                    res->points.as<uint32_t>(), res->info.n_points, d_dst.as<int32_t>(), st),
+                  "member ids");
+            check(hipMemcpyAsync(res->host_members.data(), d_dst.get(), (size_t)total * 4, hipMemcpyDeviceToHost,
+                                 st),
+                  "copy members");
+            sync(ctx);
+        }
     }
     for (int64_t c = 0; c < n; ++c)
         res->host_cells[(size_t)c].member_off = res->have_members ? off[(size_t)c] : -1;

@@ -16,6 +16,8 @@
 
 namespace hh {
 
+constexpr int kMaxTrees = 2;
+
 // Caching allocator over hipMalloc.  Sizes are rounded up to one of eight
 // steps per power of two; freed blocks wait in per-size free lists and are
 // handed out again without a hipMalloc.  All users of one pool work on one
@@ -71,11 +73,16 @@ struct hh_result {
     int32_t n_trees = 0;
     int32_t tree_pass[2] = {-1, -1};
     std::vector<hh_level_stats> stats[2];
-    hh::DevBuf cells;          // all cells, (pass, key) order
+    hh::DevBuf arena;          // device memory of the call: cells and voter lists live here
+    hh::DevBuf points;         // packed edge points (row-major for image inputs)
+    hh::DevBuf extra;          // depth-0 results
+    hh::DevBuf dev_ids;        // point ids in the layout of `members` (made on request)
+    const hh::Cell* cells = nullptr;     // all cells, (pass, key) order
     int64_t n_cells_total = 0;
-    hh::DevBuf members;        // device voter lists referenced by cells
-    hh::DevBuf members_owner2; // second buffer kept alive when cells reference it
+    const void* members = nullptr;       // voter entries referenced by cells
+    int32_t entry_bytes = 4;             // 4: packed point; 8: id << 32 | packed point
     bool have_members = false;
+    bool depth0 = false;                 // the root is the only level: every point votes
     hh_timing timing{};
     // lazily filled host copies
     bool host_ready = false;
@@ -90,13 +97,13 @@ struct hh_ctx {
     std::string last_error;
     hh::DevicePool pool;
     int cu_count = 0;
-    // pinned host staging
-    hh::LevelTotals* h_totals = nullptr;
+    // pinned host copy of an arena's fixed part (level records, tree records, error)
+    char* h_fixed = nullptr;
     hh::TreeDesc* h_trees = nullptr;
-    int64_t* h_scalar = nullptr;
-    uint32_t* h_error = nullptr;
-    // small device scratch: tickets, error word, totals, scalar
-    hh::DevBuf d_small;
+    // arena sizes that worked before (grown when a call overflows)
+    int64_t half_cap = 64ll << 20;
+    int64_t cells_cap = 1ll << 20;
+    int32_t grid = 0;          // workgroups of the level kernels (fixed grid, tiles strided)
     // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
     // then three per level (vote start, vote end = decide start, decide end)
     std::vector<hipEvent_t> events;
@@ -110,5 +117,6 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out);
 void engine_destroy(hh_ctx* ctx);
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
 hh_status engine_host_copy(hh_result* res);
+hh_status engine_device_ids(hh_result* res);
 
 }  // namespace hh
