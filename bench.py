@@ -8,11 +8,12 @@ thick, 2% salt noise, seed 0, T = 120, depth 10, 4-bit corner code variant.
 
 Prints one JSON line.  ``value`` is line-region code tests per second
 (code tests = E + 4 * sum of the votes of the regions that split, summed
-over both passes), images per second is reported beside it.  ``roofline``
-prices the dominant kernel (the per-level vote/compaction launch) against
-MI355X HBM bandwidth: its algorithmic bytes per step divided by its summed
-launch duration, measured with HIP events on the library's stream during
-the timed steps.  ``cpu_baseline`` times the CPU oracle on the same image.
+over both passes), timed over the steps with no per-launch events; images
+per second is reported beside it.  ``roofline`` prices the dominant kernel
+against MI355X HBM bandwidth: its algorithmic bytes per step divided by its
+summed launch duration, measured with HIP events on the library's stream
+over a second set of steps run with per-level events.  ``cpu_baseline``
+times the CPU oracle on the same image.
 """
 from __future__ import annotations
 
@@ -28,15 +29,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def alg_bytes(stats_by_pass, detected_votes_by_pass, E):
-    """Algorithmic bytes of the vote/compaction launches of one detection.
-
-    Per pass: level 0 reads the coordinates of every line (8 B, the root
-    list is implicit); every deeper level reads a 4 B id plus 8 B of
-    coordinates per (parent, line) entry; every entry written to a kept
-    child's list costs 4 B.  With L_l the summed votes of the regions split
-    at level l and L_D the summed votes of the detected cells:
-        8 E + sum_{1<=l<D} 12 L_l + sum_{1<=l<=D} 4 L_l."""
+def survey_alg_bytes(stats_by_pass, detected_votes_by_pass, E):
+    """Algorithmic bytes of an id-list design that gathers coordinates: per
+    pass 8 E + sum_{1<=l<D} 12 L_l + sum_{1<=l<=D} 4 L_l, with L_l the summed
+    votes of the regions split at level l and L_D those of the detected
+    cells.  Reported for comparison only; this library's lists carry the
+    packed point, see ``kernel_bytes``."""
     total = 0
     for p, st in stats_by_pass.items():
         D = len(st) - 1
@@ -46,6 +44,15 @@ def alg_bytes(stats_by_pass, detected_votes_by_pass, E):
         total += 8 * E + sum(12 * L[l] for l in range(1, D)) + sum(4 * L[l] for l in range(1, D + 1))
     return total
 
+
+def kernel_bytes(timing, entry_bytes):
+    """Algorithmic bytes per step of the two list kernels.  k_count reads
+    every (parent, line) entry once; k_write reads it again and writes each
+    vote for a kept child (the next level's lists, the voters of detected
+    cells at the finest level).  Per-tile and per-region side arrays are
+    below 1% and not counted."""
+    n_in, n_out = timing["vote_entries"], timing["vote_written"]
+    return {"count": entry_bytes * n_in, "write": entry_bytes * (n_in + n_out)}
 
 def cpu_baseline(image, W, H, T, depth, budget_s=12.0):
     import oracle
@@ -106,46 +113,57 @@ def main():
     img = torch.from_numpy(w.image).to(dev)
     stream = torch.cuda.current_stream(dev)
 
-    ctx = HoughHier(threshold=w.threshold, max_depth=w.max_depth, variant=args.variant,
-                    membership=True, device=0, stream=stream, wide_compare=args.wide,
-                    timing=True)
+    def make(timing):
+        return HoughHier(threshold=w.threshold, max_depth=w.max_depth, variant=args.variant,
+                         membership=True, device=0, stream=stream, wide_compare=args.wide,
+                         timing=timing)
 
-    def step():
-        r = ctx.detect(image=img, width=w.width, height=w.height)
-        return r
+    ctx = make(False)
+
+    def step(c):
+        return c.detect(image=img, width=w.width, height=w.height)
 
     for _ in range(args.warmup):
-        step().free()
+        step(ctx).free()
     torch.cuda.synchronize(dev)
 
     lat = []
-    vote_ms = decide_ms = total_ms = 0.0
-    vote_launches = 0
     info = None
     t_start = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        r = step()
+        r = step(ctx)
         lat.append(time.perf_counter() - t0)
-        tm = r.timing()
-        vote_ms += tm["vote_ms"]
-        decide_ms += tm["decide_ms"]
-        total_ms += tm["total_ms"]
-        vote_launches += tm["vote_launches"]
         info = r.info
         r.free()
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t_start
 
-    # one more detection, outside the timed region, for the statistics
-    r = step()
+    # kernel durations: the same steps again with HIP events around the launches
+    ctx_t = make(True)
+    for _ in range(2):
+        step(ctx_t).free()
+    kt_steps = max(1, min(args.steps, 10))
+    acc = {}
+    for _ in range(kt_steps):
+        r = step(ctx_t)
+        for k, v in r.timing().items():
+            acc[k] = acc.get(k, 0) + v
+        r.free()
+    kt = {k: v / kt_steps for k, v in acc.items()}
+    r = step(ctx_t)
     stats = {p: r.stats(p) for p in (0, 1)}
     det_votes = {p: int(r.cells(p)["votes"].astype(np.int64).sum()) for p in (0, 1)}
+    entry_bytes = 4
     r.free()
+    ctx_t.close()
+
     E = int(info["n_points"])
     code_tests = int(info["code_tests"])
-    alg = alg_bytes(stats, det_votes, E)
-    achieved = alg / (vote_ms / args.steps / 1e3) / 1e9 if vote_ms > 0 else 0.0
+    kb = kernel_bytes(kt, entry_bytes)
+    kms = {"count": kt["count_ms"], "write": kt["write_ms"]}
+    dom = max(kms, key=kms.get)
+    achieved = kb[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
 
     ms_per_step = elapsed / args.steps * 1e3
     out = {
@@ -170,13 +188,17 @@ def main():
         "images_per_s": args.steps / elapsed,
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
-        "kernel_ms_per_step": {"vote": vote_ms / args.steps, "decide": decide_ms / args.steps,
-                               "device_total": total_ms / args.steps},
-        "roofline": {"bound": "hbm", "kernel": "k_vote", "achieved": achieved,
+        "kernel_ms_per_step": {"count": kt["count_ms"], "write": kt["write_ms"],
+                               "decide": kt["decide_ms"], "extract": kt["extract_ms"],
+                               "device_total_with_events": kt["total_ms"]},
+        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None,
-                     "alg_bytes_per_step": alg,
-                     "launches_per_step": vote_launches / args.steps},
+                     "alg_bytes_per_step": kb[dom],
+                     "other": {f"k_{k}": {"alg_bytes_per_step": kb[k], "ms_per_step": kms[k],
+                                          "GB/s": kb[k] / (kms[k] / 1e3) / 1e9 if kms[k] > 0 else 0.0}
+                               for k in kms},
+                     "id_list_design_alg_bytes_per_step": survey_alg_bytes(stats, det_votes, E)},
     }
     ctx.close()
     if not args.no_cpu_baseline:

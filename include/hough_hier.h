@@ -154,16 +154,19 @@ typedef struct {
 } hh_result_info;
 
 /* Kernel timings of one call (HH_FLAG_TIMING), from HIP events recorded on
- * the context's stream around each launch; zero without the flag. */
+ * the context's stream around the launches of each level; zero without the
+ * flag.  The events themselves add a few microseconds per level. */
 typedef struct {
-    int32_t vote_launches;    /* per-level vote/compaction kernel launches          */
-    int32_t decide_launches;  /* per-level split-decision kernel launches           */
-    double vote_ms;           /* summed duration of the vote/compaction launches    */
+    int32_t vote_launches;    /* per-level count and compaction launches            */
+    int32_t decide_launches;  /* per-level split-decision launches                  */
+    double vote_ms;           /* count_ms + write_ms                                */
     double decide_ms;         /* summed duration of the split-decision launches     */
     double extract_ms;        /* edge staging (image inputs)                        */
     double total_ms;          /* first to last event of the call                    */
-    int64_t vote_entries;     /* (parent, line) entries read by the vote launches   */
-    int64_t vote_written;     /* entries written by the vote launches               */
+    int64_t vote_entries;     /* (parent, line) entries read by the count launches  */
+    int64_t vote_written;     /* entries written by the compaction launches         */
+    double count_ms;          /* summed duration of the count launches              */
+    double write_ms;          /* summed duration of the compaction launches         */
 } hh_timing;
 
 /* Create a context on cfg->device.  Checks the device is a gfx950.

@@ -27,6 +27,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                       "(python paper_1007_0547_amd/_build.py)")
 
+# PyTorch ships its own copy of the HIP runtime (same soname).  Loading torch
+# first lets the library bind to that copy: two HIP runtimes in one process
+# cannot both open the GPU.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:
+    _torch = None
+
 _lib = C.CDLL(LIB_PATH)
 
 STATUS = {0: "HH_OK", -1: "HH_EINVAL", -2: "HH_ENOMEM", -3: "HH_ECAPACITY", -4: "HH_EDEVICE",
@@ -68,7 +76,8 @@ class _Info(C.Structure):
 class _Timing(C.Structure):
     _fields_ = [("vote_launches", C.c_int32), ("decide_launches", C.c_int32),
                 ("vote_ms", C.c_double), ("decide_ms", C.c_double), ("extract_ms", C.c_double),
-                ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64)]
+                ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64),
+                ("count_ms", C.c_double), ("write_ms", C.c_double)]
 
 
 CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),

@@ -3,13 +3,12 @@
 // One call runs every enabled pass of one image as a separate quadtree; the
 // trees share every launch.  The host enqueues the whole call without
 // waiting: edge staging, the root setup, then per level l (0 .. depth-1) the
-// vote/compaction launch, the one-workgroup scan of its decision totals and
-// the launch that writes the next level's regions (or the detected cells).
-// Level sizes stay on the device (LevelInfo records in the call's arena);
-// the host waits once, at the end, and reads the level records, the tree
-// records (the per-pass statistics follow from them) and the error word.  If
-// a level did not fit the arena the call is run again with a larger arena
-// (sizes learnt this way are kept for the next calls on the context).
+// count, decide, emit and compaction launches.  Level sizes stay on the
+// device (LevelInfo records in the call's arena); the host waits once, at
+// the end, and reads the level records, the tree records (the per-pass
+// statistics follow from them) and the error word.  If a level did not fit
+// the arena the call is run again with a larger arena (sizes learnt this way
+// are kept for the next calls on the context).
 #include "hh_engine.hpp"
 
 #include <algorithm>
@@ -170,8 +169,16 @@ FixedLayout fixed_layout(int32_t n_trees, int64_t cells_cap)
     return f;
 }
 
-Arena carve(char* base, const FixedLayout& f, int32_t n_trees, int64_t cells_cap, int64_t half_cap,
-            int32_t entry_bytes)
+struct Caps {
+    int64_t cells, mem, half, work;   // cells, member entries, bytes per half, scratch bytes
+};
+
+int64_t arena_bytes(const FixedLayout& f, const Caps& c, int32_t entry_bytes)
+{
+    return f.bytes + align256(c.mem * entry_bytes) + 2 * c.half + c.work;
+}
+
+Arena carve(char* base, const FixedLayout& f, int32_t n_trees, const Caps& c, int32_t entry_bytes)
 {
     Arena a{};
     a.info = reinterpret_cast<LevelInfo*>(base + f.info);
@@ -179,10 +186,16 @@ Arena carve(char* base, const FixedLayout& f, int32_t n_trees, int64_t cells_cap
     a.error = reinterpret_cast<uint32_t*>(base + f.error);
     a.scalar = reinterpret_cast<int64_t*>(base + f.scalar);
     a.cells = reinterpret_cast<Cell*>(base + f.cells);
-    a.cells_cap = cells_cap;
-    a.half[0] = base + f.bytes;
-    a.half[1] = a.half[0] + half_cap;
-    a.half_cap = half_cap;
+    a.cells_cap = c.cells;
+    char* p = base + f.bytes;
+    a.members = p;
+    a.mem_cap = c.mem;
+    p += align256(c.mem * entry_bytes);
+    a.half[0] = p;
+    a.half[1] = p + c.half;
+    a.half_cap = c.half;
+    a.work = p + 2 * c.half;
+    a.work_cap = c.work;
     a.n_trees = n_trees;
     a.entry_bytes = entry_bytes;
     return a;
@@ -282,32 +295,38 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
     return p;
 }
 
-// After an arena overflow: estimate the sizes the call needs from the level
-// records it left (levels before the failure are complete) and grow the
-// context's sizes.  A full tree doubles its list length per level.
-void grow_sizes(hh_ctx* ctx, const LevelInfo* info, int32_t n_trees, int32_t dmax, int32_t entry_bytes)
+// After an arena overflow: size the arena from the level records the call
+// left.  Levels up to the failure are exact (a split decision records the
+// next level's sizes before it checks that they fit); deeper levels are
+// estimated: a full tree doubles its list length per level.
+void grow_sizes(hh_ctx* ctx, const LevelInfo* info, int32_t dmax, int32_t entry_bytes)
 {
-    int64_t need_half = 0, need_cells = 0;
+    int64_t need_half = 0, need_work = 0, need_cells = 0, need_mem = 0;
     int last = -1;
     for (int l = 0; l <= dmax && l < kMaxLevels; ++l) {
-        if (info[l].P <= 0) break;
+        if (l > 0 && info[l].P <= 0 && info[l].cells <= 0) break;
         last = l;
-        const int64_t Pp = l ? info[l - 1].P : 0, Lp = l ? info[l - 1].L : 0;
-        const LevelLayout y = level_layout(nullptr, l, Pp, Lp, info[l].P, info[l].L, n_trees, entry_bytes);
-        const LevelLayout nx = level_layout(nullptr, l + 1, info[l].P, info[l].L, 0, 0, n_trees, entry_bytes);
-        need_half = std::max({need_half, y.end, nx.end});
-        if (l + 1 == dmax) need_cells = std::max(need_cells, 4 * info[l].P);
+        need_half = std::max(need_half, half_layout(nullptr, info[l].P, info[l].L, entry_bytes).end);
+        need_work = std::max(need_work, work_layout(nullptr, info[l].P, info[l].L).end);
+        need_cells = std::max(need_cells, info[l].cells_base + info[l].cells);
+        need_mem = std::max(need_mem, info[l].mem_base + info[l].mem);
     }
-    const int64_t growth = last >= 0 ? ((int64_t)1 << std::max(0, dmax - 1 - last)) : 4;
+    const int64_t growth = last >= 0 ? ((int64_t)1 << std::max(0, dmax - last)) : 4;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
         total_b = (size_t)1 << 40;
     }
-    const int64_t half_limit = (int64_t)((double)total_b * 0.4);
-    const int64_t want = need_half * growth + need_half / 4;
-    ctx->half_cap = std::min(std::max(ctx->half_cap * 2, want), std::max(half_limit, ctx->half_cap));
-    ctx->cells_cap = std::max(ctx->cells_cap * 2, need_cells + need_cells / 4);
+    const int64_t limit = (int64_t)((double)total_b * 0.3);
+    auto grow = [&](int64_t cur, int64_t need) {
+        const int64_t want = need * growth + need / 4;
+        return std::min(std::max(cur * 2, want), std::max(limit, cur));
+    };
+    ctx->half_cap = grow(ctx->half_cap, need_half);
+    ctx->work_cap = grow(ctx->work_cap, need_work);
+    ctx->mem_cap = std::min(std::max(ctx->mem_cap * 2, (need_mem + need_half / entry_bytes) * 2),
+                            std::max(limit / entry_bytes, ctx->mem_cap));
+    ctx->cells_cap = std::max(ctx->cells_cap * 2, need_cells * 2 + 4 * info[std::max(last, 0)].P);
 }
 
 }  // namespace
@@ -406,11 +425,11 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     uint32_t err = 0;
     for (int attempt = 0;; ++attempt) {
         if (attempt >= 8) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
-        fl = fixed_layout(n_trees, ctx->cells_cap);
-        const int64_t bytes = fl.bytes + 2 * ctx->half_cap;
+        const Caps caps{ctx->cells_cap, plan.membership ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        fl = fixed_layout(n_trees, caps.cells);
         arena.reset();
-        arena = DevBuf(pool, (size_t)bytes);
-        ar = carve(arena.as<char>(), fl, n_trees, ctx->cells_cap, ctx->half_cap, entry_bytes);
+        arena = DevBuf(pool, (size_t)arena_bytes(fl, caps, entry_bytes));
+        ar = carve(arena.as<char>(), fl, n_trees, caps, entry_bytes);
         res->timing = hh_timing{};
         hh_timing& tm = res->timing;
 
@@ -433,8 +452,7 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
             check(launch_extract(ea, st), "extract");
         }
         mark(ctx, 1);
-        const int64_t work_bound = std::max<int64_t>(in->kind == 1 ? n_pix : E_host, 1);
-        check(launch_begin(ar, d_trees.as<TreeDesc>(), n_trees, E_host, plan.T, plan.dmax, 2 * work_bound, st),
+        check(launch_begin(ar, d_trees.as<TreeDesc>(), n_trees, E_host, plan.T, plan.dmax, xy, ctx->grid, st),
               "begin");
         LevelArgs la{};
         la.ar = ar;
@@ -443,13 +461,14 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
         la.keep_members = plan.membership ? 1 : 0;
         for (int l = 0; l < plan.dmax; ++l) {
             la.level = l;
-            la.write_out = (l + 1 < plan.dmax || plan.membership) ? 1 : 0;
             mark(ctx, 3 + 4 * l);
-            check(launch_vote(la, plan.variant, plan.wide, ctx->grid, st), "vote");
+            check(launch_count(la, plan.variant, plan.wide, ctx->grid, st), "count");
             mark(ctx, 4 + 4 * l);
-            check(launch_scan(la, st), "scan");
+            check(launch_decide(la, kRangeGrid, st), "decide");
+            check(launch_emit(la, kRangeGrid, st), "emit");
             mark(ctx, 5 + 4 * l);
-            check(launch_emit(la, ctx->grid, st), "emit");
+            if (l + 1 < plan.dmax || plan.membership)
+                check(launch_write(la, plan.variant, plan.wide, ctx->grid, st), "write");
             mark(ctx, 6 + 4 * l);
         }
         mark(ctx, 2);
@@ -462,24 +481,27 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
             tm.total_ms = elapsed(ctx, 0, 2);
             tm.extract_ms = elapsed(ctx, 0, 1);
             for (int l = 0; l < plan.dmax; ++l) {
-                tm.vote_ms += elapsed(ctx, 3 + 4 * l, 4 + 4 * l);
-                tm.decide_ms += elapsed(ctx, 4 + 4 * l, 6 + 4 * l);
+                const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
+                tm.count_ms += c;
+                tm.write_ms += w;
+                tm.vote_ms += c + w;
+                tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
             }
-            tm.vote_launches = plan.dmax;
+            tm.vote_launches = plan.dmax + (plan.membership ? plan.dmax : plan.dmax - 1);
             tm.decide_launches = 2 * plan.dmax;
         }
         for (int l = 0; l < plan.dmax; ++l) {
             tm.vote_entries += info[l].L;
-            if (l + 1 < plan.dmax || plan.membership) tm.vote_written += info[l].votes;
+            if (l + 1 < plan.dmax) tm.vote_written += info[l + 1].L;
+            else if (plan.membership) tm.vote_written += info[l + 1].mem;
         }
-        if ((err & kErrArena) && !(err & (kErrPointRange | kErrInternal | kErrLookback))) {
-            grow_sizes(ctx, info, n_trees, plan.dmax, entry_bytes);
+        if ((err & kErrArena) && !(err & (kErrPointRange | kErrInternal))) {
+            grow_sizes(ctx, info, plan.dmax, entry_bytes);
             continue;
         }
         break;
     }
     if (err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
-    if (err & kErrLookback) throw Error{HH_EINTERNAL, "a bounded wait timed out"};
     if (err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
 
     const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
@@ -492,12 +514,9 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
         const int D = plan.dmax;
         n_cells_total = info[D].cells_base + info[D].cells;
         res->cells = ar.cells;
-        if (plan.membership && info[D - 1].P > 0) {
-            const int64_t Pp = D >= 2 ? info[D - 2].P : 0, Lp = D >= 2 ? info[D - 2].L : 0;
-            const LevelLayout y = level_layout(ar.half[(D - 1) & 1], D - 1, Pp, Lp, info[D - 1].P,
-                                               info[D - 1].L, n_trees, entry_bytes);
-            res->members = y.out;
-            res->info.member_slots = 4 * info[D - 1].L;
+        if (plan.membership) {
+            res->members = ar.members;
+            res->info.member_slots = info[D].mem_base + info[D].mem;
         }
     } else if (root_votes) {
         // depth 0: the root is the finest region, every line votes for it

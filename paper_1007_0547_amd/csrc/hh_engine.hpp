@@ -79,7 +79,7 @@ struct hh_result {
     hh::DevBuf dev_ids;        // point ids in the layout of `members` (made on request)
     const hh::Cell* cells = nullptr;     // all cells, (pass, key) order
     int64_t n_cells_total = 0;
-    const void* members = nullptr;       // voter entries referenced by cells
+    const void* members = nullptr;       // voter entries of the cells, cell after cell
     int32_t entry_bytes = 4;             // 4: packed point; 8: id << 32 | packed point
     bool have_members = false;
     bool depth0 = false;                 // the root is the only level: every point votes
@@ -101,11 +101,13 @@ struct hh_ctx {
     char* h_fixed = nullptr;
     hh::TreeDesc* h_trees = nullptr;
     // arena sizes that worked before (grown when a call overflows)
-    int64_t half_cap = 64ll << 20;
+    int64_t half_cap = 64ll << 20;      // bytes per level half
+    int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
+    int64_t mem_cap = 16ll << 20;       // member entries
     int64_t cells_cap = 1ll << 20;
     int32_t grid = 0;          // workgroups of the level kernels (fixed grid, tiles strided)
     // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
-    // then three per level (vote start, vote end = decide start, decide end)
+    // then four per level: before count, after count, after emit, after the compaction
     std::vector<hipEvent_t> events;
     // results not yet freed; destroyed with the context
     std::unordered_set<hh_result*> live_results;

@@ -3,29 +3,30 @@
 //
 // Level-synchronous form of the paper's depth-first search (Sec. 3): all
 // regions that split at level l (of every tree = pass of an image) are
-// processed together.  Their voter lists are stored back to back; a flat
-// entry index e in [0, L_l) walks all (parent region, line) pairs.  A list
+// processed together.  Their voter lists are stored back to back in one
+// dense list per level, so a flat entry index e in [0, L_l) walks all
+// (parent region, line) pairs and every load is a plain streaming load.  An
 // entry carries the line itself (the packed edge point, or the point id and
 // the packed point), so no launch gathers coordinates.
 //
-//   k_vote   one read of every (parent, line) entry: the 4-bit corner codes
-//            of the line for the four children (Sec. 2, getcode()) and the
-//            vote rule (code not 0000 / 1111, steps 5 and 12.v), evaluated as
-//            wavefront lane masks; a stable compaction of the voting lines
-//            into each child's list at a position fixed by the parent alone
-//            (child q of a parent with flat start s and length n starts at
-//            4 s + q n), so workgroups never wait on each other: a tile whose
-//            first parent began in an earlier tile recounts that prefix
-//            itself.  The tile holding a parent's last entry records the
-//            child votes and the parent's split decisions (step 13).
-//   k_scan   one workgroup: exclusive prefix of the per-tile decision totals.
-//   k_emit   per parent: the level-(l+1) region table in quad order (so key
-//            order is kept), or the detected cells at the finest level.
+// Per level, four launches:
+//   k_count   one read of every entry: the 4-bit corner codes of the line for
+//             the four children (Sec. 2, getcode()) and the vote rule (code
+//             not 0000 / 1111, steps 5 and 12.v) as wavefront lane masks, and
+//             per tile of kTile entries the child-vote counts of every
+//             region piece in it.
+//   k_decide  per region: its child votes (its pieces summed), the split
+//             decisions (step 13) and their sums per range of regions.
+//   k_emit    per region: offsets from those sums; the next level's region
+//             table in quad order (so key order is kept) and tile map, or the
+//             detected cells at the finest level.
+//   k_write   a second read of every entry: each vote for a kept child is
+//             written, in list order, to that child's list in the next
+//             level (or to the member buffer at the finest level).
 //
 // Level sizes never travel to the host: each launch reads them from the
 // arena's LevelInfo records written by the launches before it, and walks its
-// tiles with a fixed grid.  No launch uses atomics or waits on another
-// workgroup.
+// work with a fixed grid.  No launch waits on another workgroup.
 
 #include <hip/hip_runtime.h>
 
@@ -35,6 +36,8 @@
 
 namespace hh {
 namespace {
+
+constexpr int kScanThreads = 1024;   // the one-workgroup prefix of the edge staging
 
 // Pointers reached through argument structs are generic; the kernels access
 // device memory through these casts so the compiler emits global (not flat)
@@ -55,9 +58,27 @@ __device__ inline void raise_error(uint32_t* error, uint32_t bits)
     __hip_atomic_fetch_or(G(error), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// set bits of b at lanes below this lane
 __device__ inline uint32_t lanes_below(uint64_t b)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
+
+__device__ inline uint64_t bits_below(int p) { return ((uint64_t)1 << p) - 1; }   // p in 0..63
+
+// v (equal in every lane) as a wavefront-uniform value.  readfirstlane
+// returns int: widen through uint32_t so bit 31 does not sign-extend.
+__device__ inline uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+template <typename T>
+__device__ inline T pick4(const T (&v)[4], int k)
+{
+    return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
 }
 
 template <typename Entry> struct EntryOps;
@@ -148,12 +169,6 @@ __device__ inline void child_masks(bool valid, uint32_t point, uint32_t meta, ui
         circle_masks(valid, u, v, pi, pj, lc, s_log2, cm);
 }
 
-__device__ inline LevelLayout layout_of(const Arena& ar, int l)
-{
-    const int64_t Pp = l ? ar.info[l - 1].P : 0, Lp = l ? ar.info[l - 1].L : 0;
-    return level_layout(ar.half[l & 1], l, Pp, Lp, ar.info[l].P, ar.info[l].L, ar.n_trees, ar.entry_bytes);
-}
-
 __device__ inline int32_t wave_incl_scan32(int32_t x, int lane)
 {
 #pragma unroll
@@ -174,201 +189,295 @@ __device__ inline int64_t wave_incl_scan64(int64_t x, int lane)
     return x;
 }
 
-// LDS of one vote tile.
-struct VoteLds {
-    uint16_t rel[kTile + 1];       // region starts relative to the tile (0: at or before it)
-    uint16_t roff[kTile + 1][4];   // tile prefix of each child slot at the region's first entry
-    int64_t inb[kStage];           // staged region data (tiles with at most kStage regions)
-    int64_t obase[kStage];         //   4 * start
-    int32_t len[kStage];
-    uint32_t ij[kStage];
-    uint32_t meta[kStage];
-    int32_t tree[kStage];
-    int32_t cnt[kWaves][4];
-    int32_t dec[kWaves][kDecCh];
-};
-
-// Region fields of the tile's regions: from LDS when every region of the tile
-// is staged, otherwise from the region table.
-template <bool kStaged>
-struct RegionView {
-    const VoteLds& S;
-    const Region* regions;
-    int r0;
-    __device__ int64_t inb(int i) const { if constexpr (kStaged) return S.inb[i]; else return regions[r0 + i].in_base; }
-    __device__ int64_t obase(int i) const { if constexpr (kStaged) return S.obase[i]; else return 4 * regions[r0 + i].start; }
-    __device__ int32_t len(int i) const { if constexpr (kStaged) return S.len[i]; else return regions[r0 + i].len; }
-    __device__ uint32_t ij(int i) const { if constexpr (kStaged) return S.ij[i]; else return regions[r0 + i].ij; }
-    __device__ uint32_t meta(int i) const { if constexpr (kStaged) return S.meta[i]; else return regions[r0 + i].meta; }
-    __device__ int32_t tree(int i) const { if constexpr (kStaged) return S.tree[i]; else return regions[r0 + i].tree; }
-};
-
-struct VoteTile {
-    int64_t tile, t0, t_end, L;
-    int r0, nr, lc;
-    bool before;            // the first region began in an earlier tile
-    int32_t carry[4];       // its votes per child slot before this tile
-};
-
-// The entries of one tile: region, line, child masks, block prefix, stable
-// compaction into the children's lists, and the parents that end here.
-template <typename Entry, int kVariant, typename CT, bool kStaged>
-__device__ __forceinline__ void vote_tile(const LevelArgs& a, const LevelLayout& lay, VoteLds& S,
-                                          const Entry* list, Entry* out, const Region* regions,
-                                          const uint32_t* pts, const TreeDesc* trees, const VoteTile& t)
+__device__ inline int64_t wave_sum64(int64_t x)
 {
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
-    const RegionView<kStaged> rv{S, regions, t.r0};
-    const int64_t wb = t.t0 + (int64_t)wave * kWaveSpan;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
 
-    // region of every entry (binary search over the region starts)
-    uint32_t ridx[kEpt];
-    uint32_t valid = 0;
-    {
-        int lo_prev = 0;
+__device__ inline int32_t wave_sum32(int32_t x)
+{
 #pragma unroll
-        for (int k = 0; k < kEpt; ++k) {
-            const int64_t e = wb + k * kWave + lane;
-            ridx[k] = 0;
-            if (e < t.t_end) {
-                const int rel = (int)(e - t.t0);
-                int lo = lo_prev, hi = t.nr - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if ((int)S.rel[mid] <= rel) lo = mid; else hi = mid - 1;
-                }
-                lo_prev = lo;
-                ridx[k] = (uint32_t)lo;
-                valid |= 1u << k;
-            }
-        }
-    }
-    // the lines, all loads issued before any use
-    Entry ent[kEpt];
-#pragma unroll
-    for (int k = 0; k < kEpt; ++k) {
-        ent[k] = 0;
-        if ((valid >> k) & 1u) {
-            const int64_t i = rv.inb((int)ridx[k]) + wb + k * kWave + lane;
-            ent[k] = list ? list[i] : EntryOps<Entry>::root(pts, i);
-        }
-    }
-    // child masks and per-wave counts
-    uint32_t bits = 0;   // 4 child bits per entry, entry k at bits 4k .. 4k+3
-    int32_t cnt[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kEpt; ++k) {
-        const int idx = (int)ridx[k];
-        uint64_t cm[4];
-        child_masks<kVariant, CT>((valid >> k) & 1u, EntryOps<Entry>::point(ent[k]), rv.meta(idx), rv.ij(idx),
-                                  t.lc, cm);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            cnt[q] += (int32_t)__popcll(cm[q]);
-            bits |= (uint32_t)((cm[q] >> lane) & 1u) << (4 * k + q);
-        }
-        // keep the rounds apart: their lane masks live in scalar registers
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if (lane == 0)
-        for (int q = 0; q < 4; ++q) S.cnt[wave][q] = cnt[q];
-    __syncthreads();
-    int32_t base[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        base[q] = 0;
-        for (int w = 0; w < wave; ++w) base[q] += S.cnt[w][q];
-    }
-    // tile prefix of each child slot at the first entry of each region that starts here
-    {
-        int32_t run[4] = {base[0], base[1], base[2], base[3]};
-#pragma unroll
-        for (int k = 0; k < kEpt; ++k) {
-            const int idx = (int)ridx[k];
-            const int64_t e = wb + k * kWave + lane;
-            const bool first = ((valid >> k) & 1u) && (int)(e - t.t0) == (int)S.rel[idx] && !(idx == 0 && t.before);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t m = __ballot((bits >> (4 * k + q)) & 1u);
-                if (first) S.roff[idx][q] = (uint16_t)(run[q] + (int32_t)lanes_below(m));
-                run[q] += (int32_t)__popcll(m);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    __syncthreads();
+    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
 
-    // stable compaction into each child's list; the entry that closes a region
-    // records the child votes and the region's split decisions
-    int32_t run[4] = {base[0], base[1], base[2], base[3]};
-    int32_t dec_run[kDecCh] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kEpt; ++k) {
-        const int64_t e = wb + k * kWave + lane;
-        const bool ok = (valid >> k) & 1u;
-        const int idx = (int)ridx[k];
-        const int64_t obase = ok ? rv.obase(idx) : 0;
-        const int32_t len = ok ? rv.len(idx) : 0;
-        const bool carried = idx == 0 && t.before;
-        int32_t votes[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t bit = (bits >> (4 * k + q)) & 1u;
-            const uint64_t m = __ballot(bit);
-            const int32_t X = run[q] + (int32_t)lanes_below(m);
-            const int32_t rank = carried ? X + t.carry[q] : X - (int32_t)S.roff[idx][q];
-            if (bit && a.write_out) out[obase + (int64_t)q * len + rank] = ent[k];
-            votes[q] = rank + (int32_t)bit;   // votes of child q up to and including e
-            run[q] += (int32_t)__popcll(m);
-        }
-        const bool last =
-            ok && ((idx + 1 < t.nr) ? ((int)S.rel[idx + 1] == (int)(e - t.t0) + 1) : (e + 1 == t.L));
-        if (__ballot(last)) {
-            int32_t dv[kDecCh] = {0, 0, 0, 0};
-            if (last) {
-                const int64_t p = t.r0 + idx;
-                const int32_t thr = trees[rv.tree(idx)].threshold;
-                const bool finest = rv.meta(idx) & kMetaChildFinest;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    G(lay.cv)[p * 4 + q] = votes[q];
-                    dv[3] += votes[q];
-                    if (votes[q] > thr) {
-                        if (finest) dv[2] += 1;
-                        else {
-                            dv[0] += 1;
-                            dv[1] += votes[q];
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kDecCh; ++c) {
-                const int32_t incl = wave_incl_scan32(dv[c], lane);
-                if (last) G(lay.dvw)[(int64_t)(t.r0 + idx) * kDecCh + c] = dec_run[c] + incl - dv[c];
-                dec_run[c] += __shfl(incl, kWave - 1, kWave);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    if (lane == 0)
-        for (int c = 0; c < kDecCh; ++c) S.dec[wave][c] = dec_run[c];
-    __syncthreads();
-    if (tid < kWaves * kDecCh) {
-        const int w = tid / kDecCh, c = tid % kDecCh;
-        int32_t pre = 0;
-        for (int v = 0; v < w; ++v) pre += S.dec[v][c];
-        G(lay.wpre)[(t.tile * kWaves + w) * kDecCh + c] = pre;
-        if (w == kWaves - 1) G(lay.vts)[t.tile * kDecCh + c] = pre + S.dec[w][c];
+// ------------------------------------------------------------------ tiles
+//
+// A tile is kTile consecutive entries of a level's list: 32 rows of 64,
+// wavefront w taking rows 8w .. 8w+7.  Its regions are tile_first[t] ..
+// tile_first[t+1] (local indices 0 .. nr-1; local 0 holds the tile's first
+// entry).  In LDS the tile keeps a bitmap of the entries (other than the
+// first) that begin a region, so the local region of an entry is the number
+// of marked entries up to it, and a row's marks form one 64-bit word.
+
+struct TileRange {
+    int r0, nr;
+    bool carried;   // local region 0 began in an earlier tile
+};
+
+__device__ inline bool tile_range(const int32_t* tile_first, int64_t tile, int64_t nt, int64_t P, TileRange& tr)
+{
+    const int r0 = tile_first[tile];
+    const int r1 = tile + 1 < nt ? tile_first[tile + 1] : (int)(P - 1);
+    tr.r0 = r0;
+    tr.nr = r1 - r0 + 1;   // <= kTile + 1: every region holds at least one entry
+    return r0 >= 0 && r1 < P && tr.nr >= 1 && tr.nr <= kTile + 1;
+}
+
+__device__ inline uint64_t row_word(const uint32_t* bm, int row)
+{
+    return uniform64((uint64_t)bm[2 * row] | ((uint64_t)bm[2 * row + 1] << 32));
+}
+
+// marked entries in the rows before wavefront `wave`
+__device__ inline int starts_before(const uint32_t* bm, int wave, int lane)
+{
+    const int nw = 2 * kRows * wave;   // bitmap words before the wavefront's rows (< 64)
+    const int c = lane < nw ? __popc(bm[lane]) : 0;
+    return __builtin_amdgcn_readfirstlane(wave_sum32(c));
+}
+
+__device__ inline void region_fields(const uint32_t* s_ij, const uint32_t* s_meta, const Region* regions, int r0,
+                                     int local, uint32_t& ij, uint32_t& meta)
+{
+    if (local < kStage) {
+        ij = s_ij[local];
+        meta = s_meta[local];
+    } else {
+        ij = regions[r0 + local].ij;
+        meta = regions[r0 + local].meta;
     }
 }
 
-template <typename Entry, int kVariant, typename CT>
-__global__ __launch_bounds__(kBlock) void k_vote(LevelArgs a)
+struct CountLds {
+    uint32_t bm[kTile / 32];
+    uint32_t ij[kStage];
+    uint32_t meta[kStage];
+    int32_t wfirst[kWaves][4];   // per wavefront: votes of the region open at its first entry (up to its close)
+    int32_t wlast[kWaves][4];    //   votes of the region open at its end, from that region's start
+    int32_t wlocal[kWaves];      //   local index of that region
+    int32_t wclosed[kWaves];     //   whether the region open at its first entry ended inside it
+};
+
+struct WriteLds {
+    uint32_t bm[kTile / 32];
+    uint32_t ij[kStage];
+    uint32_t meta[kStage];
+    int64_t dst[kStage][4];
+};
+
+template <typename Lds>
+__device__ inline bool stage_tile(Lds& S, const Region* regions, int64_t t0, const TileRange& tr)
 {
-    __shared__ VoteLds S;
+    for (int k = threadIdx.x; k < tr.nr; k += kBlock) {
+        const Region R = regions[tr.r0 + k];
+        const int64_t rel = R.start - t0;
+        if (rel >= 1 && rel < kTile) atomicOr(&S.bm[rel >> 5], 1u << (rel & 31));
+        if (k < kStage) {
+            S.ij[k] = R.ij;
+            S.meta[k] = R.meta;
+        }
+    }
+    return regions[tr.r0].start < t0;
+}
+
+// ------------------------------------------------------------------ k_count
+//
+// Child-vote counts of every region piece of a tile.  A wavefront walks its
+// rows keeping the counts of the region open at the current entry in scalar
+// registers; a region that begins and ends inside the wavefront is written
+// out at once (head), the rest is combined across the four wavefronts at the
+// end of the tile: head for a region that begins in the tile, tcar for the
+// region carried in from the previous tile, and woff, the votes of each
+// wavefront's first region counted before that wavefront inside the tile.
+template <typename Entry, int kVariant, typename CT>
+__global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
+{
+    __shared__ CountLds S;
+    const Arena& ar = a.ar;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    if (stopped(ar.error)) return;
+    const int l = a.level;
+    const int lc = l + 1;
+    const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    if (P == 0) return;
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, L);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap) {
+        if (tid == 0 && blockIdx.x == 0) raise_error(ar.error, kErrArena);
+        return;
+    }
+    const Entry* const list = G(static_cast<const Entry*>(hl.list));
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
+    int32_t* const head = G(wl.head);
+    int32_t* const tcar = G(wl.tcar);
+    int32_t* const woff = G(wl.woff);
+    const int64_t nt = cdiv(L, kTile);
+
+    if (tid < kTile / 32) S.bm[tid] = 0u;
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const int64_t t0 = tile * kTile;
+        const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
+        Entry ent[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = rb + k * kWave + lane;
+            ent[k] = e < L ? list[e] : Entry(0);
+        }
+        TileRange tr;
+        if (!tile_range(tile_first, tile, nt, P, tr)) {
+            if (tid == 0) raise_error(ar.error, kErrInternal);
+            return;
+        }
+        __syncthreads();   // the previous tile is done with S (its bitmap is clear again)
+        const bool carried = stage_tile(S, regions, t0, tr);
+        __syncthreads();
+
+        int open = starts_before(S.bm, wave, lane);   // local index of the open region
+        bool open_here = false;                       // it began inside this wavefront
+        bool closed = false;                          // the first region ended inside this wavefront
+        int32_t run[4] = {0, 0, 0, 0}, first[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = rb + k * kWave + lane;
+            const uint64_t W = row_word(S.bm, wave * kRows + k);
+            const uint64_t le = W & ((2ull << lane) - 1);
+            const int local = std::min(open + (int)__popcll(le), tr.nr - 1);
+            uint32_t ij, meta;
+            region_fields(S.ij, S.meta, regions, tr.r0, local, ij, meta);
+            uint64_t cm[4];
+            child_masks<kVariant, CT>(e < L, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
+            uint64_t rest = W;
+            int prev = 0;
+            while (rest) {   // regions that end inside this row
+                const int p = __builtin_ctzll(rest);
+                rest &= rest - 1;
+                const uint64_t seg = bits_below(p) & ~bits_below(prev);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & seg);
+                if (open_here) {
+                    if (lane < 4 && tr.r0 + open < P) head[(int64_t)(tr.r0 + open) * 4 + lane] = pick4(run, lane);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) first[q] = run[q];
+                    closed = true;
+                }
+                ++open;
+                open_here = true;
+                prev = p;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[q] = 0;
+            }
+            const uint64_t tail = ~bits_below(prev);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
+        }
+        if (!closed)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) first[q] = run[q];
+        if (lane < 4) {
+            S.wfirst[wave][lane] = pick4(first, lane);
+            S.wlast[wave][lane] = pick4(run, lane);
+        }
+        if (lane == 0) {
+            S.wlocal[wave] = open;
+            S.wclosed[wave] = closed ? 1 : 0;
+        }
+        __syncthreads();
+        if (tid < 4) {   // one thread per child slot
+            const int q = tid;
+            int cur = 0;
+            bool cur_carried = carried;
+            int32_t cnt = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                woff[(tile * kWaves + w) * 4 + q] = cnt;
+                cnt += S.wfirst[w][q];
+                if (S.wclosed[w]) {
+                    if (cur_carried) tcar[tile * 4 + q] = cnt;
+                    else if (tr.r0 + cur < P) head[(int64_t)(tr.r0 + cur) * 4 + q] = cnt;
+                    cur = S.wlocal[w];
+                    cur_carried = false;
+                    cnt = S.wlast[w][q];
+                }
+            }
+            if (cur_carried) tcar[tile * 4 + q] = cnt;
+            else {
+                if (tr.r0 + cur < P) head[(int64_t)(tr.r0 + cur) * 4 + q] = cnt;
+                if (!carried) tcar[tile * 4 + q] = 0;
+            }
+        }
+        if (tid < kTile / 32) S.bm[tid] = 0u;   // every wavefront has read the bitmap
+    }
+}
+
+// ------------------------------------------------------------------ k_decide / k_emit
+//
+// Both launches split the P regions into blocks of kBlock and the blocks
+// into kRangeGrid contiguous ranges, range g going to workgroup g of either
+// launch.  k_decide leaves one sum per range and channel; k_emit takes the
+// exclusive prefix of those sums as its range's starting offsets, so no
+// launch scans all regions.
+
+__device__ inline void range_of(int64_t nb, int g, int64_t& b0, int64_t& b1)
+{
+    b0 = nb * g / kRangeGrid;
+    b1 = nb * (g + 1) / kRangeGrid;
+}
+
+// Decision channels of one region from its child votes.
+__device__ inline void decision(const int32_t (&cv)[4], int32_t thr, bool finest, int64_t (&dv)[kAggCh])
+{
+#pragma unroll
+    for (int c = 0; c < kAggCh; ++c) dv[c] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        dv[4] += cv[q];
+        if (cv[q] > thr) {
+            if (finest) {
+                dv[2] += 1;
+                dv[3] += cv[q];
+            } else {
+                dv[0] += 1;
+                dv[1] += cv[q];
+            }
+        }
+    }
+}
+
+__device__ inline void block_scan4(const int32_t (&v)[4], int32_t (&ex)[4], int32_t (&tot)[4], int32_t (*s)[4])
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int32_t inc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) inc[q] = wave_incl_scan32(v[q], lane);
+    if (lane == kWave - 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[wave][q] = inc[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int32_t pre = 0, all = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) pre += s[w][q];
+            all += s[w][q];
+        }
+        ex[q] = pre + inc[q] - v[q];
+        tot[q] = all;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
+{
+    __shared__ int32_t s_long[kBlock];
+    __shared__ int32_t s_nlong;
+    __shared__ int32_t s_scan[kWaves][4];
+    __shared__ int64_t s_red[kWaves][kAggCh];
     const Arena& ar = a.ar;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -377,150 +486,98 @@ __global__ __launch_bounds__(kBlock) void k_vote(LevelArgs a)
     const int l = a.level;
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
     if (P == 0) return;
-    const LevelLayout lay = layout_of(ar, l);
-    if (lay.end > ar.half_cap) {
-        if (tid == 0 && blockIdx.x == 0) raise_error(ar.error, kErrArena);
-        return;
-    }
-    const Entry* const list = G(l ? static_cast<const Entry*>(layout_of(ar, l - 1).out) : nullptr);
-    Entry* const out = G(static_cast<Entry*>(lay.out));
-    const Region* const regions = G(static_cast<const Region*>(lay.regions));
-    const int32_t* tile_first = G(static_cast<const int32_t*>(lay.tile_first));
-    const uint32_t* const pts = G(a.xy);
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, L);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;   // k_count raised the error
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    const int32_t* const head = G(static_cast<const int32_t*>(wl.head));
+    const int32_t* const tcar = G(static_cast<const int32_t*>(wl.tcar));
+    int32_t* const tpre = G(wl.tpre);
+    int32_t* const cvo = G(wl.cv);
     const TreeDesc* const trees = G(a.trees);
-    const int64_t n_tiles = cdiv(L, kTile);
+    const int64_t nb = cdiv(P, kBlock);
 
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        VoteTile t;
-        t.tile = tile;
-        t.t0 = tile * kTile;
-        t.t_end = std::min<int64_t>(t.t0 + kTile, L);
-        t.L = L;
-        t.lc = l + 1;
-        t.r0 = tile_first[tile];
-        const int r1 = (tile + 1 < n_tiles) ? tile_first[tile + 1] : (int)(P - 1);
-        t.nr = r1 - t.r0 + 1;   // <= kTile + 1: every region holds at least one entry
-        if (t.r0 < 0 || r1 >= P || t.nr < 1 || t.nr > kTile + 1) {
-            if (tid == 0) raise_error(ar.error, kErrInternal);
-            continue;
-        }
-        __syncthreads();   // LDS of the previous tile is free
-        for (int k = tid; k < t.nr; k += kBlock) {
-            const Region R = regions[t.r0 + k];
-            const int64_t rel = R.start - t.t0;
-            S.rel[k] = (uint16_t)(rel <= 0 ? 0 : (rel > kTile ? kTile : rel));
-            if (k < kStage) {
-                S.inb[k] = R.in_base;
-                S.obase[k] = 4 * R.start;
-                S.len[k] = R.len;
-                S.ij[k] = R.ij;
-                S.meta[k] = R.meta;
-                S.tree[k] = R.tree;
+    for (int g = blockIdx.x; g < kRangeGrid; g += gridDim.x) {
+        int64_t b0, b1;
+        range_of(nb, g, b0, b1);
+        int64_t acc[kAggCh] = {0, 0, 0, 0, 0};
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t r = b * kBlock + tid;
+            const bool valid = r < P;
+            Region R{};
+            int64_t ts = 0, te = 0;
+            int32_t tot[4] = {0, 0, 0, 0};
+            if (valid) {
+                R = regions[r];
+                ts = R.start / kTile;
+                te = (R.start + R.len - 1) / kTile;
+                if (R.len < 1 || R.start + R.len > L) {
+                    raise_error(ar.error, kErrInternal);
+                    te = ts;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tot[q] = head[r * 4 + q];
+            }
+            const bool is_long = valid && te - ts > kLongSpan;
+            if (valid && !is_long) {
+                for (int64_t t = ts + 1; t <= te; ++t)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        tpre[t * 4 + q] = tot[q];
+                        tot[q] += tcar[t * 4 + q];
+                    }
+            }
+            // regions over many tiles: the workgroup scans their tiles together
+            if (tid == 0) s_nlong = 0;
+            __syncthreads();
+            if (is_long) s_long[atomicAdd(&s_nlong, 1)] = tid;
+            __syncthreads();
+            const int nlong = s_nlong;
+            for (int k = 0; k < nlong; ++k) {
+                const int owner = s_long[k];
+                const int64_t rr = b * kBlock + owner;
+                const Region RR = regions[rr];
+                const int64_t ts2 = RR.start / kTile, te2 = (RR.start + RR.len - 1) / kTile;   // checked above
+                int32_t run[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[q] = head[rr * 4 + q];
+                for (int64_t c0 = ts2 + 1; c0 <= te2; c0 += kBlock) {
+                    const int64_t t = c0 + tid;
+                    int32_t v[4], ex[4], all[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = t <= te2 ? tcar[t * 4 + q] : 0;
+                    block_scan4(v, ex, all, s_scan);
+                    if (t <= te2)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) tpre[t * 4 + q] = run[q] + ex[q];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) run[q] += all[q];
+                }
+                if (tid == owner)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tot[q] = run[q];
+            }
+            if (valid) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cvo[r * 4 + q] = tot[q];
+                int64_t dv[kAggCh];
+                decision(tot, trees[R.tree].threshold, (R.meta & kMetaChildFinest) != 0, dv);
+#pragma unroll
+                for (int c = 0; c < kAggCh; ++c) acc[c] += dv[c];
             }
         }
-        const int64_t start0 = regions[t.r0].start;
-        t.before = start0 < t.t0;
+#pragma unroll
+        for (int c = 0; c < kAggCh; ++c) {
+            const int64_t s = wave_sum64(acc[c]);
+            if (lane == 0) s_red[wave][c] = s;
+        }
         __syncthreads();
-
-        // lines of the first region before this tile: their child-slot counts
-        for (int q = 0; q < 4; ++q) t.carry[q] = 0;
-        if (t.before) {
-            const int64_t inb = S.inb[0];
-            const uint32_t ij = S.ij[0], meta = S.meta[0];
-            int32_t c[4] = {0, 0, 0, 0};
-            for (int64_t b = start0; b < t.t0; b += kTile) {
-                Entry ent[kEpt];
-#pragma unroll
-                for (int k = 0; k < kEpt; ++k) {
-                    const int64_t e = b + k * kBlock + tid;
-                    ent[k] = 0;
-                    if (e < t.t0) ent[k] = list ? list[inb + e] : EntryOps<Entry>::root(pts, inb + e);
-                }
-#pragma unroll
-                for (int k = 0; k < kEpt; ++k) {
-                    const int64_t e = b + k * kBlock + tid;
-                    uint64_t cm[4];
-                    child_masks<kVariant, CT>(e < t.t0, EntryOps<Entry>::point(ent[k]), meta, ij, t.lc, cm);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) c[q] += (int32_t)__popcll(cm[q]);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            if (lane == 0)
-                for (int q = 0; q < 4; ++q) S.cnt[wave][q] = c[q];
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                for (int w = 0; w < kWaves; ++w) t.carry[q] += S.cnt[w][q];
-            __syncthreads();
+        if (tid < kAggCh) {
+            int64_t s = 0;
+            for (int w = 0; w < kWaves; ++w) s += s_red[w][tid];
+            G(wl.agg)[(int64_t)g * kAggCh + tid] = s;
         }
-        if (t.nr <= kStage)
-            vote_tile<Entry, kVariant, CT, true>(a, lay, S, list, out, regions, pts, trees, t);
-        else
-            vote_tile<Entry, kVariant, CT, false>(a, lay, S, list, out, regions, pts, trees, t);
-    }
-}
-
-// One workgroup: exclusive prefix of the per-tile decision totals of level l
-// and the sizes of level l+1.
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void k_scan(LevelArgs a)
-{
-    __shared__ int64_t s_w[kScanThreads / kWave][kDecCh];
-    const Arena& ar = a.ar;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
-    if (stopped(ar.error)) return;
-    const int l = a.level;
-    const int lc = l + 1;
-    const int64_t P = ar.info[l].P, L = ar.info[l].L;
-    const int64_t cells_base = ar.info[l].cells_base + ar.info[l].cells;
-    if (P == 0) {
-        if (tid == 0) {
-            LevelInfo& nx = ar.info[lc];
-            nx.P = 0;
-            nx.L = 0;
-            nx.cells = 0;
-            nx.cells_base = cells_base;
-        }
-        return;
-    }
-    const LevelLayout lay = layout_of(ar, l);
-    const int64_t nt = cdiv(L, kTile);
-    const int64_t chunk = cdiv(nt, kScanThreads);
-    const int64_t b = std::min<int64_t>(nt, tid * chunk), e = std::min<int64_t>(nt, b + chunk);
-    int64_t sum[kDecCh] = {0, 0, 0, 0};
-    for (int64_t t = b; t < e; ++t)
-#pragma unroll
-        for (int c = 0; c < kDecCh; ++c) sum[c] += G(lay.vts)[t * kDecCh + c];
-    int64_t incl[kDecCh];
-#pragma unroll
-    for (int c = 0; c < kDecCh; ++c) {
-        incl[c] = wave_incl_scan64(sum[c], lane);
-        if (lane == kWave - 1) s_w[wave][c] = incl[c];
-    }
-    __syncthreads();
-    int64_t run[kDecCh];
-#pragma unroll
-    for (int c = 0; c < kDecCh; ++c) {
-        run[c] = incl[c] - sum[c];
-        for (int w = 0; w < wave; ++w) run[c] += s_w[w][c];
-    }
-    for (int64_t t = b; t < e; ++t)
-#pragma unroll
-        for (int c = 0; c < kDecCh; ++c) {
-            G(lay.vtp)[t * kDecCh + c] = run[c];
-            run[c] += G(lay.vts)[t * kDecCh + c];
-        }
-    if (tid == kScanThreads - 1) {
-        LevelInfo& nx = ar.info[lc];
-        nx.P = run[0];
-        nx.L = run[1];
-        nx.cells = run[2];
-        nx.cells_base = cells_base;
-        ar.info[l].votes = run[3];
+        __syncthreads();
     }
 }
 
@@ -537,86 +594,302 @@ __device__ inline int64_t key_of(int32_t i, int32_t j, int depth)
 
 __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
 {
+    __shared__ int64_t s_red[kWaves][2 * kAggCh];
+    __shared__ int64_t s_w[kWaves][kAggCh];
     const Arena& ar = a.ar;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    if (stopped(ar.error)) return;
+    const int l = a.level;
+    const int lc = l + 1;
+    const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    const int64_t cells_base = ar.info[l].cells_base + ar.info[l].cells;
+    const int64_t mem_base = ar.info[l].mem_base + ar.info[l].mem;
+    if (P == 0) {
+        if (tid == 0 && blockIdx.x == 0) {
+            LevelInfo& nx = ar.info[lc];
+            nx.P = 0;
+            nx.L = 0;
+            nx.cells = 0;
+            nx.mem = 0;
+            nx.cells_base = cells_base;
+            nx.mem_base = mem_base;
+        }
+        return;
+    }
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, L);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
+    const int64_t* const agg = G(static_cast<const int64_t*>(wl.agg));
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    const int32_t* const cvi = G(static_cast<const int32_t*>(wl.cv));
+    int64_t* const dsto = G(wl.dst);
+    const TreeDesc* const trees = G(a.trees);
+    const int64_t nb = cdiv(P, kBlock);
+
+    for (int g = blockIdx.x; g < kRangeGrid; g += gridDim.x) {
+        // this range's offsets and the level totals
+        int64_t pre[kAggCh], tot[kAggCh];
+        {
+            int64_t p2[2 * kAggCh];
+#pragma unroll
+            for (int c = 0; c < 2 * kAggCh; ++c) p2[c] = 0;
+            for (int k = tid; k < kRangeGrid; k += kBlock)
+#pragma unroll
+                for (int c = 0; c < kAggCh; ++c) {
+                    const int64_t v = agg[(int64_t)k * kAggCh + c];
+                    if (k < g) p2[c] += v;
+                    p2[kAggCh + c] += v;
+                }
+#pragma unroll
+            for (int c = 0; c < 2 * kAggCh; ++c) {
+                const int64_t s = wave_sum64(p2[c]);
+                if (lane == 0) s_red[wave][c] = s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < kAggCh; ++c) {
+                pre[c] = 0;
+                tot[c] = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    pre[c] += s_red[w][c];
+                    tot[c] += s_red[w][kAggCh + c];
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t P2 = tot[0], L2 = tot[1];
+        const HalfLayout nx = half_layout(ar.half[lc & 1], P2, L2, ar.entry_bytes);
+        const bool fits = nx.end <= ar.half_cap && work_layout(ar.work, P2, L2).end <= ar.work_cap &&
+                          cells_base + tot[2] <= ar.cells_cap &&
+                          (!a.keep_members || mem_base + tot[3] <= ar.mem_cap);
+        if (g == 0 && tid == 0) {
+            LevelInfo& ni = ar.info[lc];
+            ni.P = P2;
+            ni.L = L2;
+            ni.cells = tot[2];
+            ni.cells_base = cells_base;
+            ni.mem = tot[3];
+            ni.mem_base = mem_base;
+            ar.info[l].votes = tot[4];
+            if (!fits) raise_error(ar.error, kErrArena);
+        }
+        if (!fits) return;
+        Region* const nreg = G(nx.regions);
+        int32_t* const ntf = G(nx.tile_first);
+        const int64_t n_ntiles = cdiv(L2, kTile);
+        int64_t b0, b1;
+        range_of(nb, g, b0, b1);
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t r = b * kBlock + tid;
+            const bool valid = r < P;
+            Region R{};
+            int32_t cv[4] = {0, 0, 0, 0};
+            int32_t thr = 0;
+            int64_t dv[kAggCh] = {0, 0, 0, 0, 0};
+            if (valid) {
+                R = regions[r];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cv[q] = cvi[r * 4 + q];
+                thr = trees[R.tree].threshold;
+                decision(cv, thr, (R.meta & kMetaChildFinest) != 0, dv);
+            }
+            int64_t ex[kAggCh], inc[kAggCh];
+#pragma unroll
+            for (int c = 0; c < kAggCh; ++c) {
+                inc[c] = wave_incl_scan64(dv[c], lane);
+                if (lane == kWave - 1) s_w[wave][c] = inc[c];
+            }
+            __syncthreads();
+            int64_t btot[kAggCh];
+#pragma unroll
+            for (int c = 0; c < kAggCh; ++c) {
+                int64_t wp = 0;
+                btot[c] = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    if (w < wave) wp += s_w[w][c];
+                    btot[c] += s_w[w][c];
+                }
+                ex[c] = pre[c] + wp + inc[c] - dv[c];
+            }
+            __syncthreads();
+            if (valid) {
+                const TreeDesc T = trees[R.tree];
+                const bool finest = R.meta & kMetaChildFinest;
+                const int32_t pi = (int32_t)(R.ij & 0xFFFFu), pj = (int32_t)(R.ij >> 16);
+                int64_t ri = ex[0], start = ex[1], ci = cells_base + ex[2], mo = mem_base + ex[3];
+                int64_t dq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    dq[q] = -1;
+                    if (cv[q] <= thr) continue;
+                    const int32_t e = (q == 0 || q == 3) ? 1 : 0;
+                    const int32_t n = (q <= 1) ? 1 : 0;
+                    const int32_t ci_ = 2 * pi + e, cj = 2 * pj + n;
+                    if (finest) {
+                        Cell c;
+                        c.i = ci_;
+                        c.j = cj;
+                        c.votes = cv[q];
+                        c.pass = T.pass;
+                        c.key = key_of(ci_, cj, lc);
+                        c.member_off = a.keep_members ? mo : -1;
+                        G(ar.cells)[ci++] = c;
+                        if (a.keep_members) dq[q] = mo;
+                        mo += cv[q];
+                    } else {
+                        if (ri >= P2) {
+                            raise_error(ar.error, kErrInternal);
+                            continue;
+                        }
+                        Region C;
+                        C.start = start;
+                        C.ij = (uint32_t)ci_ | ((uint32_t)cj << 16);
+                        C.len = cv[q];
+                        C.tree = R.tree;
+                        C.meta = (R.meta & ~kMetaChildFinest) | (lc + 1 == T.dmax ? kMetaChildFinest : 0u);
+                        nreg[ri] = C;
+                        // next-level tiles whose first entry falls inside this region
+                        for (int64_t t = cdiv(start, kTile); t * kTile < start + cv[q] && t < n_ntiles; ++t)
+                            ntf[t] = (int32_t)ri;
+                        dq[q] = start;
+                        ++ri;
+                        start += cv[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dsto[r * 4 + q] = dq[q];
+                // the first parent of each tree records where its tree's sums begin
+                if (r == 0 || regions[r - 1].tree != R.tree) {
+                    int64_t* rc = G(ar.rec + ((int64_t)R.tree * kMaxLevels + l) * kRecCh);
+                    rc[0] = r;
+                    rc[1] = R.start;
+                    rc[2] = ex[0];
+                    rc[3] = ex[1];
+                    rc[4] = ex[2];
+                    rc[5] = ex[4];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kAggCh; ++c) pre[c] += btot[c];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ k_write
+//
+// Second read of every entry.  A vote of the entry for child q of its region
+// r goes to dst[r][q] + its rank among the votes of r for q in list order.
+// Within a row the rank is a lane count: for the lanes of the region open at
+// the row's first entry the wavefront's running count plus the lanes below,
+// for a region that begins in the row the lanes below minus the lanes below
+// its first entry.  A wavefront starts its running counts from woff (and the
+// carried region from tpre), so wavefronts never exchange counts.
+template <typename Entry, int kVariant, typename CT>
+__global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
+{
+    __shared__ WriteLds S;
+    const Arena& ar = a.ar;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     if (stopped(ar.error)) return;
     const int l = a.level;
     const int lc = l + 1;
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
     if (P == 0) return;
-    const LevelLayout lay = layout_of(ar, l);
-    const LevelLayout nxt = level_layout(ar.half[lc & 1], lc, P, L, 0, 0, ar.n_trees, ar.entry_bytes);
-    if (nxt.end > ar.half_cap) {
-        if (threadIdx.x == 0 && blockIdx.x == 0) raise_error(ar.error, kErrArena);
-        return;
-    }
-    const int64_t cells_base = ar.info[lc].cells_base;
-    for (int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x; p < P; p += (int64_t)gridDim.x * kBlock) {
-        const Region R = G(lay.regions)[p];
-        const int64_t le = R.start + R.len - 1;   // the region's last entry
-        const int64_t tile = le / kTile;
-        const int64_t w = (le - tile * kTile) / kWaveSpan;
-        int64_t pre[kDecCh];
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, L);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
+    const int64_t P2 = ar.info[lc].P, L2 = ar.info[lc].L;
+    const HalfLayout nx = half_layout(ar.half[lc & 1], P2, L2, ar.entry_bytes);
+    if (nx.end > ar.half_cap) return;
+    const int64_t mem_end = a.keep_members ? ar.info[lc].mem_base + ar.info[lc].mem : 0;
+    if (mem_end > ar.mem_cap) return;
+    const Entry* const list = G(static_cast<const Entry*>(hl.list));
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
+    const int64_t* const dsti = G(static_cast<const int64_t*>(wl.dst));
+    const int32_t* const tpre = G(static_cast<const int32_t*>(wl.tpre));
+    const int32_t* const woff = G(static_cast<const int32_t*>(wl.woff));
+    Entry* const nlist = G(static_cast<Entry*>(nx.list));
+    Entry* const members = G(static_cast<Entry*>(ar.members));
+    const int64_t nt = cdiv(L, kTile);
+
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const int64_t t0 = tile * kTile;
+        const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
+        Entry ent[kRows];
 #pragma unroll
-        for (int c = 0; c < kDecCh; ++c)
-            pre[c] = G(lay.vtp)[tile * kDecCh + c] + G(lay.wpre)[(tile * kWaves + w) * kDecCh + c] +
-                     G(lay.dvw)[p * kDecCh + c];
-        int32_t cv[4];
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = rb + k * kWave + lane;
+            ent[k] = e < L ? list[e] : Entry(0);
+        }
+        TileRange tr;
+        if (!tile_range(tile_first, tile, nt, P, tr)) {
+            if (tid == 0) raise_error(ar.error, kErrInternal);
+            return;
+        }
+        __syncthreads();   // the previous tile is done with S
+        if (tid < kTile / 32) S.bm[tid] = 0u;
+        __syncthreads();
+        const bool carried = stage_tile(S, regions, t0, tr);
+        for (int k = tid; k < tr.nr && k < kStage; k += kBlock)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cv[q] = G(lay.cv)[p * 4 + q];
-        const TreeDesc T = G(a.trees)[R.tree];
-        const bool finest = R.meta & kMetaChildFinest;
-        const int32_t pi = (int32_t)(R.ij & 0xFFFFu), pj = (int32_t)(R.ij >> 16);
-        int64_t ri = pre[0], start = pre[1], ci = cells_base + pre[2];
+            for (int q = 0; q < 4; ++q) S.dst[k][q] = dsti[(int64_t)(tr.r0 + k) * 4 + q];
+        __syncthreads();
+
+        int open = starts_before(S.bm, wave, lane);
+        int32_t run[4];
+        {
+            const bool first_carried = open == 0 && carried;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (cv[q] <= T.threshold) continue;
-            const int32_t e = (q == 0 || q == 3) ? 1 : 0;
-            const int32_t n = (q <= 1) ? 1 : 0;
-            const int32_t ci_ = 2 * pi + e, cj = 2 * pj + n;
-            const int64_t off = 4 * R.start + (int64_t)q * R.len;   // the child's list in this level's output
-            if (finest) {
-                if (ci >= ar.cells_cap) {
-                    raise_error(ar.error, kErrArena);
-                    continue;
-                }
-                Cell c;
-                c.i = ci_;
-                c.j = cj;
-                c.votes = cv[q];
-                c.pass = T.pass;
-                c.key = key_of(ci_, cj, lc);
-                c.member_off = a.keep_members ? off : -1;
-                G(ar.cells)[ci++] = c;
+            for (int q = 0; q < 4; ++q)
+                run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? tpre[tile * 4 + q] : 0);
+        }
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = rb + k * kWave + lane;
+            const uint64_t W = row_word(S.bm, wave * kRows + k);
+            const uint64_t le = W & ((2ull << lane) - 1);
+            const bool seg0 = le == 0;
+            const int local = std::min(open + (int)__popcll(le), tr.nr - 1);
+            const int p = seg0 ? 0 : 63 - __builtin_clzll(le);   // first lane of this lane's region in the row
+            uint32_t ij, meta;
+            region_fields(S.ij, S.meta, regions, tr.r0, local, ij, meta);
+            uint64_t cm[4];
+            child_masks<kVariant, CT>(e < L, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
+            uint32_t m[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) m[q] = lanes_below(cm[q]);
+            const uint32_t packed = m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
+            const uint32_t at_p = (uint32_t)__shfl((int)packed, p, kWave);
+            const bool finest = meta & kMetaChildFinest;
+            Entry* const out = finest ? members : nlist;
+            const int64_t cap = finest ? mem_end : L2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!((cm[q] >> lane) & 1u)) continue;
+                const int64_t d = local < kStage ? S.dst[local][q] : dsti[(int64_t)(tr.r0 + local) * 4 + q];
+                if (d < 0) continue;
+                const int64_t pos =
+                    d + (int64_t)m[q] - (int64_t)((at_p >> (8 * q)) & 255u) + (seg0 ? run[q] : 0);
+                if (pos < cap) out[pos] = ent[k];
+                else bad = true;
+            }
+            if (W) {
+                open += (int)__popcll(W);
+                const uint64_t from = ~bits_below(63 - __builtin_clzll(W));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & from);
             } else {
-                if (ri >= nxt.regions_cap) {
-                    raise_error(ar.error, kErrInternal);
-                    continue;
-                }
-                Region C;
-                C.start = start;
-                C.in_base = off - start;
-                C.ij = (uint32_t)ci_ | ((uint32_t)cj << 16);
-                C.len = cv[q];
-                C.tree = R.tree;
-                C.meta = (R.meta & ~kMetaChildFinest) | (lc + 1 == T.dmax ? kMetaChildFinest : 0u);
-                G(nxt.regions)[ri] = C;
-                // next-level tiles whose first entry falls inside this region
-                for (int64_t t = cdiv(start, kTile); t * kTile < start + cv[q]; ++t)
-                    if (t < nxt.tile_cap) G(nxt.tile_first)[t] = (int32_t)ri;
-                ++ri;
-                start += cv[q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q]);
             }
         }
-        // the first parent of each tree records where its tree's sums begin
-        if (p == 0 || G(lay.regions)[p - 1].tree != R.tree) {
-            int64_t* r = G(ar.rec + ((int64_t)R.tree * kMaxLevels + l) * kRecCh);
-            r[0] = p;
-            r[1] = R.start;
-            r[2] = pre[0];
-            r[3] = pre[1];
-            r[4] = pre[2];
-            r[5] = pre[3];
-        }
+        if (__any(bad) && lane == 0) raise_error(ar.error, kErrInternal);
     }
 }
 
@@ -735,8 +1008,12 @@ __global__ void k_pack_points(const int32_t* x, const int32_t* y, int64_t n, int
     if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) raise_error(error, kErrPointRange | kErrInternal);
 }
 
+// Root setup: level 0 holds one region per tree (the whole parameter space;
+// every line crosses it, code 0011) whose list is the tree's points in
+// input order.
+template <typename Entry>
 __global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
-                        int32_t dmax)
+                        int32_t dmax, const uint32_t* xy)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -750,28 +1027,33 @@ __global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_po
         in.votes = 0;
         in.cells = 0;
         in.cells_base = 0;
+        in.mem = 0;
+        in.mem_base = 0;
         if (n_points >= 0) ar.scalar[0] = E;
     }
     if (g < n_trees) trees[g].n_points = E;
     if (P0 == 0) return;
-    const LevelLayout lay = level_layout(ar.half[0], 0, 0, 0, P0, L0, n_trees, ar.entry_bytes);
-    if (lay.end > ar.half_cap) {
+    const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
+    if (hl.end > ar.half_cap || work_layout(ar.work, P0, L0).end > ar.work_cap) {
         if (g == 0) raise_error(ar.error, kErrArena);
         return;
     }
     for (int64_t t = g; t < P0; t += stride) {
-        const TreeDesc T = trees[t];
+        const int32_t pass = trees[t].pass, s_log2 = trees[t].s_log2, td = trees[t].dmax;
         Region R;
         R.start = t * E;
-        R.in_base = T.xy_base - t * E;   // root lists are the point array itself
         R.ij = 0;
         R.len = (int32_t)E;
         R.tree = (int32_t)t;
-        R.meta = (T.pass ? kMetaPass : 0u) | ((uint32_t)T.s_log2 << kMetaSlogShift) |
-                 (T.dmax == 1 ? kMetaChildFinest : 0u);
-        lay.regions[t] = R;
+        R.meta = (pass ? kMetaPass : 0u) | ((uint32_t)s_log2 << kMetaSlogShift) | (td == 1 ? kMetaChildFinest : 0u);
+        hl.regions[t] = R;
     }
-    for (int64_t k = g; k < cdiv(L0, kTile); k += stride) lay.tile_first[k] = (int32_t)((k * kTile) / E);
+    for (int64_t k = g; k < cdiv(L0, kTile); k += stride) hl.tile_first[k] = (int32_t)((k * kTile) / E);
+    Entry* const list = static_cast<Entry*>(hl.list);
+    for (int64_t k = g; k < L0; k += stride) {
+        const int64_t t = k / E;
+        list[k] = EntryOps<Entry>::root(xy + trees[t].xy_base, k - t * E);
+    }
 }
 
 // Point ids of the voters of detected cells, one wavefront per cell.  A
@@ -820,6 +1102,23 @@ int grid_for(int64_t n, int per_block, int max_grid = 4096)
     return (int)g;
 }
 
+// The level kernels in their three forms: code variant with 32-bit or
+// 64-bit compares, circle variant; entries of 4 or 8 bytes.
+#define HH_LEVEL_LAUNCH(kernel)                                                                  \
+    do {                                                                                         \
+        const bool ids = a.ar.entry_bytes == 8;                                                  \
+        if (variant == 1) {                                                                      \
+            if (ids) kernel<uint64_t, 1, int64_t><<<grid, kBlock, 0, s>>>(a);                    \
+            else kernel<uint32_t, 1, int64_t><<<grid, kBlock, 0, s>>>(a);                        \
+        } else if (wide) {                                                                       \
+            if (ids) kernel<uint64_t, 0, int64_t><<<grid, kBlock, 0, s>>>(a);                    \
+            else kernel<uint32_t, 0, int64_t><<<grid, kBlock, 0, s>>>(a);                        \
+        } else {                                                                                 \
+            if (ids) kernel<uint64_t, 0, int32_t><<<grid, kBlock, 0, s>>>(a);                    \
+            else kernel<uint32_t, 0, int32_t><<<grid, kBlock, 0, s>>>(a);                        \
+        }                                                                                        \
+    } while (0)
+
 }  // namespace
 
 hipError_t launch_clear(const Arena& ar, int64_t n_rec, hipStream_t s)
@@ -847,37 +1146,36 @@ hipError_t launch_extract(const ExtractArgs& a, hipStream_t s)
 }
 
 hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
-                        int32_t dmax, int64_t work_bound, hipStream_t s)
+                        int32_t dmax, const uint32_t* xy, int grid, hipStream_t s)
 {
-    k_begin<<<grid_for(work_bound, kBlock, 1024), kBlock, 0, s>>>(ar, trees, n_trees, n_points, threshold, dmax);
+    if (ar.entry_bytes == 8)
+        k_begin<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, n_trees, n_points, threshold, dmax, xy);
+    else
+        k_begin<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, n_trees, n_points, threshold, dmax, xy);
     return hipGetLastError();
 }
 
-hipError_t launch_vote(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
+hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
 {
-    const bool ids = a.ar.entry_bytes == 8;
-    if (variant == 1) {
-        if (ids) k_vote<uint64_t, 1, int64_t><<<grid, kBlock, 0, s>>>(a);
-        else k_vote<uint32_t, 1, int64_t><<<grid, kBlock, 0, s>>>(a);
-    } else if (wide) {
-        if (ids) k_vote<uint64_t, 0, int64_t><<<grid, kBlock, 0, s>>>(a);
-        else k_vote<uint32_t, 0, int64_t><<<grid, kBlock, 0, s>>>(a);
-    } else {
-        if (ids) k_vote<uint64_t, 0, int32_t><<<grid, kBlock, 0, s>>>(a);
-        else k_vote<uint32_t, 0, int32_t><<<grid, kBlock, 0, s>>>(a);
-    }
+    HH_LEVEL_LAUNCH(k_count);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const LevelArgs& a, hipStream_t s)
+hipError_t launch_decide(const LevelArgs& a, int grid, hipStream_t s)
 {
-    k_scan<<<1, kScanThreads, 0, s>>>(a);
+    k_decide<<<std::min(grid, kRangeGrid), kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s)
 {
-    k_emit<<<grid, kBlock, 0, s>>>(a);
+    k_emit<<<std::min(grid, kRangeGrid), kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
+{
+    HH_LEVEL_LAUNCH(k_write);
     return hipGetLastError();
 }
 

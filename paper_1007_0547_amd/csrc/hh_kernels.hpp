@@ -14,9 +14,7 @@ struct LevelArgs {
     const TreeDesc* trees;
     const uint32_t* xy;        // packed edge points
     int32_t level;             // l: the parents' level; children are at l + 1
-    int32_t write_out;         // 0: count only (the finest level without voter lists)
-    int32_t keep_members;      // 0: detected cells get member_off = -1
-    int32_t pad;
+    int32_t keep_members;      // 0: detected cells get member_off = -1 and keep no voters
 };
 
 struct ExtractArgs {
@@ -39,15 +37,20 @@ hipError_t launch_pack_points(const int32_t* x, const int32_t* y, int64_t n, int
 // Edge staging in three launches: edge pixels per tile, their exclusive
 // prefix, then the row-major compaction.
 hipError_t launch_extract(const ExtractArgs& a, hipStream_t s);
-// Root setup: level-0 sizes, root regions and tile map.  n_points < 0 takes
-// the edge count from ar.scalar[0] (left there by the edge staging).
-hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64_t n_points,
-                        int32_t threshold, int32_t dmax, int64_t work_bound, hipStream_t s);
-hipError_t launch_vote(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
-hipError_t launch_scan(const LevelArgs& a, hipStream_t s);
+// Root setup: level-0 sizes, root regions, tile map and root lists.
+// n_points < 0 takes the edge count from ar.scalar[0] (left there by the
+// edge staging).
+hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
+                        int32_t dmax, const uint32_t* xy, int grid, hipStream_t s);
+// One level: child-vote counts per tile, per-region totals and decisions,
+// the next level's tables, then the compaction of the voters of the kept
+// children (skipped by the host at the finest level without members).
+hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
+hipError_t launch_decide(const LevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
 // Point ids of the voters of detected cells (see k_member_ids): into the
-// entry buffer's layout (dst_off == nullptr) or compacted at dst_off[c].
+// member buffer's layout (dst_off == nullptr) or compacted at dst_off[c].
 hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, const void* src,
                              int entry_bytes, const uint32_t* xy, int64_t n_points, int32_t* dst, hipStream_t s);
 hipError_t launch_iota(int32_t* dst, int64_t n, hipStream_t s);

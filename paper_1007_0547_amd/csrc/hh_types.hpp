@@ -8,25 +8,26 @@
 
 namespace hh {
 
-constexpr int kWave = 64;                 // CDNA wavefront width
-constexpr int kBlock = 256;               // threads per workgroup (4 wavefronts)
+constexpr int kWave = 64;                   // CDNA wavefront width
+constexpr int kBlock = 256;                 // threads per workgroup (4 wavefronts)
 constexpr int kWaves = kBlock / kWave;
-constexpr int kEpt = 8;                   // list entries per lane in the vote kernel
-constexpr int kWaveSpan = kWave * kEpt;   // 512 consecutive entries per wavefront
-constexpr int kTile = kBlock * kEpt;      // 2048 entries per vote tile
-constexpr int kStage = 128;               // regions of a tile whose data is staged in LDS
-constexpr int kPixPerThread = 16;         // image bytes per lane in edge staging
+constexpr int kRows = 8;                    // 64-entry rows per wavefront in a tile
+constexpr int kTileRows = kWaves * kRows;   // 32 rows
+constexpr int kTile = kTileRows * kWave;    // 2048 list entries per tile
+constexpr int kStage = 256;                 // regions of a tile whose fields are staged in LDS
+constexpr int kPixPerThread = 16;           // image bytes per lane in edge staging
 constexpr int kPixTile = kBlock * kPixPerThread;
-constexpr int kMaxLevels = 16;            // depth <= 15
-constexpr int kNumStats = 6;              // evaluated, votes, split, detected, code_tests, entries
-constexpr int kDecCh = 4;                 // decision channels: n_next, len_next, cells, votes
-constexpr int kRecCh = 6;                 // tree record: p, start, then the decision prefixes
+constexpr int kMaxLevels = 16;              // depth <= 15
+constexpr int kNumStats = 6;                // evaluated, votes, split, detected, code_tests, entries
+constexpr int kAggCh = 5;                   // decision sums: next regions, next entries, cells, member entries, votes
+constexpr int kRecCh = 6;                   // tree record: p, start, then the decision prefixes
+constexpr int kLongSpan = 8;                // regions spanning more tiles are summed by a whole workgroup
+constexpr int kRangeGrid = 512;             // region ranges of the split-decision launches
 
 // Error bits set by kernels (the host reports them after the call).
-constexpr uint32_t kErrLookback = 1u;     // a bounded wait timed out
-constexpr uint32_t kErrPointRange = 2u;   // an input point lies outside [0,W)x[0,H)
-constexpr uint32_t kErrInternal = 4u;     // an index failed a range check
-constexpr uint32_t kErrArena = 8u;        // a level did not fit its arena; rerun larger
+constexpr uint32_t kErrPointRange = 2u;     // an input point lies outside [0,W)x[0,H)
+constexpr uint32_t kErrInternal = 4u;       // an index failed a range check
+constexpr uint32_t kErrArena = 8u;          // a level did not fit its arena; rerun larger
 constexpr uint32_t kErrStop = kErrArena | kErrInternal;   // later kernels do nothing
 
 // Edge points are stored packed: x in bits 0..15, y in bits 16..31, so the
@@ -46,15 +47,14 @@ struct TreeDesc {
 };
 
 // Region.meta bits
-constexpr uint32_t kMetaPass = 1u;            // pass 1: axes swapped
-constexpr int kMetaSlogShift = 1;             // s_log2 in bits 1..4
+constexpr uint32_t kMetaPass = 1u;               // pass 1: axes swapped
+constexpr int kMetaSlogShift = 1;                // s_log2 in bits 1..4
 constexpr uint32_t kMetaChildFinest = 1u << 5;   // the region's children are at the finest level
 
-// A region that split: its voters form one list of the level.
+// A region that split at its level.  Its voters are entries
+// [start, start + len) of the level's list.
 struct Region {
-    int64_t start;      // first flat entry index of its list within the level
-    int64_t in_base;    // entry e of the level lives at list[in_base + e]; for the
-                        // root lists (level 0) in_base + e indexes the point array
+    int64_t start;
     uint32_t ij;        // i | j << 16, indices at its level
     int32_t len;        // votes = list length
     int32_t tree;
@@ -68,7 +68,9 @@ struct LevelInfo {
     int64_t votes;      // summed votes of their children
     int64_t cells;      // cells detected at this level
     int64_t cells_base; // cells detected at shallower levels
-    int64_t pad[3];
+    int64_t mem;        // voter entries of the cells detected at this level
+    int64_t mem_base;   // voter entries of the cells detected at shallower levels
+    int64_t pad;
 };
 
 // A detected cell; layout equal to the public hh_cell.
@@ -83,61 +85,76 @@ struct Cell {
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t align256(int64_t bytes) { return (bytes + 255) & ~(int64_t)255; }
 
-// Buffers of level l inside its arena half (l & 1).  regions / tile_first
-// are written by the split decision of level l-1 (or the root setup) and
-// sized from level l-1; the rest is written by the launches of level l.
-//   out    children's voter lists: child q of the parent with flat start s
-//          and length n occupies out[4 s + q n, 4 s + q n + votes)
-//   cv     [P][4] child votes
-//   dvw    [P][4] decision values of the parents before it whose list ends in
-//          the same wavefront span (exclusive prefix)
-//   wpre   [tiles][kWaves][4] exclusive prefix of the decision values of the
-//          wavefront spans of a tile
-//   vts    [tiles][4] decision totals per tile;  vtp: their exclusive prefix
-struct LevelLayout {
+// A level's data inside its arena half (l & 1): the region table and the
+// tile map, written by the previous level's split decision (or the root
+// setup), then the level's list, written by the previous level's
+// compaction.  tile_first[t] is the region holding entry t * kTile.
+struct HalfLayout {
     Region* regions;
-    int64_t regions_cap;
     int32_t* tile_first;
-    int64_t tile_cap;
-    void* out;          // 4 L entries of entry_bytes
-    int32_t* cv;
-    int32_t* dvw;
-    int32_t* wpre;
-    int32_t* vts;
-    int64_t* vtp;
+    void* list;
     int64_t end;        // bytes used from the half's start
 };
 
-__host__ __device__ inline LevelLayout level_layout(char* half, int level, int64_t P_prev, int64_t L_prev,
-                                                    int64_t P, int64_t L, int32_t n_trees, int entry_bytes)
+__host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t L, int entry_bytes)
 {
-    LevelLayout y;
-    y.regions_cap = level == 0 ? n_trees : 4 * P_prev;
-    y.tile_cap = (level == 0 ? cdiv(L, kTile) : cdiv(4 * L_prev, kTile)) + 1;
-    const int64_t nt = cdiv(L, kTile);
+    HalfLayout y;
     int64_t off = 0;
     y.regions = reinterpret_cast<Region*>(half + off);
-    off += align256(y.regions_cap * (int64_t)sizeof(Region));
+    off += align256(P * (int64_t)sizeof(Region));
     y.tile_first = reinterpret_cast<int32_t*>(half + off);
-    off += align256(y.tile_cap * 4);
-    y.out = half + off;
-    off += align256(4 * L * entry_bytes);
-    y.cv = reinterpret_cast<int32_t*>(half + off);
-    off += align256(4 * P * 4);
-    y.dvw = reinterpret_cast<int32_t*>(half + off);
-    off += align256(4 * P * 4);
-    y.wpre = reinterpret_cast<int32_t*>(half + off);
-    off += align256(nt * kWaves * kDecCh * 4);
-    y.vts = reinterpret_cast<int32_t*>(half + off);
-    off += align256(nt * kDecCh * 4);
-    y.vtp = reinterpret_cast<int64_t*>(half + off);
-    off += align256(nt * kDecCh * 8);
+    off += align256((cdiv(L, kTile) + 1) * 4);
+    y.list = half + off;
+    off += align256(L * entry_bytes);
     y.end = off;
     return y;
 }
 
-// All device memory of one call: a fixed part and two level halves used in
-// turn.
+// Per-level scratch, reused by every level.
+//   head  [P][4]  child votes counted in the tile where the region starts
+//   cv    [P][4]  child votes
+//   dst   [P][4]  where the child's voters go (next list or member buffer), -1: dropped
+//   tcar  [nt][4] child votes of the region carried into tile t from earlier tiles
+//   tpre  [nt][4] child votes of that region before tile t
+//   woff  [nt][kWaves][4] child votes of the region open at each wavefront's
+//                 first entry, counted from its first entry in the tile
+//   agg   [kRangeGrid][kAggCh] decision sums per range of regions
+struct WorkLayout {
+    int32_t* head;
+    int32_t* cv;
+    int64_t* dst;
+    int32_t* tcar;
+    int32_t* tpre;
+    int32_t* woff;
+    int64_t* agg;
+    int64_t end;
+};
+
+__host__ __device__ inline WorkLayout work_layout(char* work, int64_t P, int64_t L)
+{
+    WorkLayout w;
+    const int64_t nt = cdiv(L, kTile);
+    int64_t off = 0;
+    w.head = reinterpret_cast<int32_t*>(work + off);
+    off += align256(P * 16);
+    w.cv = reinterpret_cast<int32_t*>(work + off);
+    off += align256(P * 16);
+    w.dst = reinterpret_cast<int64_t*>(work + off);
+    off += align256(P * 32);
+    w.tcar = reinterpret_cast<int32_t*>(work + off);
+    off += align256(nt * 16);
+    w.tpre = reinterpret_cast<int32_t*>(work + off);
+    off += align256(nt * 16);
+    w.woff = reinterpret_cast<int32_t*>(work + off);
+    off += align256(nt * kWaves * 16);
+    w.agg = reinterpret_cast<int64_t*>(work + off);
+    off += align256((int64_t)kRangeGrid * kAggCh * 8);
+    w.end = off;
+    return w;
+}
+
+// All device memory of one call: a fixed part, the member buffer, two level
+// halves used in turn and the per-level scratch.
 struct Arena {
     LevelInfo* info;       // [kMaxLevels + 1]
     int64_t* rec;          // [n_trees][kMaxLevels][kRecCh] tree boundary records (-1: none)
@@ -145,8 +162,12 @@ struct Arena {
     int64_t* scalar;       // [8] scratch (edge count, ...)
     Cell* cells;
     int64_t cells_cap;
+    void* members;         // voters of the detected cells, cell after cell
+    int64_t mem_cap;       // entries
     char* half[2];
     int64_t half_cap;      // bytes per half
+    char* work;
+    int64_t work_cap;      // bytes
     int32_t n_trees;
     int32_t entry_bytes;   // 4: packed points; 8: (id, packed point)
 };
