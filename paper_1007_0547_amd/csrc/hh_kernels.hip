@@ -101,11 +101,14 @@ template <> struct EntryOps<uint64_t> {   // point id << 32 | packed edge point
 // M_c = 2 ic - 2^lc and B_r = -S 2^lc + 3 S jc.  Corner (c, r) is below the
 // line b = v - u m iff B_r < t_c with t_c = v 2^lc - u M_c (a corner on the
 // line is above); consecutive columns differ by 2 in M, so
-// t_{c+1} = t_c - 2u.  The nine compares become nine lane masks b_cr, and a
-// child's code (NE, NW, SW, SE corner bits) votes iff it is neither 0000 nor
-// 1111: some corner below and not all of them.
+// t_{c+1} = t_c - 2u.  Since u >= 0, t_c does not grow with c while B_r
+// grows with r: a corner below the line has every corner west or south of it
+// below too.  So a child's code (NE, NW, SW, SE corner bits) is some-but-not-
+// all below -- neither 0000 nor 1111, the vote rule -- exactly when its SW
+// corner is below and its NE corner is not; the other two bits never decide.
+// Seven of the nine corner compares are needed, each one lane mask b_cr.
 template <typename CT>
-__device__ inline void code_masks(bool valid, int32_t u, int32_t v, int32_t pi, int32_t pj, int lc, int s_log2,
+__device__ inline void code_masks(uint64_t vm, int32_t u, int32_t v, int32_t pi, int32_t pj, int lc, int s_log2,
                                   uint64_t (&cm)[4])
 {
     const CT S = (CT)1 << s_log2;
@@ -118,17 +121,14 @@ __device__ inline void code_masks(bool valid, int32_t u, int32_t v, int32_t pi, 
     const CT B0 = (CT)6 * S * (CT)pj - (S << lc);
     const CT B1 = B0 + (CT)3 * S;
     const CT B2 = B1 + (CT)3 * S;
-    const uint64_t b00 = __ballot(valid && B0 < t0), b01 = __ballot(valid && B1 < t0),
-                   b02 = __ballot(valid && B2 < t0);
-    const uint64_t b10 = __ballot(valid && B0 < t1), b11 = __ballot(valid && B1 < t1),
-                   b12 = __ballot(valid && B2 < t1);
-    const uint64_t b20 = __ballot(valid && B0 < t2), b21 = __ballot(valid && B1 < t2),
-                   b22 = __ballot(valid && B2 < t2);
-    // child at (east e, north n): NE = (e+1, n+1), NW = (e, n+1), SW = (e, n), SE = (e+1, n)
-    cm[0] = (b22 | b12 | b11 | b21) & ~(b22 & b12 & b11 & b21);   // NE child, e = 1, n = 1
-    cm[1] = (b12 | b02 | b01 | b11) & ~(b12 & b02 & b01 & b11);   // NW child, e = 0, n = 1
-    cm[2] = (b11 | b01 | b00 | b10) & ~(b11 & b01 & b00 & b10);   // SW child, e = 0, n = 0
-    cm[3] = (b21 | b11 | b10 | b20) & ~(b21 & b11 & b10 & b20);   // SE child, e = 1, n = 0
+    const uint64_t b00 = __ballot(B0 < t0), b01 = __ballot(B1 < t0);
+    const uint64_t b10 = __ballot(B0 < t1), b11 = __ballot(B1 < t1), b12 = __ballot(B2 < t1);
+    const uint64_t b21 = __ballot(B1 < t2), b22 = __ballot(B2 < t2);
+    // child at (east e, north n): SW corner (e, n), NE corner (e+1, n+1)
+    cm[0] = vm & b11 & ~b22;   // NE child, e = 1, n = 1
+    cm[1] = vm & b01 & ~b12;   // NW child, e = 0, n = 1
+    cm[2] = vm & b00 & ~b11;   // SW child, e = 0, n = 0
+    cm[3] = vm & b10 & ~b21;   // SE child, e = 1, n = 0
 }
 
 // Circumscribed-circle variant (comparison method of the paper's ref. [9]).
@@ -136,7 +136,7 @@ __device__ inline void code_masks(bool valid, int32_t u, int32_t v, int32_t pi, 
 // b = -S + 3S(2j+1)/2^(lc+1), in units where the cell is a unit square, the
 // line is within the circumradius iff D^2 <= 2 (9 S^2 + 4 u^2) with
 // D = 3S(2j+1) + 2u(2i+1) - (v + u + S) 2^(lc+1).
-__device__ inline void circle_masks(bool valid, int32_t u, int32_t v, int32_t pi, int32_t pj, int lc,
+__device__ inline void circle_masks(uint64_t vm, int32_t u, int32_t v, int32_t pi, int32_t pj, int lc,
                                     int s_log2, uint64_t (&cm)[4])
 {
     const int64_t S = (int64_t)1 << s_log2;
@@ -148,14 +148,14 @@ __device__ inline void circle_masks(bool valid, int32_t u, int32_t v, int32_t pi
     const int64_t c_e = c_w + 4 * U;                             // east = 1
     const int64_t rhs = 2 * (9 * S * S + 4 * U * U);
     const int64_t dNE = a_n + c_e, dNW = a_n + c_w, dSW = a_s + c_w, dSE = a_s + c_e;
-    cm[0] = __ballot(valid && dNE * dNE <= rhs);
-    cm[1] = __ballot(valid && dNW * dNW <= rhs);
-    cm[2] = __ballot(valid && dSW * dSW <= rhs);
-    cm[3] = __ballot(valid && dSE * dSE <= rhs);
+    cm[0] = vm & __ballot(dNE * dNE <= rhs);
+    cm[1] = vm & __ballot(dNW * dNW <= rhs);
+    cm[2] = vm & __ballot(dSW * dSW <= rhs);
+    cm[3] = vm & __ballot(dSE * dSE <= rhs);
 }
 
 template <int kVariant, typename CT>
-__device__ inline void child_masks(bool valid, uint32_t point, uint32_t meta, uint32_t ij, int lc,
+__device__ inline void child_masks(uint64_t vm, uint32_t point, uint32_t meta, uint32_t ij, int lc,
                                    uint64_t (&cm)[4])
 {
     const int32_t x = (int32_t)(point & 0xFFFFu), y = (int32_t)(point >> 16);
@@ -164,9 +164,9 @@ __device__ inline void child_masks(bool valid, uint32_t point, uint32_t meta, ui
     const int s_log2 = (int)((meta >> kMetaSlogShift) & 15u);
     const int32_t pi = (int32_t)(ij & 0xFFFFu), pj = (int32_t)(ij >> 16);
     if constexpr (kVariant == 0)
-        code_masks<CT>(valid, u, v, pi, pj, lc, s_log2, cm);
+        code_masks<CT>(vm, u, v, pi, pj, lc, s_log2, cm);
     else
-        circle_masks(valid, u, v, pi, pj, lc, s_log2, cm);
+        circle_masks(vm, u, v, pi, pj, lc, s_log2, cm);
 }
 
 __device__ inline int32_t wave_incl_scan32(int32_t x, int lane)
@@ -210,20 +210,47 @@ __device__ inline int32_t wave_sum32(int32_t x)
 // tile_first[t+1] (local indices 0 .. nr-1; local 0 holds the tile's first
 // entry).  In LDS the tile keeps a bitmap of the entries (other than the
 // first) that begin a region, so the local region of an entry is the number
-// of marked entries up to it, and a row's marks form one 64-bit word.
+// of marked entries up to it, and a row's marks form one 64-bit word.  A row
+// with no mark belongs entirely to the wavefront's open region, whose fields
+// the wavefront keeps in scalar registers; only rows with a mark look up
+// region fields per lane.  Region fields come from LDS when the tile has at
+// most kStage regions, otherwise from the region table (a separate
+// instantiation, so no load has to choose between the two at run time).
+// Each workgroup walks its tiles with the next tile's entries and bounds
+// already in flight.
 
-struct TileRange {
-    int r0, nr;
-    bool carried;   // local region 0 began in an earlier tile
+__device__ inline uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+template <typename Entry>
+__device__ inline void load_rows(const Entry* list, int64_t L, int64_t tile, int wave, int lane, Entry (&ent)[kRows])
+{
+    const int64_t rb = tile * kTile + (int64_t)wave * (kRows * kWave);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int64_t e = rb + k * kWave + lane;
+        ent[k] = e < L ? list[e] : Entry(0);
+    }
+}
+
+struct TileBounds {
+    int r0, r1;
 };
 
-__device__ inline bool tile_range(const int32_t* tile_first, int64_t tile, int64_t nt, int64_t P, TileRange& tr)
+__device__ inline TileBounds tile_bounds(const int32_t* tile_first, int64_t tile, int64_t nt, int64_t P)
 {
-    const int r0 = tile_first[tile];
-    const int r1 = tile + 1 < nt ? tile_first[tile + 1] : (int)(P - 1);
-    tr.r0 = r0;
-    tr.nr = r1 - r0 + 1;   // <= kTile + 1: every region holds at least one entry
-    return r0 >= 0 && r1 < P && tr.nr >= 1 && tr.nr <= kTile + 1;
+    TileBounds b{0, -1};
+    if (tile < nt) {
+        b.r0 = tile_first[tile];
+        b.r1 = tile + 1 < nt ? tile_first[tile + 1] : (int)(P - 1);
+    }
+    return b;
+}
+
+// <= kTile + 1 regions: every region holds at least one entry
+__device__ inline bool bounds_ok(const TileBounds& b, int64_t P)
+{
+    const int nr = b.r1 - b.r0 + 1;
+    return b.r0 >= 0 && b.r1 < P && nr >= 1 && nr <= kTile + 1;
 }
 
 __device__ inline uint64_t row_word(const uint32_t* bm, int row)
@@ -239,59 +266,142 @@ __device__ inline int starts_before(const uint32_t* bm, int wave, int lane)
     return __builtin_amdgcn_readfirstlane(wave_sum32(c));
 }
 
-__device__ inline void region_fields(const uint32_t* s_ij, const uint32_t* s_meta, const Region* regions, int r0,
-                                     int local, uint32_t& ij, uint32_t& meta)
-{
-    if (local < kStage) {
-        ij = s_ij[local];
-        meta = s_meta[local];
-    } else {
-        ij = regions[r0 + local].ij;
-        meta = regions[r0 + local].meta;
-    }
-}
-
-struct CountLds {
-    uint32_t bm[kTile / 32];
+// Staged fields of a tile's first kStage regions.
+struct StagedRegions {
     uint32_t ij[kStage];
     uint32_t meta[kStage];
-    int32_t wfirst[kWaves][4];   // per wavefront: votes of the region open at its first entry (up to its close)
-    int32_t wlast[kWaves][4];    //   votes of the region open at its end, from that region's start
-    int32_t wlocal[kWaves];      //   local index of that region
-    int32_t wclosed[kWaves];     //   whether the region open at its first entry ended inside it
 };
 
-struct WriteLds {
-    uint32_t bm[kTile / 32];
-    uint32_t ij[kStage];
-    uint32_t meta[kStage];
-    int64_t dst[kStage][4];
-};
-
-template <typename Lds>
-__device__ inline bool stage_tile(Lds& S, const Region* regions, int64_t t0, const TileRange& tr)
-{
-    for (int k = threadIdx.x; k < tr.nr; k += kBlock) {
-        const Region R = regions[tr.r0 + k];
-        const int64_t rel = R.start - t0;
-        if (rel >= 1 && rel < kTile) atomicOr(&S.bm[rel >> 5], 1u << (rel & 31));
-        if (k < kStage) {
-            S.ij[k] = R.ij;
-            S.meta[k] = R.meta;
+// Fields of local region `local`: from LDS (kStaged) or the region table.
+template <bool kStaged>
+struct RegionSource {
+    const StagedRegions& S;
+    const Region* regions;
+    int r0;
+    __device__ void fields(int local, uint32_t& ij, uint32_t& meta) const
+    {
+        if constexpr (kStaged) {
+            ij = S.ij[local];
+            meta = S.meta[local];
+        } else {
+            ij = regions[r0 + local].ij;
+            meta = regions[r0 + local].meta;
         }
     }
-    return regions[tr.r0].start < t0;
+};
+
+// Region marks and staged fields of one tile; returns whether local region 0
+// began in an earlier tile.
+__device__ inline bool stage_tile(uint32_t* bm, StagedRegions& sr, const Region* regions, int64_t t0,
+                                  const TileBounds& tb)
+{
+    const int nr = tb.r1 - tb.r0 + 1;
+    for (int k = threadIdx.x; k < nr; k += kBlock) {
+        const Region R = regions[tb.r0 + k];
+        const int64_t rel = R.start - t0;
+        if (rel >= 1 && rel < kTile) atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+        if (k < kStage) {
+            sr.ij[k] = R.ij;
+            sr.meta[k] = R.meta;
+        }
+    }
+    return regions[tb.r0].start < t0;
 }
 
 // ------------------------------------------------------------------ k_count
 //
 // Child-vote counts of every region piece of a tile.  A wavefront walks its
 // rows keeping the counts of the region open at the current entry in scalar
-// registers; a region that begins and ends inside the wavefront is written
-// out at once (head), the rest is combined across the four wavefronts at the
-// end of the tile: head for a region that begins in the tile, tcar for the
-// region carried in from the previous tile, and woff, the votes of each
-// wavefront's first region counted before that wavefront inside the tile.
+// registers.  A region that begins and ends inside one tile has its total
+// stored in cv at once (by the wavefront where it ends, or by the tile's
+// combine step when it crosses wavefronts); the pieces of a region that
+// crosses tiles are added to cv atomically, and the tile keeps for the
+// compaction pass: head (the piece in the region's first tile), tcar (the
+// piece of the region carried in from earlier tiles) and woff (the votes of
+// each wavefront's first region counted before that wavefront in the tile).
+
+struct CountLds {
+    uint32_t bm[kTile / 32];
+    StagedRegions sr;
+    int32_t wfirst[kWaves][4];   // per wavefront: votes of the region open at its first entry (up to its close)
+    int32_t wlast[kWaves][4];    //   votes of the region open at its end, from that region's start
+    int32_t wlocal[kWaves];      //   local index of that region
+    int32_t wclosed[kWaves];     //   whether the region open at its first entry ended inside it
+};
+
+struct WaveCount {
+    int open;          // local index of the open region
+    bool closed;       // the first region ended inside the wavefront
+    int32_t run[4];    // votes of the open region counted inside the wavefront
+    int32_t first[4];  // votes of the first region inside the wavefront
+};
+
+template <typename Entry, int kVariant, typename CT, bool kStaged>
+__device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, const uint32_t* bm, const Entry (&ent)[kRows],
+                                           int64_t rb, int64_t L, int lc, int wave, int lane, int nr, int32_t* cv,
+                                           WaveCount& wc)
+{
+    int open = starts_before(bm, wave, lane);
+    uint32_t o_ij, o_meta;
+    src.fields(std::min(open, nr - 1), o_ij, o_meta);
+    o_ij = rfl(o_ij);
+    o_meta = rfl(o_meta);
+    bool open_here = false;   // the open region began inside this wavefront
+    bool closed = false;
+    int32_t run[4] = {0, 0, 0, 0}, first[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const uint64_t vm = __ballot(rb + k * kWave + lane < L);
+        const uint64_t W = row_word(bm, wave * kRows + k);
+        uint64_t cm[4];
+        if (W == 0) {   // the whole row belongs to the open region
+            child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), o_meta, o_ij, lc, cm);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q]);
+            continue;
+        }
+        const uint64_t le = W & ((2ull << lane) - 1);
+        const int local = std::min(open + (int)__popcll(le), nr - 1);
+        uint32_t ij, meta;
+        src.fields(local, ij, meta);
+        child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
+        uint64_t rest = W;
+        int prev = 0;
+        while (rest) {   // regions that end inside this row
+            const int p = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const uint64_t seg = bits_below(p) & ~bits_below(prev);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & seg);
+            if (open_here) {   // began and ended in this wavefront: its total
+                if (lane < 4) cv[(int64_t)(src.r0 + open) * 4 + lane] = pick4(run, lane);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) first[q] = run[q];
+                closed = true;
+            }
+            ++open;
+            open_here = true;
+            prev = p;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) run[q] = 0;
+        }
+        const uint64_t tail = ~bits_below(prev);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
+        src.fields(std::min(open, nr - 1), o_ij, o_meta);
+        o_ij = rfl(o_ij);
+        o_meta = rfl(o_meta);
+    }
+    wc.open = open;
+    wc.closed = closed;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        wc.run[q] = run[q];
+        wc.first[q] = closed ? first[q] : run[q];
+    }
+}
+
 template <typename Entry, int kVariant, typename CT>
 __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
 {
@@ -314,79 +424,48 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
     const Entry* const list = G(static_cast<const Entry*>(hl.list));
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
+    int32_t* const cv = G(hl.cv);
     int32_t* const head = G(wl.head);
     int32_t* const tcar = G(wl.tcar);
     int32_t* const woff = G(wl.woff);
     const int64_t nt = cdiv(L, kTile);
+    int64_t tile = blockIdx.x;
+    if (tile >= nt) return;
 
     if (tid < kTile / 32) S.bm[tid] = 0u;
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    Entry ent[kRows];
+    load_rows(list, L, tile, wave, lane, ent);
+    TileBounds tb = tile_bounds(tile_first, tile, nt, P);
+    for (;;) {
+        const int64_t next = tile + gridDim.x;
+        Entry nent[kRows];
+        load_rows(list, L, next, wave, lane, nent);
+        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
+
         const int64_t t0 = tile * kTile;
         const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
-        Entry ent[kRows];
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t e = rb + k * kWave + lane;
-            ent[k] = e < L ? list[e] : Entry(0);
-        }
-        TileRange tr;
-        if (!tile_range(tile_first, tile, nt, P, tr)) {
+        if (!bounds_ok(tb, P)) {
             if (tid == 0) raise_error(ar.error, kErrInternal);
             return;
         }
+        const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
         __syncthreads();   // the previous tile is done with S (its bitmap is clear again)
-        const bool carried = stage_tile(S, regions, t0, tr);
+        const bool carried = stage_tile(S.bm, S.sr, regions, t0, tb);
         __syncthreads();
-
-        int open = starts_before(S.bm, wave, lane);   // local index of the open region
-        bool open_here = false;                       // it began inside this wavefront
-        bool closed = false;                          // the first region ended inside this wavefront
-        int32_t run[4] = {0, 0, 0, 0}, first[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t e = rb + k * kWave + lane;
-            const uint64_t W = row_word(S.bm, wave * kRows + k);
-            const uint64_t le = W & ((2ull << lane) - 1);
-            const int local = std::min(open + (int)__popcll(le), tr.nr - 1);
-            uint32_t ij, meta;
-            region_fields(S.ij, S.meta, regions, tr.r0, local, ij, meta);
-            uint64_t cm[4];
-            child_masks<kVariant, CT>(e < L, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
-            uint64_t rest = W;
-            int prev = 0;
-            while (rest) {   // regions that end inside this row
-                const int p = __builtin_ctzll(rest);
-                rest &= rest - 1;
-                const uint64_t seg = bits_below(p) & ~bits_below(prev);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & seg);
-                if (open_here) {
-                    if (lane < 4 && tr.r0 + open < P) head[(int64_t)(tr.r0 + open) * 4 + lane] = pick4(run, lane);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) first[q] = run[q];
-                    closed = true;
-                }
-                ++open;
-                open_here = true;
-                prev = p;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) run[q] = 0;
-            }
-            const uint64_t tail = ~bits_below(prev);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
-        }
-        if (!closed)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) first[q] = run[q];
+        WaveCount wc;
+        if (nr <= kStage)
+            count_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0}, S.bm, ent, rb, L, lc, wave,
+                                                  lane, nr, cv, wc);
+        else
+            count_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0}, S.bm, ent, rb, L, lc,
+                                                   wave, lane, nr, cv, wc);
         if (lane < 4) {
-            S.wfirst[wave][lane] = pick4(first, lane);
-            S.wlast[wave][lane] = pick4(run, lane);
+            S.wfirst[wave][lane] = pick4(wc.first, lane);
+            S.wlast[wave][lane] = pick4(wc.run, lane);
         }
         if (lane == 0) {
-            S.wlocal[wave] = open;
-            S.wclosed[wave] = closed ? 1 : 0;
+            S.wlocal[wave] = wc.open;
+            S.wclosed[wave] = wc.closed ? 1 : 0;
         }
         __syncthreads();
         if (tid < 4) {   // one thread per child slot
@@ -398,20 +477,29 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
                 woff[(tile * kWaves + w) * 4 + q] = cnt;
                 cnt += S.wfirst[w][q];
                 if (S.wclosed[w]) {
-                    if (cur_carried) tcar[tile * 4 + q] = cnt;
-                    else if (tr.r0 + cur < P) head[(int64_t)(tr.r0 + cur) * 4 + q] = cnt;
+                    if (cur_carried) {   // the last piece of a region from earlier tiles
+                        tcar[tile * 4 + q] = cnt;
+                        atomicAdd(&cv[(int64_t)r0 * 4 + q], cnt);
+                    } else {
+                        cv[(int64_t)(r0 + cur) * 4 + q] = cnt;   // began and ended in this tile
+                    }
                     cur = S.wlocal[w];
                     cur_carried = false;
                     cnt = S.wlast[w][q];
                 }
             }
+            // the region open at the tile's end (it may continue in the next tile)
             if (cur_carried) tcar[tile * 4 + q] = cnt;
-            else {
-                if (tr.r0 + cur < P) head[(int64_t)(tr.r0 + cur) * 4 + q] = cnt;
-                if (!carried) tcar[tile * 4 + q] = 0;
-            }
+            else head[(int64_t)(r0 + cur) * 4 + q] = cnt;
+            atomicAdd(&cv[(int64_t)(r0 + cur) * 4 + q], cnt);
         }
         if (tid < kTile / 32) S.bm[tid] = 0u;   // every wavefront has read the bitmap
+
+        if (next >= nt) break;
+        tile = next;
+        tb = ntb;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) ent[k] = nent[k];
     }
 }
 
@@ -449,34 +537,21 @@ __device__ inline void decision(const int32_t (&cv)[4], int32_t thr, bool finest
     }
 }
 
-__device__ inline void block_scan4(const int32_t (&v)[4], int32_t (&ex)[4], int32_t (&tot)[4], int32_t (*s)[4])
+__device__ inline void region_decision(const Region* regions, const int32_t* cvi, const TreeDesc* trees, int64_t r,
+                                       Region& R, int32_t (&cv)[4], int32_t& thr, int64_t (&dv)[kAggCh])
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    int32_t inc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) inc[q] = wave_incl_scan32(v[q], lane);
-    if (lane == kWave - 1)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) s[wave][q] = inc[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int32_t pre = 0, all = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wave) pre += s[w][q];
-            all += s[w][q];
-        }
-        ex[q] = pre + inc[q] - v[q];
-        tot[q] = all;
-    }
-    __syncthreads();
+    R = regions[r];
+    const int4 c = reinterpret_cast<const int4*>(cvi)[r];
+    cv[0] = c.x;
+    cv[1] = c.y;
+    cv[2] = c.z;
+    cv[3] = c.w;
+    thr = trees[R.tree].threshold;
+    decision(cv, thr, (R.meta & kMetaChildFinest) != 0, dv);
 }
 
 __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
 {
-    __shared__ int32_t s_long[kBlock];
-    __shared__ int32_t s_nlong;
-    __shared__ int32_t s_scan[kWaves][4];
     __shared__ int64_t s_red[kWaves][kAggCh];
     const Arena& ar = a.ar;
     const int tid = threadIdx.x;
@@ -490,10 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
     const WorkLayout wl = work_layout(ar.work, P, L);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;   // k_count raised the error
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
-    const int32_t* const head = G(static_cast<const int32_t*>(wl.head));
-    const int32_t* const tcar = G(static_cast<const int32_t*>(wl.tcar));
-    int32_t* const tpre = G(wl.tpre);
-    int32_t* const cvo = G(wl.cv);
+    const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
     const TreeDesc* const trees = G(a.trees);
     const int64_t nb = cdiv(P, kBlock);
 
@@ -501,70 +573,13 @@ __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
         int64_t b0, b1;
         range_of(nb, g, b0, b1);
         int64_t acc[kAggCh] = {0, 0, 0, 0, 0};
-        for (int64_t b = b0; b < b1; ++b) {
-            const int64_t r = b * kBlock + tid;
-            const bool valid = r < P;
-            Region R{};
-            int64_t ts = 0, te = 0;
-            int32_t tot[4] = {0, 0, 0, 0};
-            if (valid) {
-                R = regions[r];
-                ts = R.start / kTile;
-                te = (R.start + R.len - 1) / kTile;
-                if (R.len < 1 || R.start + R.len > L) {
-                    raise_error(ar.error, kErrInternal);
-                    te = ts;
-                }
+        for (int64_t r = b0 * kBlock + tid; r < std::min(P, b1 * kBlock); r += kBlock) {
+            Region R;
+            int32_t cv[4], thr;
+            int64_t dv[kAggCh];
+            region_decision(regions, cvi, trees, r, R, cv, thr, dv);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) tot[q] = head[r * 4 + q];
-            }
-            const bool is_long = valid && te - ts > kLongSpan;
-            if (valid && !is_long) {
-                for (int64_t t = ts + 1; t <= te; ++t)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        tpre[t * 4 + q] = tot[q];
-                        tot[q] += tcar[t * 4 + q];
-                    }
-            }
-            // regions over many tiles: the workgroup scans their tiles together
-            if (tid == 0) s_nlong = 0;
-            __syncthreads();
-            if (is_long) s_long[atomicAdd(&s_nlong, 1)] = tid;
-            __syncthreads();
-            const int nlong = s_nlong;
-            for (int k = 0; k < nlong; ++k) {
-                const int owner = s_long[k];
-                const int64_t rr = b * kBlock + owner;
-                const Region RR = regions[rr];
-                const int64_t ts2 = RR.start / kTile, te2 = (RR.start + RR.len - 1) / kTile;   // checked above
-                int32_t run[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) run[q] = head[rr * 4 + q];
-                for (int64_t c0 = ts2 + 1; c0 <= te2; c0 += kBlock) {
-                    const int64_t t = c0 + tid;
-                    int32_t v[4], ex[4], all[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) v[q] = t <= te2 ? tcar[t * 4 + q] : 0;
-                    block_scan4(v, ex, all, s_scan);
-                    if (t <= te2)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) tpre[t * 4 + q] = run[q] + ex[q];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) run[q] += all[q];
-                }
-                if (tid == owner)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) tot[q] = run[q];
-            }
-            if (valid) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cvo[r * 4 + q] = tot[q];
-                int64_t dv[kAggCh];
-                decision(tot, trees[R.tree].threshold, (R.meta & kMetaChildFinest) != 0, dv);
-#pragma unroll
-                for (int c = 0; c < kAggCh; ++c) acc[c] += dv[c];
-            }
+            for (int c = 0; c < kAggCh; ++c) acc[c] += dv[c];
         }
 #pragma unroll
         for (int c = 0; c < kAggCh; ++c) {
@@ -623,12 +638,15 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
     const int64_t* const agg = G(static_cast<const int64_t*>(wl.agg));
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
-    const int32_t* const cvi = G(static_cast<const int32_t*>(wl.cv));
+    const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
     int64_t* const dsto = G(wl.dst);
     const TreeDesc* const trees = G(a.trees);
     const int64_t nb = cdiv(P, kBlock);
 
     for (int g = blockIdx.x; g < kRangeGrid; g += gridDim.x) {
+        int64_t b0, b1;
+        range_of(nb, g, b0, b1);
+        if (b0 == b1 && g != 0) continue;   // nothing here, and the level totals are written by range 0
         // this range's offsets and the level totals
         int64_t pre[kAggCh], tot[kAggCh];
         {
@@ -678,9 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
         if (!fits) return;
         Region* const nreg = G(nx.regions);
         int32_t* const ntf = G(nx.tile_first);
+        int32_t* const ncv = G(nx.cv);
         const int64_t n_ntiles = cdiv(L2, kTile);
-        int64_t b0, b1;
-        range_of(nb, g, b0, b1);
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t r = b * kBlock + tid;
             const bool valid = r < P;
@@ -688,13 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
             int32_t cv[4] = {0, 0, 0, 0};
             int32_t thr = 0;
             int64_t dv[kAggCh] = {0, 0, 0, 0, 0};
-            if (valid) {
-                R = regions[r];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) cv[q] = cvi[r * 4 + q];
-                thr = trees[R.tree].threshold;
-                decision(cv, thr, (R.meta & kMetaChildFinest) != 0, dv);
-            }
+            if (valid) region_decision(regions, cvi, trees, r, R, cv, thr, dv);
             int64_t ex[kAggCh], inc[kAggCh];
 #pragma unroll
             for (int c = 0; c < kAggCh; ++c) {
@@ -750,6 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         C.tree = R.tree;
                         C.meta = (R.meta & ~kMetaChildFinest) | (lc + 1 == T.dmax ? kMetaChildFinest : 0u);
                         nreg[ri] = C;
+                        reinterpret_cast<int4*>(ncv)[ri] = int4{0, 0, 0, 0};
                         // next-level tiles whose first entry falls inside this region
                         for (int64_t t = cdiv(start, kTile); t * kTile < start + cv[q] && t < n_ntiles; ++t)
                             ntf[t] = (int32_t)ri;
@@ -758,8 +770,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         start += cv[q];
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) dsto[r * 4 + q] = dq[q];
+                int4* const d4 = reinterpret_cast<int4*>(dsto + r * 4);
+                d4[0] = int4{(int32_t)dq[0], (int32_t)(dq[0] >> 32), (int32_t)dq[1], (int32_t)(dq[1] >> 32)};
+                d4[1] = int4{(int32_t)dq[2], (int32_t)(dq[2] >> 32), (int32_t)dq[3], (int32_t)(dq[3] >> 32)};
                 // the first parent of each tree records where its tree's sums begin
                 if (r == 0 || regions[r - 1].tree != R.tree) {
                     int64_t* rc = G(ar.rec + ((int64_t)R.tree * kMaxLevels + l) * kRecCh);
@@ -784,8 +797,100 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
 // Within a row the rank is a lane count: for the lanes of the region open at
 // the row's first entry the wavefront's running count plus the lanes below,
 // for a region that begins in the row the lanes below minus the lanes below
-// its first entry.  A wavefront starts its running counts from woff (and the
-// carried region from tpre), so wavefronts never exchange counts.
+// its first entry.  A wavefront starts its running counts from woff, plus,
+// for a region carried in from earlier tiles, its votes in those tiles
+// (head of its first tile and tcar of the tiles between), so wavefronts never
+// exchange counts.
+
+struct WriteLds {
+    uint32_t bm[2][kTile / 32];  // alternate tiles: one is cleared while the other is in use
+    StagedRegions sr;
+    int64_t dst[kStage][4];
+    int32_t tpre[4];             // votes of the carried region before this tile
+};
+
+template <bool kStaged>
+struct DstSource {
+    const int64_t (*s)[4];
+    const int64_t* dsti;
+    int r0;
+    __device__ int64_t at(int local, int q) const
+    {
+        if constexpr (kStaged) return s[local][q];
+        else return dsti[(int64_t)(r0 + local) * 4 + q];
+    }
+};
+
+template <typename Entry, int kVariant, typename CT, bool kStaged>
+__device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, const DstSource<kStaged>& dsrc,
+                                           const uint32_t* bm, const Entry (&ent)[kRows], int64_t rb, int64_t L,
+                                           int lc, int wave, int lane, int nr, int32_t (&run)[4], int open,
+                                           Entry* nlist, int64_t L2, Entry* members, int64_t mem_end, bool& bad)
+{
+    uint32_t o_ij, o_meta;
+    int64_t o_dst[4];
+    auto open_fields = [&]() {
+        const int o = std::min(open, nr - 1);
+        src.fields(o, o_ij, o_meta);
+        o_ij = rfl(o_ij);
+        o_meta = rfl(o_meta);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o_dst[q] = (int64_t)uniform64((uint64_t)dsrc.at(o, q));
+    };
+    open_fields();
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const uint64_t vm = __ballot(rb + k * kWave + lane < L);
+        const uint64_t W = row_word(bm, wave * kRows + k);
+        uint64_t cm[4];
+        if (W == 0) {   // the whole row belongs to the open region
+            child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), o_meta, o_ij, lc, cm);
+            const bool finest = o_meta & kMetaChildFinest;
+            Entry* const out = finest ? members : nlist;
+            const int64_t cap = finest ? mem_end : L2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (o_dst[q] >= 0 && ((cm[q] >> lane) & 1u)) {
+                    const int64_t pos = o_dst[q] + run[q] + (int64_t)lanes_below(cm[q]);
+                    if (pos < cap) out[pos] = ent[k];
+                    else bad = true;
+                }
+                run[q] += (int32_t)__popcll(cm[q]);
+            }
+            continue;
+        }
+        const uint64_t le = W & ((2ull << lane) - 1);
+        const bool seg0 = le == 0;
+        const int local = std::min(open + (int)__popcll(le), nr - 1);
+        const int p = seg0 ? 0 : 63 - __builtin_clzll(le);   // first lane of this lane's region in the row
+        uint32_t ij, meta;
+        src.fields(local, ij, meta);
+        child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
+        uint32_t m[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[q] = lanes_below(cm[q]);
+        const uint32_t packed = m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
+        const uint32_t at_p = (uint32_t)__shfl((int)packed, p, kWave);
+        const bool finest = meta & kMetaChildFinest;
+        Entry* const out = finest ? members : nlist;
+        const int64_t cap = finest ? mem_end : L2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!((cm[q] >> lane) & 1u)) continue;
+            const int64_t d = seg0 ? o_dst[q] : dsrc.at(local, q);
+            if (d < 0) continue;
+            const int64_t pos = d + (int64_t)m[q] - (int64_t)((at_p >> (8 * q)) & 255u) + (seg0 ? run[q] : 0);
+            if (pos < cap) out[pos] = ent[k];
+            else bad = true;
+        }
+        open += (int)__popcll(W);
+        const uint64_t from = ~bits_below(63 - __builtin_clzll(W));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & from);
+        open_fields();
+    }
+}
+
 template <typename Entry, int kVariant, typename CT>
 __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
 {
@@ -811,86 +916,85 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
     const int64_t* const dsti = G(static_cast<const int64_t*>(wl.dst));
-    const int32_t* const tpre = G(static_cast<const int32_t*>(wl.tpre));
+    const int32_t* const head = G(static_cast<const int32_t*>(wl.head));
+    const int32_t* const tcar = G(static_cast<const int32_t*>(wl.tcar));
     const int32_t* const woff = G(static_cast<const int32_t*>(wl.woff));
     Entry* const nlist = G(static_cast<Entry*>(nx.list));
     Entry* const members = G(static_cast<Entry*>(ar.members));
     const int64_t nt = cdiv(L, kTile);
+    int64_t tile = blockIdx.x;
+    if (tile >= nt) return;
 
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    if (tid < kTile / 32) {
+        S.bm[0][tid] = 0u;
+        S.bm[1][tid] = 0u;
+    }
+    Entry ent[kRows];
+    load_rows(list, L, tile, wave, lane, ent);
+    TileBounds tb = tile_bounds(tile_first, tile, nt, P);
+    bool bad = false;
+    for (int it = 0;; ++it) {
+        const int64_t next = tile + gridDim.x;
+        Entry nent[kRows];
+        load_rows(list, L, next, wave, lane, nent);
+        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
+
         const int64_t t0 = tile * kTile;
         const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
-        Entry ent[kRows];
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t e = rb + k * kWave + lane;
-            ent[k] = e < L ? list[e] : Entry(0);
-        }
-        TileRange tr;
-        if (!tile_range(tile_first, tile, nt, P, tr)) {
+        if (!bounds_ok(tb, P)) {
             if (tid == 0) raise_error(ar.error, kErrInternal);
             return;
         }
+        const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
+        uint32_t* const bm = S.bm[it & 1];
         __syncthreads();   // the previous tile is done with S
-        if (tid < kTile / 32) S.bm[tid] = 0u;
-        __syncthreads();
-        const bool carried = stage_tile(S, regions, t0, tr);
-        for (int k = tid; k < tr.nr && k < kStage; k += kBlock)
+        if (tid < kTile / 32) S.bm[(it + 1) & 1][tid] = 0u;   // last read two tiles ago
+        const bool carried = stage_tile(bm, S.sr, regions, t0, tb);
+        for (int k = tid; k < nr && k < kStage; k += kBlock)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) S.dst[k][q] = dsti[(int64_t)(tr.r0 + k) * 4 + q];
+            for (int q = 0; q < 4; ++q) S.dst[k][q] = dsti[(int64_t)(r0 + k) * 4 + q];
+        if (carried && wave == 0) {
+            // votes of the carried region before this tile: its first tile's
+            // piece plus the whole tiles in between
+            const int64_t ts = regions[r0].start / kTile;
+            int32_t c[4] = {0, 0, 0, 0};
+            for (int64_t t = ts + 1 + lane; t < tile; t += kWave) {
+                const int4 v = reinterpret_cast<const int4*>(tcar)[t];
+                c[0] += v.x;
+                c[1] += v.y;
+                c[2] += v.z;
+                c[3] += v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = wave_sum32(c[q]);
+            if (lane < 4) S.tpre[lane] = pick4(c, lane) + head[(int64_t)r0 * 4 + lane];
+        }
         __syncthreads();
 
-        int open = starts_before(S.bm, wave, lane);
+        const int open = starts_before(bm, wave, lane);
         int32_t run[4];
         {
             const bool first_carried = open == 0 && carried;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? tpre[tile * 4 + q] : 0);
+                run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? S.tpre[q] : 0);
         }
-        bool bad = false;
+        if (nr <= kStage)
+            write_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0},
+                                                  DstSource<true>{S.dst, dsti, r0}, bm, ent, rb, L, lc, wave, lane,
+                                                  nr, run, open, nlist, L2, members, mem_end, bad);
+        else
+            write_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0},
+                                                   DstSource<false>{S.dst, dsti, r0}, bm, ent, rb, L, lc, wave,
+                                                   lane, nr, run, open, nlist, L2, members, mem_end, bad);
+
+        if (next >= nt) break;
+        tile = next;
+        tb = ntb;
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t e = rb + k * kWave + lane;
-            const uint64_t W = row_word(S.bm, wave * kRows + k);
-            const uint64_t le = W & ((2ull << lane) - 1);
-            const bool seg0 = le == 0;
-            const int local = std::min(open + (int)__popcll(le), tr.nr - 1);
-            const int p = seg0 ? 0 : 63 - __builtin_clzll(le);   // first lane of this lane's region in the row
-            uint32_t ij, meta;
-            region_fields(S.ij, S.meta, regions, tr.r0, local, ij, meta);
-            uint64_t cm[4];
-            child_masks<kVariant, CT>(e < L, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
-            uint32_t m[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) m[q] = lanes_below(cm[q]);
-            const uint32_t packed = m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
-            const uint32_t at_p = (uint32_t)__shfl((int)packed, p, kWave);
-            const bool finest = meta & kMetaChildFinest;
-            Entry* const out = finest ? members : nlist;
-            const int64_t cap = finest ? mem_end : L2;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!((cm[q] >> lane) & 1u)) continue;
-                const int64_t d = local < kStage ? S.dst[local][q] : dsti[(int64_t)(tr.r0 + local) * 4 + q];
-                if (d < 0) continue;
-                const int64_t pos =
-                    d + (int64_t)m[q] - (int64_t)((at_p >> (8 * q)) & 255u) + (seg0 ? run[q] : 0);
-                if (pos < cap) out[pos] = ent[k];
-                else bad = true;
-            }
-            if (W) {
-                open += (int)__popcll(W);
-                const uint64_t from = ~bits_below(63 - __builtin_clzll(W));
-#pragma unroll
-                for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & from);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q]);
-            }
-        }
-        if (__any(bad) && lane == 0) raise_error(ar.error, kErrInternal);
+        for (int k = 0; k < kRows; ++k) ent[k] = nent[k];
     }
+    if (__any(bad) && lane == 0) raise_error(ar.error, kErrInternal);
 }
 
 // Edge staging: nonzero pixels of a row-major binary image in row-major order.
@@ -1039,6 +1143,7 @@ __global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_po
         return;
     }
     for (int64_t t = g; t < P0; t += stride) {
+        for (int q = 0; q < 4; ++q) hl.cv[t * 4 + q] = 0;
         const int32_t pass = trees[t].pass, s_log2 = trees[t].s_log2, td = trees[t].dmax;
         Region R;
         R.start = t * E;

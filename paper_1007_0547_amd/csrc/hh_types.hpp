@@ -21,7 +21,6 @@ constexpr int kMaxLevels = 16;              // depth <= 15
 constexpr int kNumStats = 6;                // evaluated, votes, split, detected, code_tests, entries
 constexpr int kAggCh = 5;                   // decision sums: next regions, next entries, cells, member entries, votes
 constexpr int kRecCh = 6;                   // tree record: p, start, then the decision prefixes
-constexpr int kLongSpan = 8;                // regions spanning more tiles are summed by a whole workgroup
 constexpr int kRangeGrid = 512;             // region ranges of the split-decision launches
 
 // Error bits set by kernels (the host reports them after the call).
@@ -85,13 +84,15 @@ struct Cell {
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t align256(int64_t bytes) { return (bytes + 255) & ~(int64_t)255; }
 
-// A level's data inside its arena half (l & 1): the region table and the
-// tile map, written by the previous level's split decision (or the root
-// setup), then the level's list, written by the previous level's
-// compaction.  tile_first[t] is the region holding entry t * kTile.
+// A level's data inside its arena half (l & 1): the region table, the tile
+// map and the child-vote totals (zeroed), written by the previous level's
+// split decision (or the root setup), then the level's list, written by the
+// previous level's compaction.  tile_first[t] is the region holding entry
+// t * kTile; cv[r][q] collects the votes of child q of region r.
 struct HalfLayout {
     Region* regions;
     int32_t* tile_first;
+    int32_t* cv;
     void* list;
     int64_t end;        // bytes used from the half's start
 };
@@ -104,6 +105,8 @@ __host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t
     off += align256(P * (int64_t)sizeof(Region));
     y.tile_first = reinterpret_cast<int32_t*>(half + off);
     off += align256((cdiv(L, kTile) + 1) * 4);
+    y.cv = reinterpret_cast<int32_t*>(half + off);
+    off += align256(P * 16);
     y.list = half + off;
     off += align256(L * entry_bytes);
     y.end = off;
@@ -111,20 +114,17 @@ __host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t
 }
 
 // Per-level scratch, reused by every level.
-//   head  [P][4]  child votes counted in the tile where the region starts
-//   cv    [P][4]  child votes
+//   head  [P][4]  child votes of a region in the tile where it starts, for
+//                 regions that run past that tile
 //   dst   [P][4]  where the child's voters go (next list or member buffer), -1: dropped
 //   tcar  [nt][4] child votes of the region carried into tile t from earlier tiles
-//   tpre  [nt][4] child votes of that region before tile t
 //   woff  [nt][kWaves][4] child votes of the region open at each wavefront's
 //                 first entry, counted from its first entry in the tile
 //   agg   [kRangeGrid][kAggCh] decision sums per range of regions
 struct WorkLayout {
     int32_t* head;
-    int32_t* cv;
     int64_t* dst;
     int32_t* tcar;
-    int32_t* tpre;
     int32_t* woff;
     int64_t* agg;
     int64_t end;
@@ -137,13 +137,9 @@ __host__ __device__ inline WorkLayout work_layout(char* work, int64_t P, int64_t
     int64_t off = 0;
     w.head = reinterpret_cast<int32_t*>(work + off);
     off += align256(P * 16);
-    w.cv = reinterpret_cast<int32_t*>(work + off);
-    off += align256(P * 16);
     w.dst = reinterpret_cast<int64_t*>(work + off);
     off += align256(P * 32);
     w.tcar = reinterpret_cast<int32_t*>(work + off);
-    off += align256(nt * 16);
-    w.tpre = reinterpret_cast<int32_t*>(work + off);
     off += align256(nt * 16);
     w.woff = reinterpret_cast<int32_t*>(work + off);
     off += align256(nt * kWaves * 16);
