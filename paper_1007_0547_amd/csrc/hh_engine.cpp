@@ -459,16 +459,18 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
         la.trees = d_trees.as<TreeDesc>();
         la.xy = xy;
         la.keep_members = plan.membership ? 1 : 0;
+        const int count_grid = level_grid(0, plan.variant, plan.wide, entry_bytes, ctx->cu_count);
+        const int write_grid = level_grid(1, plan.variant, plan.wide, entry_bytes, ctx->cu_count);
         for (int l = 0; l < plan.dmax; ++l) {
             la.level = l;
             mark(ctx, 3 + 4 * l);
-            check(launch_count(la, plan.variant, plan.wide, ctx->grid, st), "count");
+            check(launch_count(la, plan.variant, plan.wide, count_grid, st), "count");
             mark(ctx, 4 + 4 * l);
             check(launch_decide(la, kRangeGrid, st), "decide");
             check(launch_emit(la, kRangeGrid, st), "emit");
             mark(ctx, 5 + 4 * l);
             if (l + 1 < plan.dmax || plan.membership)
-                check(launch_write(la, plan.variant, plan.wide, ctx->grid, st), "write");
+                check(launch_write(la, write_grid, st), "write");
             mark(ctx, 6 + 4 * l);
         }
         mark(ctx, 2);

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hh_kernels.hpp"
 
@@ -81,14 +82,31 @@ __device__ inline T pick4(const T (&v)[4], int k)
     return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
 }
 
+// A list entry carries its line as (u, v) packed u | v << 16: the edge point
+// (x, y) in pass 0 and (y, x) in pass 1 (Sec. 3, BETA reads the point with
+// its axes swapped), so no kernel tests the pass per entry.  swap16 turns one
+// form into the other.
+__device__ inline uint32_t swap16(uint32_t p) { return (p >> 16) | (p << 16); }
+
 template <typename Entry> struct EntryOps;
-template <> struct EntryOps<uint32_t> {   // the packed edge point
+template <> struct EntryOps<uint32_t> {   // the packed line
     __device__ static uint32_t point(uint32_t e) { return e; }
-    __device__ static uint32_t root(const uint32_t* pts, int64_t k) { return pts[k]; }
+    __device__ static uint32_t root(const uint32_t* pts, int64_t k, bool swap)
+    {
+        return swap ? swap16(pts[k]) : pts[k];
+    }
+    __device__ static uint32_t natural(uint32_t e, bool swap) { return swap ? swap16(e) : e; }
 };
-template <> struct EntryOps<uint64_t> {   // point id << 32 | packed edge point
+template <> struct EntryOps<uint64_t> {   // point id << 32 | packed line
     __device__ static uint32_t point(uint64_t e) { return (uint32_t)e; }
-    __device__ static uint64_t root(const uint32_t* pts, int64_t k) { return ((uint64_t)k << 32) | pts[k]; }
+    __device__ static uint64_t root(const uint32_t* pts, int64_t k, bool swap)
+    {
+        return ((uint64_t)k << 32) | (swap ? swap16(pts[k]) : pts[k]);
+    }
+    __device__ static uint64_t natural(uint64_t e, bool swap)
+    {
+        return swap ? ((e & 0xFFFFFFFF00000000ull) | swap16((uint32_t)e)) : e;
+    }
 };
 
 // The lines of a wavefront against the four children of each lane's parent
@@ -158,9 +176,7 @@ template <int kVariant, typename CT>
 __device__ inline void child_masks(uint64_t vm, uint32_t point, uint32_t meta, uint32_t ij, int lc,
                                    uint64_t (&cm)[4])
 {
-    const int32_t x = (int32_t)(point & 0xFFFFu), y = (int32_t)(point >> 16);
-    const bool swap = meta & kMetaPass;   // pass 1 reads (x0, y0) as (y0, x0)
-    const int32_t u = swap ? y : x, v = swap ? x : y;
+    const int32_t u = (int32_t)(point & 0xFFFFu), v = (int32_t)(point >> 16);
     const int s_log2 = (int)((meta >> kMetaSlogShift) & 15u);
     const int32_t pi = (int32_t)(ij & 0xFFFFu), pj = (int32_t)(ij >> 16);
     if constexpr (kVariant == 0)
@@ -168,6 +184,79 @@ __device__ inline void child_masks(uint64_t vm, uint32_t point, uint32_t meta, u
     else
         circle_masks(vm, u, v, pi, pj, lc, s_log2, cm);
 }
+
+// The open region's part of the vote test, computed once per region and kept
+// in scalar registers; masks() evaluates a whole row of lines against it as
+// lane masks, votes() (code variant) as per-lane bits without any scalar
+// work.  With d_cr = t_c - B_r - 1, corner (c, r) is below the line iff
+// d_cr >= 0, so a child votes iff the sign bit of ~d_SW & d_NE is set.
+template <int kVariant, typename CT>
+struct OpenMasks {
+    uint32_t ij, meta;
+    CT M0, B0, B1, B2;      // code variant: scaled corner values of the children's grid
+    CT nB0, nB1, nB2;       //   -B_r - 1
+    __device__ void set(uint32_t ij_, uint32_t meta_, int lc)
+    {
+        ij = ij_;
+        meta = meta_;
+        const int s_log2 = (int)((meta >> kMetaSlogShift) & 15u);
+        const CT S = (CT)1 << s_log2;
+        const int32_t pi = (int32_t)(ij & 0xFFFFu), pj = (int32_t)(ij >> 16);
+        M0 = (CT)4 * (CT)pi - ((CT)1 << lc);
+        B0 = (CT)6 * S * (CT)pj - (S << lc);
+        B1 = B0 + (CT)3 * S;
+        B2 = B1 + (CT)3 * S;
+        nB0 = -B0 - 1;
+        nB1 = -B1 - 1;
+        nB2 = -B2 - 1;
+    }
+    __device__ void masks(uint64_t vm, uint32_t point, int lc, uint64_t (&cm)[4]) const
+    {
+        if constexpr (kVariant == 0) {
+            const CT u = (CT)(point & 0xFFFFu), v = (CT)(point >> 16);
+            const CT t0 = (v << lc) - mul(u, M0);
+            const CT du = 2 * u;
+            const CT t1 = t0 - du;
+            const CT t2 = t1 - du;
+            const uint64_t b00 = __ballot(B0 < t0), b01 = __ballot(B1 < t0);
+            const uint64_t b10 = __ballot(B0 < t1), b11 = __ballot(B1 < t1), b12 = __ballot(B2 < t1);
+            const uint64_t b21 = __ballot(B1 < t2), b22 = __ballot(B2 < t2);
+            cm[0] = vm & b11 & ~b22;
+            cm[1] = vm & b01 & ~b12;
+            cm[2] = vm & b00 & ~b11;
+            cm[3] = vm & b10 & ~b21;
+        } else {
+            child_masks<kVariant, CT>(vm, point, meta, ij, lc, cm);
+        }
+    }
+    // code variant: vote bits of one lane (NE, NW, SW, SE in bits 0..3)
+    // |u| < 2^14 and |M0| <= 2^15: a 24-bit multiply is exact for 32-bit compares
+    __device__ static CT mul(CT u, CT m)
+    {
+        if constexpr (sizeof(CT) == 4) return __mul24(u, m);
+        else return u * m;
+    }
+    template <bool kAllValid>
+    __device__ uint32_t votes(bool valid, uint32_t point, int lc) const
+    {
+        const CT u = (CT)(point & 0xFFFFu), v = (CT)(point >> 16);
+        CT t0 = (v << lc) - mul(u, M0);
+        const CT du = 2 * u;
+        CT t1 = t0 - du;
+        CT t2 = t1 - du;
+        if (!kAllValid && !valid) t0 = t1 = t2 = -((CT)1 << 30);   // below every corner: no vote
+        const CT d00 = t0 + nB0, d01 = t0 + nB1;
+        const CT d10 = t1 + nB0, d11 = t1 + nB1, d12 = t1 + nB2;
+        const CT d21 = t2 + nB1, d22 = t2 + nB2;
+        constexpr int kSign = 8 * (int)sizeof(CT) - 1;
+        using U = typename std::conditional<sizeof(CT) == 8, uint64_t, uint32_t>::type;
+        const uint32_t ne = (uint32_t)((U)(~d11 & d22) >> kSign);
+        const uint32_t nw = (uint32_t)((U)(~d01 & d12) >> kSign);
+        const uint32_t sw = (uint32_t)((U)(~d00 & d11) >> kSign);
+        const uint32_t se = (uint32_t)((U)(~d10 & d21) >> kSign);
+        return ne | (nw << 1) | (sw << 2) | (se << 3);
+    }
+};
 
 __device__ inline int32_t wave_incl_scan32(int32_t x, int lane)
 {
@@ -320,9 +409,31 @@ __device__ inline bool stage_tile(uint32_t* bm, StagedRegions& sr, const Region*
 // piece of the region carried in from earlier tiles) and woff (the votes of
 // each wavefront's first region counted before that wavefront in the tile).
 
+// Vote bits (NE, NW, SW, SE in bits 0..3) of the line `point` for the
+// children of a region with constants c, 32-bit compares.  With
+// d_cr = t_c - B_r - 1, corner (c, r) is below iff d_cr >= 0, so a child votes
+// iff the sign bit of ~d_SW & d_NE is set (see code_masks).
+__device__ inline uint32_t code_votes(uint32_t point, const CodeConsts& c, int lc)
+{
+    const int32_t u = (int32_t)(point & 0xFFFFu), v = (int32_t)(point >> 16);
+    const int32_t t0 = (v << lc) - __mul24(u, c.M0);   // |u| < 2^14, |M0| <= 2^15
+    const int32_t du = 2 * u;
+    const int32_t t1 = t0 - du;
+    const int32_t t2 = t1 - du;
+    const int32_t d00 = t0 + c.nB0, d01 = t0 + c.nB1;
+    const int32_t d10 = t1 + c.nB0, d11 = t1 + c.nB1, d12 = t1 + c.nB2;
+    const int32_t d21 = t2 + c.nB1, d22 = t2 + c.nB2;
+    const uint32_t ne = (uint32_t)(~d11 & d22) >> 31;
+    const uint32_t nw = (uint32_t)(~d01 & d12) >> 31;
+    const uint32_t sw = (uint32_t)(~d00 & d11) >> 31;
+    const uint32_t se = (uint32_t)(~d10 & d21) >> 31;
+    return ne | (nw << 1) | (sw << 2) | (se << 3);
+}
+
 struct CountLds {
     uint32_t bm[kTile / 32];
     StagedRegions sr;
+    CodeConsts cc[kStage];
     int32_t wfirst[kWaves][4];   // per wavefront: votes of the region open at its first entry (up to its close)
     int32_t wlast[kWaves][4];    //   votes of the region open at its end, from that region's start
     int32_t wlocal[kWaves];      //   local index of that region
@@ -334,37 +445,59 @@ struct WaveCount {
     bool closed;       // the first region ended inside the wavefront
     int32_t run[4];    // votes of the open region counted inside the wavefront
     int32_t first[4];  // votes of the first region inside the wavefront
+    uint32_t vword;    // this lane's vote bits, row k in bits 4k .. 4k+3
 };
 
+__device__ inline uint32_t lane_bits(const uint64_t (&cm)[4], int lane)
+{
+    uint32_t b = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b |= (uint32_t)((cm[q] >> lane) & 1u) << q;
+    return b;
+}
+
+// Vote bits of one lane's line for the children of its region (local index
+// `local`): the staged code constants for 32-bit compares, otherwise the
+// general lane-mask form.
+template <int kVariant, typename CT, bool kStaged>
+__device__ inline uint32_t lane_votes(const RegionSource<kStaged>& src, const CodeConsts* cc, int local,
+                                      uint32_t point, uint64_t vm, int lc, int lane)
+{
+    if constexpr (kVariant == 0 && sizeof(CT) == 4) {
+        // staged: cc is the tile's LDS copy; otherwise the level's table from region r0
+        return ((vm >> lane) & 1u) ? code_votes(point, cc[local], lc) : 0u;
+    } else {
+        uint32_t ij, meta;
+        src.fields(local, ij, meta);
+        uint64_t cm[4];
+        child_masks<kVariant, CT>(vm, point, meta, ij, lc, cm);
+        return lane_bits(cm, lane);
+    }
+}
+
 template <typename Entry, int kVariant, typename CT, bool kStaged>
-__device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, const uint32_t* bm, const Entry (&ent)[kRows],
-                                           int64_t rb, int64_t L, int lc, int wave, int lane, int nr, int32_t* cv,
-                                           WaveCount& wc)
+__device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, const CodeConsts* cc, const uint32_t* bm,
+                                           const Entry (&ent)[kRows], int64_t rb, int64_t L, int lc, int wave,
+                                           int lane, int nr, int32_t* cv, WaveCount& wc)
 {
     int open = starts_before(bm, wave, lane);
-    uint32_t o_ij, o_meta;
-    src.fields(std::min(open, nr - 1), o_ij, o_meta);
-    o_ij = rfl(o_ij);
-    o_meta = rfl(o_meta);
     bool open_here = false;   // the open region began inside this wavefront
     bool closed = false;
     int32_t run[4] = {0, 0, 0, 0}, first[4] = {0, 0, 0, 0};
+    uint32_t vword = 0;
+    const int lim = (int)std::max<int64_t>(0, std::min<int64_t>(L - rb, kRows * kWave));   // valid entries
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
-        const uint64_t vm = __ballot(rb + k * kWave + lane < L);
+        const int left = lim - k * kWave;
+        const uint64_t vm = left >= kWave ? ~0ull : (left <= 0 ? 0ull : bits_below(left));
         const uint64_t W = row_word(bm, wave * kRows + k);
+        const int local = std::min(open + (int)__popcll(W & ((2ull << lane) - 1)), nr - 1);
+        const uint32_t vb = lane_votes<kVariant, CT, kStaged>(src, cc, local, EntryOps<Entry>::point(ent[k]), vm, lc,
+                                                                lane);
+        vword |= vb << (4 * k);
         uint64_t cm[4];
-        if (W == 0) {   // the whole row belongs to the open region
-            child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), o_meta, o_ij, lc, cm);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q]);
-            continue;
-        }
-        const uint64_t le = W & ((2ull << lane) - 1);
-        const int local = std::min(open + (int)__popcll(le), nr - 1);
-        uint32_t ij, meta;
-        src.fields(local, ij, meta);
-        child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
+        for (int q = 0; q < 4; ++q) cm[q] = __ballot((vb >> q) & 1u);
         uint64_t rest = W;
         int prev = 0;
         while (rest) {   // regions that end inside this row
@@ -389,12 +522,12 @@ __device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, con
         const uint64_t tail = ~bits_below(prev);
 #pragma unroll
         for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
-        src.fields(std::min(open, nr - 1), o_ij, o_meta);
-        o_ij = rfl(o_ij);
-        o_meta = rfl(o_meta);
+        // one row at a time: rows interleaved by the scheduler only cost registers
+        __builtin_amdgcn_sched_barrier(0);
     }
     wc.open = open;
     wc.closed = closed;
+    wc.vword = vword;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         wc.run[q] = run[q];
@@ -425,6 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
     int32_t* const cv = G(hl.cv);
+    const CodeConsts* const ccg = G(static_cast<const CodeConsts*>(hl.cc));
     int32_t* const head = G(wl.head);
     int32_t* const tcar = G(wl.tcar);
     int32_t* const woff = G(wl.woff);
@@ -451,14 +585,17 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
         const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
         __syncthreads();   // the previous tile is done with S (its bitmap is clear again)
         const bool carried = stage_tile(S.bm, S.sr, regions, t0, tb);
+        if constexpr (kVariant == 0 && sizeof(CT) == 4)
+            for (int k = tid; k < nr && k < kStage; k += kBlock) S.cc[k] = ccg[r0 + k];
         __syncthreads();
         WaveCount wc;
         if (nr <= kStage)
-            count_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0}, S.bm, ent, rb, L, lc, wave,
-                                                  lane, nr, cv, wc);
+            count_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0}, S.cc, S.bm, ent, rb, L, lc,
+                                                  wave, lane, nr, cv, wc);
         else
-            count_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0}, S.bm, ent, rb, L, lc,
-                                                   wave, lane, nr, cv, wc);
+            count_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0}, ccg + r0, S.bm, ent, rb,
+                                                   L, lc, wave, lane, nr, cv, wc);
+        G(wl.vbits)[tile * kBlock + tid] = wc.vword;
         if (lane < 4) {
             S.wfirst[wave][lane] = pick4(wc.first, lane);
             S.wlast[wave][lane] = pick4(wc.run, lane);
@@ -761,6 +898,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         C.tree = R.tree;
                         C.meta = (R.meta & ~kMetaChildFinest) | (lc + 1 == T.dmax ? kMetaChildFinest : 0u);
                         nreg[ri] = C;
+                        G(nx.cc)[ri] = code_consts(C.ij, C.meta, lc + 1);
                         reinterpret_cast<int4*>(ncv)[ri] = int4{0, 0, 0, 0};
                         // next-level tiles whose first entry falls inside this region
                         for (int64_t t = cdiv(start, kTile); t * kTile < start + cv[q] && t < n_ntiles; ++t)
@@ -806,66 +944,114 @@ struct WriteLds {
     uint32_t bm[2][kTile / 32];  // alternate tiles: one is cleared while the other is in use
     StagedRegions sr;
     int64_t dst[kStage][4];
+    int32_t cv[kStage][4];
     int32_t tpre[4];             // votes of the carried region before this tile
 };
 
+// Child destinations and child votes of local region `local`.
 template <bool kStaged>
-struct DstSource {
-    const int64_t (*s)[4];
+struct KidSource {
+    const int64_t (*s_dst)[4];
+    const int32_t (*s_cv)[4];
     const int64_t* dsti;
+    const int32_t* cvi;
     int r0;
-    __device__ int64_t at(int local, int q) const
+    __device__ int64_t dst(int local, int q) const
     {
-        if constexpr (kStaged) return s[local][q];
+        if constexpr (kStaged) return s_dst[local][q];
         else return dsti[(int64_t)(r0 + local) * 4 + q];
+    }
+    __device__ int32_t votes(int local, int q) const
+    {
+        if constexpr (kStaged) return s_cv[local][q];
+        else return cvi[(int64_t)(r0 + local) * 4 + q];
     }
 };
 
-template <typename Entry, int kVariant, typename CT, bool kStaged>
-__device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, const DstSource<kStaged>& dsrc,
-                                           const uint32_t* bm, const Entry (&ent)[kRows], int64_t rb, int64_t L,
-                                           int lc, int wave, int lane, int nr, int32_t (&run)[4], int open,
-                                           Entry* nlist, int64_t L2, Entry* members, int64_t mem_end, bool& bad)
+// Rows of one wavefront.  Per child slot q the open region keeps bq[q], the
+// start of that child's list (in the next level's list, or the member buffer
+// at the finest level), run[q], its votes for q so far, and cv[q], its total
+// votes for q from the count pass (the emit step checked every child's slot
+// [dst, dst + cv) against its buffer).  The lanes voting for q write at
+// run[q] + their rank in the row, the offset clamped to cv[q] - 1 so that no
+// store leaves the child's slot; when a region closes, run must equal cv
+// (else the call fails with an internal error).  A row without a region start
+// is one segment; a row with a few starts is taken segment by segment; a row
+// with many starts takes per-lane destinations.
+template <typename Entry, bool kStaged>
+__device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, const KidSource<kStaged>& kids,
+                                           const uint32_t* bm, const Entry (&ent)[kRows], uint32_t vword, int wave,
+                                           int lane, int nr, const int32_t (&run0)[4], int open, Entry* nlist,
+                                           Entry* members, bool& bad)
 {
-    uint32_t o_ij, o_meta;
-    int64_t o_dst[4];
+    Entry* bq[4];
+    int32_t run[4], cv[4];
+    uint32_t keep;     // bit q: child q's voters are kept
+    bool unswap;       // member entries are stored as (x, y) whatever the pass
     auto open_fields = [&]() {
         const int o = std::min(open, nr - 1);
-        src.fields(o, o_ij, o_meta);
-        o_ij = rfl(o_ij);
-        o_meta = rfl(o_meta);
+        uint32_t ij, meta;
+        src.fields(o, ij, meta);
+        meta = rfl(meta);
+        const bool finest = meta & kMetaChildFinest;
+        Entry* const out = finest ? members : nlist;
+        unswap = finest && (meta & kMetaPass);
+        keep = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o_dst[q] = (int64_t)uniform64((uint64_t)dsrc.at(o, q));
+        for (int q = 0; q < 4; ++q) {
+            const int64_t d = (int64_t)uniform64((uint64_t)kids.dst(o, q));
+            keep |= (d >= 0 ? 1u : 0u) << q;
+            bq[q] = out + (d >= 0 ? d : 0);
+            cv[q] = (int32_t)rfl((uint32_t)kids.votes(o, q));
+            run[q] = 0;
+        }
+    };
+    auto close_check = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (((keep >> q) & 1u) && run[q] != cv[q]) bad = true;
     };
     open_fields();
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const uint64_t vm = __ballot(rb + k * kWave + lane < L);
-        const uint64_t W = row_word(bm, wave * kRows + k);
-        uint64_t cm[4];
-        if (W == 0) {   // the whole row belongs to the open region
-            child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), o_meta, o_ij, lc, cm);
-            const bool finest = o_meta & kMetaChildFinest;
-            Entry* const out = finest ? members : nlist;
-            const int64_t cap = finest ? mem_end : L2;
+    for (int q = 0; q < 4; ++q) run[q] = run0[q];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (o_dst[q] >= 0 && ((cm[q] >> lane) & 1u)) {
-                    const int64_t pos = o_dst[q] + run[q] + (int64_t)lanes_below(cm[q]);
-                    if (pos < cap) out[pos] = ent[k];
-                    else bad = true;
+    for (int k = 0; k < kRows; ++k) {
+        const uint32_t vb = (vword >> (4 * k)) & 15u;
+        uint64_t cm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cm[q] = __ballot((vb >> q) & 1u);
+        const uint64_t W = row_word(bm, wave * kRows + k);
+        const int starts = (int)__popcll(W);
+        if (starts <= 3) {
+            uint64_t rest = W;
+            int prev = 0;
+            for (;;) {   // the segments of this row, one region each
+                const int p = rest ? __builtin_ctzll(rest) : kWave;
+                const bool inseg = lane >= prev && lane < p;
+                const uint32_t vk = inseg ? (vb & keep) : 0u;
+                const Entry e_out = EntryOps<Entry>::natural(ent[k], unswap);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t mq = cm[q] & (p == kWave ? ~0ull : bits_below(p)) & ~bits_below(prev);
+                    if ((vk >> q) & 1u) bq[q][std::min(run[q] + (int32_t)lanes_below(mq), cv[q] - 1)] = e_out;
+                    run[q] += (int32_t)__popcll(mq);
                 }
-                run[q] += (int32_t)__popcll(cm[q]);
+                if (!rest) break;
+                rest &= rest - 1;
+                prev = p;
+                close_check();
+                ++open;
+                open_fields();
             }
             continue;
         }
+        // many regions in this row: per-lane destinations
         const uint64_t le = W & ((2ull << lane) - 1);
         const bool seg0 = le == 0;
         const int local = std::min(open + (int)__popcll(le), nr - 1);
         const int p = seg0 ? 0 : 63 - __builtin_clzll(le);   // first lane of this lane's region in the row
         uint32_t ij, meta;
         src.fields(local, ij, meta);
-        child_masks<kVariant, CT>(vm, EntryOps<Entry>::point(ent[k]), meta, ij, lc, cm);
         uint32_t m[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[q] = lanes_below(cm[q]);
@@ -873,25 +1059,31 @@ __device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, con
         const uint32_t at_p = (uint32_t)__shfl((int)packed, p, kWave);
         const bool finest = meta & kMetaChildFinest;
         Entry* const out = finest ? members : nlist;
-        const int64_t cap = finest ? mem_end : L2;
+        const Entry e_out = EntryOps<Entry>::natural(ent[k], finest && (meta & kMetaPass));
+        const uint64_t first = bits_below(__builtin_ctzll(W));   // the lanes of the region open at the row start
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (!((cm[q] >> lane) & 1u)) continue;
-            const int64_t d = seg0 ? o_dst[q] : dsrc.at(local, q);
-            if (d < 0) continue;
-            const int64_t pos = d + (int64_t)m[q] - (int64_t)((at_p >> (8 * q)) & 255u) + (seg0 ? run[q] : 0);
-            if (pos < cap) out[pos] = ent[k];
-            else bad = true;
+            if (!((vb >> q) & 1u)) continue;
+            const int32_t rank = (int32_t)m[q] - (int32_t)((at_p >> (8 * q)) & 255u);
+            if (seg0) {
+                if ((keep >> q) & 1u) bq[q][std::min(run[q] + rank, cv[q] - 1)] = e_out;
+            } else {
+                const int64_t d = kids.dst(local, q);
+                if (d >= 0) out[d + std::min(rank, kids.votes(local, q) - 1)] = e_out;
+            }
         }
-        open += (int)__popcll(W);
-        const uint64_t from = ~bits_below(63 - __builtin_clzll(W));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & from);
+        for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & first);
+        close_check();
+        open += starts;
+        const int h = 63 - __builtin_clzll(W);
         open_fields();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & ~bits_below(h));
     }
 }
 
-template <typename Entry, int kVariant, typename CT>
+template <typename Entry>
 __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
 {
     __shared__ WriteLds S;
@@ -907,11 +1099,8 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
     const WorkLayout wl = work_layout(ar.work, P, L);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
-    const int64_t P2 = ar.info[lc].P, L2 = ar.info[lc].L;
-    const HalfLayout nx = half_layout(ar.half[lc & 1], P2, L2, ar.entry_bytes);
-    if (nx.end > ar.half_cap) return;
-    const int64_t mem_end = a.keep_members ? ar.info[lc].mem_base + ar.info[lc].mem : 0;
-    if (mem_end > ar.mem_cap) return;
+    // the next level's list and the member buffer were checked by the emit step
+    const HalfLayout nx = half_layout(ar.half[lc & 1], ar.info[lc].P, ar.info[lc].L, ar.entry_bytes);
     const Entry* const list = G(static_cast<const Entry*>(hl.list));
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
@@ -919,6 +1108,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     const int32_t* const head = G(static_cast<const int32_t*>(wl.head));
     const int32_t* const tcar = G(static_cast<const int32_t*>(wl.tcar));
     const int32_t* const woff = G(static_cast<const int32_t*>(wl.woff));
+    const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
     Entry* const nlist = G(static_cast<Entry*>(nx.list));
     Entry* const members = G(static_cast<Entry*>(ar.members));
     const int64_t nt = cdiv(L, kTile);
@@ -929,19 +1119,21 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
         S.bm[0][tid] = 0u;
         S.bm[1][tid] = 0u;
     }
+    const uint32_t* const vbits = G(static_cast<const uint32_t*>(wl.vbits));
     Entry ent[kRows];
     load_rows(list, L, tile, wave, lane, ent);
+    uint32_t vword = vbits[tile * kBlock + tid];
     TileBounds tb = tile_bounds(tile_first, tile, nt, P);
     bool bad = false;
     for (int it = 0;; ++it) {
         const int64_t next = tile + gridDim.x;
         Entry nent[kRows];
         load_rows(list, L, next, wave, lane, nent);
+        const uint32_t nvword = next < nt ? vbits[next * kBlock + tid] : 0u;
         const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
 
         const int64_t t0 = tile * kTile;
-        const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
-        if (!bounds_ok(tb, P)) {
+                if (!bounds_ok(tb, P)) {
             if (tid == 0) raise_error(ar.error, kErrInternal);
             return;
         }
@@ -950,9 +1142,11 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
         __syncthreads();   // the previous tile is done with S
         if (tid < kTile / 32) S.bm[(it + 1) & 1][tid] = 0u;   // last read two tiles ago
         const bool carried = stage_tile(bm, S.sr, regions, t0, tb);
-        for (int k = tid; k < nr && k < kStage; k += kBlock)
+        for (int k = tid; k < nr && k < kStage; k += kBlock) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) S.dst[k][q] = dsti[(int64_t)(r0 + k) * 4 + q];
+            *reinterpret_cast<int4*>(S.cv[k]) = reinterpret_cast<const int4*>(cvi)[r0 + k];
+        }
         if (carried && wave == 0) {
             // votes of the carried region before this tile: its first tile's
             // piece plus the whole tiles in between
@@ -980,17 +1174,18 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
                 run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? S.tpre[q] : 0);
         }
         if (nr <= kStage)
-            write_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0},
-                                                  DstSource<true>{S.dst, dsti, r0}, bm, ent, rb, L, lc, wave, lane,
-                                                  nr, run, open, nlist, L2, members, mem_end, bad);
+            write_rows<Entry, true>(RegionSource<true>{S.sr, regions, r0},
+                                    KidSource<true>{S.dst, S.cv, dsti, cvi, r0}, bm, ent, vword, wave, lane, nr, run,
+                                    open, nlist, members, bad);
         else
-            write_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0},
-                                                   DstSource<false>{S.dst, dsti, r0}, bm, ent, rb, L, lc, wave,
-                                                   lane, nr, run, open, nlist, L2, members, mem_end, bad);
+            write_rows<Entry, false>(RegionSource<false>{S.sr, regions, r0},
+                                     KidSource<false>{S.dst, S.cv, dsti, cvi, r0}, bm, ent, vword, wave, lane, nr,
+                                     run, open, nlist, members, bad);
 
         if (next >= nt) break;
         tile = next;
         tb = ntb;
+        vword = nvword;
 #pragma unroll
         for (int k = 0; k < kRows; ++k) ent[k] = nent[k];
     }
@@ -1152,12 +1347,13 @@ __global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_po
         R.tree = (int32_t)t;
         R.meta = (pass ? kMetaPass : 0u) | ((uint32_t)s_log2 << kMetaSlogShift) | (td == 1 ? kMetaChildFinest : 0u);
         hl.regions[t] = R;
+        hl.cc[t] = code_consts(R.ij, R.meta, 1);
     }
     for (int64_t k = g; k < cdiv(L0, kTile); k += stride) hl.tile_first[k] = (int32_t)((k * kTile) / E);
     Entry* const list = static_cast<Entry*>(hl.list);
     for (int64_t k = g; k < L0; k += stride) {
         const int64_t t = k / E;
-        list[k] = EntryOps<Entry>::root(xy + trees[t].xy_base, k - t * E);
+        list[k] = EntryOps<Entry>::root(xy + trees[t].xy_base, k - t * E, trees[t].pass != 0);
     }
 }
 
@@ -1260,6 +1456,39 @@ hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64
     return hipGetLastError();
 }
 
+// Workgroups of the count / compaction kernels that fit on the device at
+// once: each walks its share of the tiles, so a grid larger than what is
+// resident would run in two rounds.
+template <typename K>
+int resident_grid(K kernel, int cu_count)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return per_cu * cu_count;
+}
+
+#define HH_LEVEL_GRID(kernel)                                                                   \
+    do {                                                                                        \
+        if (variant == 1)                                                                       \
+            return ids ? resident_grid(kernel<uint64_t, 1, int64_t>, cu_count)                  \
+                       : resident_grid(kernel<uint32_t, 1, int64_t>, cu_count);                 \
+        if (wide)                                                                               \
+            return ids ? resident_grid(kernel<uint64_t, 0, int64_t>, cu_count)                  \
+                       : resident_grid(kernel<uint32_t, 0, int64_t>, cu_count);                 \
+        return ids ? resident_grid(kernel<uint64_t, 0, int32_t>, cu_count)                      \
+                   : resident_grid(kernel<uint32_t, 0, int32_t>, cu_count);                     \
+    } while (0)
+
+int level_grid(int which, int variant, bool wide, int entry_bytes, int cu_count)
+{
+    const bool ids = entry_bytes == 8;
+    if (which == 0) HH_LEVEL_GRID(k_count);
+    return ids ? resident_grid(k_write<uint64_t>, cu_count) : resident_grid(k_write<uint32_t>, cu_count);
+}
+
 hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
 {
     HH_LEVEL_LAUNCH(k_count);
@@ -1278,9 +1507,10 @@ hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
+hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s)
 {
-    HH_LEVEL_LAUNCH(k_write);
+    if (a.ar.entry_bytes == 8) k_write<uint64_t><<<grid, kBlock, 0, s>>>(a);
+    else k_write<uint32_t><<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

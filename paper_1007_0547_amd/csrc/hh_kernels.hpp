@@ -45,10 +45,14 @@ hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64
 // One level: child-vote counts per tile, per-region totals and decisions,
 // the next level's tables, then the compaction of the voters of the kept
 // children (skipped by the host at the finest level without members).
+// Resident workgroups of the count (which = 0) or compaction (which = 1)
+// kernel of the given form on a device with cu_count compute units (the
+// compaction kernel depends on the entry size only).
+int level_grid(int which, int variant, bool wide, int entry_bytes, int cu_count);
 hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
 hipError_t launch_decide(const LevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s);
-hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
+hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s);
 // Point ids of the voters of detected cells (see k_member_ids): into the
 // member buffer's layout (dst_off == nullptr) or compacted at dst_off[c].
 hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, const void* src,

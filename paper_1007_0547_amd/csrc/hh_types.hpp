@@ -84,14 +84,38 @@ struct Cell {
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t align256(int64_t bytes) { return (bytes + 255) & ~(int64_t)255; }
 
+// The part of the corner test (Sec. 2) a region shares with all its lines,
+// for the 4-bit code variant with 32-bit compares: M0 = M of the first corner
+// column of its children's grid and nB_r = -B_r - 1 for the three corner rows,
+// at the children's level.
+struct CodeConsts {
+    int32_t M0, nB0, nB1, nB2;
+};
+
+__host__ __device__ inline CodeConsts code_consts(uint32_t ij, uint32_t meta, int lc)
+{
+    const int s_log2 = (int)((meta >> 1) & 15u);
+    const int32_t S = 1 << s_log2;
+    const int32_t pi = (int32_t)(ij & 0xFFFFu), pj = (int32_t)(ij >> 16);
+    const int32_t B0 = 6 * S * pj - (S << lc);
+    CodeConsts c;
+    c.M0 = 4 * pi - (1 << lc);
+    c.nB0 = -B0 - 1;
+    c.nB1 = -(B0 + 3 * S) - 1;
+    c.nB2 = -(B0 + 6 * S) - 1;
+    return c;
+}
+
 // A level's data inside its arena half (l & 1): the region table, the tile
-// map and the child-vote totals (zeroed), written by the previous level's
-// split decision (or the root setup), then the level's list, written by the
-// previous level's compaction.  tile_first[t] is the region holding entry
-// t * kTile; cv[r][q] collects the votes of child q of region r.
+// map, the regions' code constants and the child-vote totals (zeroed),
+// written by the previous level's split decision (or the root setup), then
+// the level's list, written by the previous level's compaction.
+// tile_first[t] is the region holding entry t * kTile; cv[r][q] collects the
+// votes of child q of region r.
 struct HalfLayout {
     Region* regions;
     int32_t* tile_first;
+    CodeConsts* cc;
     int32_t* cv;
     void* list;
     int64_t end;        // bytes used from the half's start
@@ -105,6 +129,8 @@ __host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t
     off += align256(P * (int64_t)sizeof(Region));
     y.tile_first = reinterpret_cast<int32_t*>(half + off);
     off += align256((cdiv(L, kTile) + 1) * 4);
+    y.cc = reinterpret_cast<CodeConsts*>(half + off);
+    off += align256(P * (int64_t)sizeof(CodeConsts));
     y.cv = reinterpret_cast<int32_t*>(half + off);
     off += align256(P * 16);
     y.list = half + off;
@@ -120,12 +146,16 @@ __host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t
 //   tcar  [nt][4] child votes of the region carried into tile t from earlier tiles
 //   woff  [nt][kWaves][4] child votes of the region open at each wavefront's
 //                 first entry, counted from its first entry in the tile
+//   vbits [nt][kBlock] the vote bits of the count pass for the compaction
+//                 pass: lane t of a tile, bits 4k .. 4k+3 = votes of the
+//                 entry in its wavefront's row k for the children NE, NW, SW, SE
 //   agg   [kRangeGrid][kAggCh] decision sums per range of regions
 struct WorkLayout {
     int32_t* head;
     int64_t* dst;
     int32_t* tcar;
     int32_t* woff;
+    uint32_t* vbits;
     int64_t* agg;
     int64_t end;
 };
@@ -143,6 +173,8 @@ __host__ __device__ inline WorkLayout work_layout(char* work, int64_t P, int64_t
     off += align256(nt * 16);
     w.woff = reinterpret_cast<int32_t*>(work + off);
     off += align256(nt * kWaves * 16);
+    w.vbits = reinterpret_cast<uint32_t*>(work + off);
+    off += align256(nt * kBlock * 4);
     w.agg = reinterpret_cast<int64_t*>(work + off);
     off += align256((int64_t)kRangeGrid * kAggCh * 8);
     w.end = off;
