@@ -54,6 +54,29 @@ def kernel_bytes(timing, entry_bytes):
     n_in, n_out = timing["vote_entries"], timing["vote_written"]
     return {"count": entry_bytes * n_in, "write": entry_bytes * (n_in + n_out)}
 
+def measured_traffic(kernel):
+    """HBM bytes per step of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_write_seg1024_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1007_0547_amd", "csrc", "hh_kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    v = fields.get(f"{kernel}_traffic_bytes_per_step")
+    return float(v) if v else None
+
+
 def cpu_baseline(image, W, H, T, depth, budget_s=12.0):
     import oracle
     x, y = oracle.edge_points(image)
@@ -193,7 +216,7 @@ def main():
                                "device_total_with_events": kt["total_ms"]},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": measured_traffic(f"k_{dom}"),
                      "alg_bytes_per_step": kb[dom],
                      "other": {f"k_{k}": {"alg_bytes_per_step": kb[k], "ms_per_step": kms[k],
                                           "GB/s": kb[k] / (kms[k] / 1e3) / 1e9 if kms[k] > 0 else 0.0}
