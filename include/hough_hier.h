@@ -189,6 +189,20 @@ HH_API const char* hough_hier_last_error(const hh_ctx* ctx);
  * out of range), HH_ENOMEM, HH_EDEVICE, HH_EINTERNAL. */
 HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
 
+/* Run the vote on n inputs of one kind (all point lists or all images) in one
+ * call.  Every enabled pass of every input is its own quadtree (Sec. 3) and
+ * all trees share each level's launches, so a batch of small inputs pays the
+ * per-level launch cost once.  Each input keeps its own size, threshold and
+ * depth; the call runs to the deepest of them.  out[k] (an array of n
+ * handles owned by the caller) receives the result of inputs[k], with the
+ * same cells, members and statistics that hough_hier_detect(&inputs[k])
+ * returns.  Each handle is freed on its own; the device memory the handles
+ * share is released with the last of them.  n * (enabled passes) <= 2048.
+ * Errors: as hough_hier_detect; HH_EINVAL also for n < 1 or inputs of mixed
+ * kinds, HH_ECAPACITY for more than 2048 trees.  On an error no handle is
+ * returned (out[] is all NULL). */
+HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out);
+
 /* Cells of one pass (0 or 1), sorted by key.  on_device = 1 returns a device
  * pointer (member_off indexes the device members array); on_device = 0 copies
  * to host memory owned by the result (member_off indexes the host members

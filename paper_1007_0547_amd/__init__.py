@@ -95,10 +95,15 @@ _lib.hough_hier_last_error.restype = C.c_char_p
 _lib.hough_hier_last_error.argtypes = [_p]
 _lib.hough_hier_detect.restype = C.c_int
 _lib.hough_hier_detect.argtypes = [_p, C.POINTER(_Input), C.POINTER(_p)]
+_lib.hough_hier_detect_batch.restype = C.c_int
+_lib.hough_hier_detect_batch.argtypes = [_p, C.POINTER(_Input), C.c_int32, C.POINTER(_p)]
 _lib.hough_hier_result_cells.restype = C.c_int
 _lib.hough_hier_result_cells.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int64)]
 _lib.hough_hier_result_members.restype = C.c_int
 _lib.hough_hier_result_members.argtypes = [_p, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int64)]
+_lib.hough_hier_result_member_points.restype = C.c_int
+_lib.hough_hier_result_member_points.argtypes = [_p, C.POINTER(_p), C.POINTER(C.c_int64),
+                                                 C.POINTER(C.c_int32)]
 _lib.hough_hier_result_stats.restype = C.c_int
 _lib.hough_hier_result_stats.argtypes = [_p, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int32)]
 _lib.hough_hier_result_info.restype = C.c_int
@@ -176,6 +181,13 @@ class Result:
         self._check(_lib.hough_hier_result_members(self._h, 1, C.byref(ptr), C.byref(n)))
         return (ptr.value or 0), n.value
 
+    def member_points(self):
+        """``(device_pointer, entries, entry_bytes)`` of the voter entries as
+        the kernels left them (``hough_hier_result_member_points``)."""
+        ptr, n, eb = C.c_void_p(), C.c_int64(), C.c_int32()
+        self._check(_lib.hough_hier_result_member_points(self._h, C.byref(ptr), C.byref(n), C.byref(eb)))
+        return (ptr.value or 0), n.value, eb.value
+
     def stats(self, pass_: int) -> np.ndarray:
         """Per-level statistics (``STATS_DTYPE``), level 0 first."""
         ptr, n = C.c_void_p(), C.c_int32()
@@ -237,11 +249,10 @@ class HoughHier:
             return ""
         return (_lib.hough_hier_last_error(self._h) or b"").decode()
 
-    def detect(self, x=None, y=None, *, image=None, width: int, height: int,
-               threshold: int = -1, max_depth: Optional[int] = None) -> Result:
-        """Run the vote on a point list ``(x, y)`` or a binary ``image``
-        (H x W, nonzero = edge).  Torch device tensors are passed as device
-        pointers; anything else is copied from host memory."""
+    @staticmethod
+    def _input(x=None, y=None, *, image=None, width: int, height: int, threshold: int = -1,
+               max_depth: Optional[int] = None):
+        """An ``hh_input`` and the objects that must outlive the call."""
         inp = _Input()
         inp.width, inp.height = int(width), int(height)
         inp.threshold = int(threshold)
@@ -278,11 +289,40 @@ class HoughHier:
                 inp.x, inp.y = hx.ctypes.data, hy.ctypes.data
                 inp.n_points = int(hx.size)
                 keep += [hx, hy]
+        return inp, keep
+
+    def detect(self, x=None, y=None, *, image=None, width: int, height: int,
+               threshold: int = -1, max_depth: Optional[int] = None) -> Result:
+        """Run the vote on a point list ``(x, y)`` or a binary ``image``
+        (H x W, nonzero = edge).  Torch device tensors are passed as device
+        pointers; anything else is copied from host memory."""
+        inp, keep = self._input(x, y, image=image, width=width, height=height, threshold=threshold,
+                                max_depth=max_depth)
         out = C.c_void_p()
         s = _lib.hough_hier_detect(self._h, C.byref(inp), C.byref(out))
+        del keep
         if s != 0:
             raise HHError(s, self.last_error())
         return Result(self, out.value)
+
+    def detect_batch(self, inputs) -> list:
+        """Run the vote on several inputs of one kind in one call
+        (``hough_hier_detect_batch``).  ``inputs`` holds dicts with the
+        keyword arguments of :meth:`detect`; the results come in input
+        order."""
+        n = len(inputs)
+        arr = (_Input * n)()
+        keep = []
+        for k, d in enumerate(inputs):
+            inp, kp = self._input(**d)
+            arr[k] = inp
+            keep += kp
+        out = (C.c_void_p * n)()
+        s = _lib.hough_hier_detect_batch(self._h, arr, n, out)
+        del keep
+        if s != 0:
+            raise HHError(s, self.last_error())
+        return [Result(self, out[k]) for k in range(n)]
 
     def close(self):
         if self._h:

@@ -73,6 +73,16 @@ hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     return guarded(ctx, [&] { return hh::engine_detect(ctx, in, out); });
 }
 
+hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!inputs || !out) return fail(ctx, HH_EINVAL, "input and output pointers must not be NULL");
+    if (n < 1) return fail(ctx, HH_EINVAL, "a batch needs at least one input");
+    for (int32_t k = 0; k < n; ++k) out[k] = nullptr;
+    ctx->last_error.clear();
+    return guarded(ctx, [&] { return hh::engine_detect_batch(ctx, inputs, n, out); });
+}
+
 hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_device, const hh_cell** cells,
                                   int64_t* n)
 {
@@ -91,7 +101,13 @@ hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_devic
     if (!enabled) return HH_OK;
     const int64_t count = res->info.n_cells[pass];
     if (on_device) {
-        if (count > 0) *cells = reinterpret_cast<const hh_cell*>(res->cells) + before;
+        const hh::Cell* dc = nullptr;
+        hh_status s = guarded(res->ctx, [&] {
+            dc = hh::engine_device_cells(res);
+            return HH_OK;
+        });
+        if (s != HH_OK) return s;
+        if (count > 0) *cells = reinterpret_cast<const hh_cell*>(dc) + before;
         *n = count;
         return HH_OK;
     }

@@ -228,6 +228,10 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
         check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
         check(hipHostMalloc((void**)&ctx->h_trees, kMaxTrees * sizeof(TreeDesc), hipHostMallocDefault),
               "hipHostMalloc");
+        check(hipHostMalloc((void**)&ctx->h_images, kMaxTrees * sizeof(ImageDesc), hipHostMallocDefault),
+              "hipHostMalloc");
+        check(hipHostMalloc((void**)&ctx->h_lists, kMaxTrees * sizeof(PointsDesc), hipHostMallocDefault),
+              "hipHostMalloc");
         if (cfg->flags & HH_FLAG_TIMING) {
             ctx->events.resize(3 + 4 * kMaxLevels, nullptr);
             for (auto& e : ctx->events) check(hipEventCreate(&e), "hipEventCreate");
@@ -251,6 +255,8 @@ void engine_destroy(hh_ctx* ctx)
     ctx->live_results.clear();
     if (ctx->h_fixed) (void)hipHostFree(ctx->h_fixed);
     if (ctx->h_trees) (void)hipHostFree(ctx->h_trees);
+    if (ctx->h_images) (void)hipHostFree(ctx->h_images);
+    if (ctx->h_lists) (void)hipHostFree(ctx->h_lists);
     delete ctx;
 }
 
@@ -331,90 +337,233 @@ void grow_sizes(hh_ctx* ctx, const LevelInfo* info, int32_t dmax, int32_t entry_
 
 }  // namespace
 
+namespace {
+
+// Host-side view of one image of a call.
+struct ImagePlan {
+    Plan plan;
+    int32_t kind;
+    int64_t n_points;          // point lists: from the input; images: known after the call
+    int64_t xy_base;           // point lists: position of its points
+};
+
+// Statistics of one tree from the level and tree records (levels 0 .. D):
+// level 0 is the root; level l+1 sums the parents of the tree at level l,
+// delimited by the tree's record and the next tree's record at level l (or
+// the level totals for the last tree).
+std::vector<hh_level_stats> tree_stats(const LevelInfo* info, const int64_t* rec, int32_t t, int32_t n_trees,
+                                       int32_t D, int64_t E, int32_t T)
+{
+    std::vector<hh_level_stats> v((size_t)D + 1, hh_level_stats{});
+    const bool root_votes = E > T;   // every line crosses the root (code 0011)
+    v[0].evaluated = 1;
+    v[0].votes = E;
+    v[0].code_tests = E;
+    if (root_votes && D > 0) {
+        v[0].split = 1;
+        v[0].entries = E;
+    }
+    if (root_votes && D == 0) v[0].detected = 1;
+    for (int l = 0; l < D; ++l) {
+        const int64_t* r = rec + ((int64_t)t * kMaxLevels + l) * kRecCh;
+        if (r[0] < 0) continue;   // the tree had no parent at level l
+        int64_t nx[kRecCh] = {info[l].P, info[l].L, info[l + 1].P, info[l + 1].L, info[l + 1].cells,
+                              info[l].votes, info[l + 1].mem};
+        for (int t2 = t + 1; t2 < n_trees; ++t2) {
+            const int64_t* r2 = rec + ((int64_t)t2 * kMaxLevels + l) * kRecCh;
+            if (r2[0] >= 0) {
+                for (int c = 0; c < kRecCh; ++c) nx[c] = r2[c];
+                break;
+            }
+        }
+        hh_level_stats& s = v[(size_t)l + 1];
+        s.evaluated = 4 * (nx[0] - r[0]);
+        s.code_tests = 4 * (nx[1] - r[1]);
+        s.split = nx[2] - r[2];
+        s.entries = nx[3] - r[3];
+        s.detected = nx[4] - r[4];
+        s.votes = nx[5] - r[5];
+    }
+    return v;
+}
+
+// [lo, hi) of the tree's cells (channel 4) or member entries (channel 6) at
+// its finest level D, in the call's numbering.
+void tree_range(const LevelInfo* info, const int64_t* rec, int32_t t, int32_t n_trees, int32_t D, int ch,
+                int64_t& lo, int64_t& hi)
+{
+    const int l = D - 1;
+    const int64_t base = ch == 4 ? info[D].cells_base : info[D].mem_base;
+    const int64_t total = ch == 4 ? info[D].cells : info[D].mem;
+    const int64_t* r = rec + ((int64_t)t * kMaxLevels + l) * kRecCh;
+    lo = hi = -1;
+    if (r[0] < 0) return;
+    lo = base + r[ch];
+    hi = base + total;
+    for (int t2 = t + 1; t2 < n_trees; ++t2) {
+        const int64_t* r2 = rec + ((int64_t)t2 * kMaxLevels + l) * kRecCh;
+        if (r2[0] >= 0) {
+            hi = base + r2[ch];
+            break;
+        }
+    }
+}
+
+}  // namespace
+
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
 {
-    std::unique_ptr<hh_result> res(new (std::nothrow) hh_result());
-    if (!res) return HH_ENOMEM;
-    res->ctx = ctx;
+    return engine_detect_batch(ctx, in, 1, out);
+}
+
+hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out)
+{
     hipStream_t st = ctx->stream;
     DevicePool* pool = &ctx->pool;
     check(hipSetDevice(ctx->device), "hipSetDevice");
-    const Plan plan = make_plan(ctx, in);
     const bool timing = !ctx->events.empty();
+    const uint32_t passes = ctx->cfg.passes;
+    const int32_t n_pass = __builtin_popcount(passes);
+    if (n < 1) throw Error{HH_EINVAL, "a call needs at least one input"};
+    if ((int64_t)n * n_pass > kMaxTrees) throw Error{HH_ECAPACITY, "too many images in one call"};
+    const int32_t n_trees = n * n_pass;
 
-    // ---- validate the input form; bring host data to the device
-    DevBuf hx, hy, himg, tcount, tpre;
-    const int32_t* dx = nullptr;
-    const int32_t* dy = nullptr;
-    const uint8_t* dimg = nullptr;
-    int64_t dstride = 0, n_pix = 0, E_host = -1;
-    int32_t entry_bytes = 4;
-    if (in->kind == 0) {
-        if (in->n_points < 0 || in->n_points > INT32_MAX) throw Error{HH_EINVAL, "bad n_points"};
-        E_host = in->n_points;
-        entry_bytes = 8;   // point lists keep their own ids (duplicates and any order allowed)
-        if (E_host > 0 && (!in->x || !in->y)) throw Error{HH_EINVAL, "x and y must not be NULL"};
-        if (in->on_device) {
-            dx = in->x;
-            dy = in->y;
-        } else {
-            for (int64_t k = 0; k < E_host; ++k)
-                if (in->x[k] < 0 || in->x[k] >= plan.W || in->y[k] < 0 || in->y[k] >= plan.H)
-                    throw Error{HH_EINVAL, "point " + std::to_string(k) + " outside the image"};
-            hx = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
-            hy = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
-            if (E_host > 0) {
-                check(hipMemcpyAsync(hx.get(), in->x, (size_t)E_host * 4, hipMemcpyHostToDevice, st), "copy x");
-                check(hipMemcpyAsync(hy.get(), in->y, (size_t)E_host * 4, hipMemcpyHostToDevice, st), "copy y");
+    // ---- plans; every input of a call is of one kind
+    std::vector<ImagePlan> ip((size_t)n);
+    int32_t dmax_all = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const hh_input* in = &inputs[k];
+        ip[(size_t)k].plan = make_plan(ctx, in);
+        ip[(size_t)k].kind = in->kind;
+        if (in->kind != 0 && in->kind != 1) throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
+        if (in->kind != inputs[0].kind) throw Error{HH_EINVAL, "all inputs of a call must be of one kind"};
+        dmax_all = std::max(dmax_all, ip[(size_t)k].plan.dmax);
+    }
+    const Plan& p0 = ip[0].plan;   // variant, compares and membership are the context's
+    const int32_t kind = inputs[0].kind;
+    const int32_t entry_bytes = kind == 0 ? 8 : 4;   // point lists keep their own ids
+
+    auto store = std::make_shared<CallStore>();
+    DevBuf hx, hy, himg, tcount, tpre, d_desc;
+    int64_t n_tiles = 0, total_points = 0;
+    if (kind == 0) {
+        // point lists: host lists are gathered into one upload
+        int64_t host_points = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const hh_input* in = &inputs[k];
+            if (in->n_points < 0 || in->n_points > INT32_MAX) throw Error{HH_EINVAL, "bad n_points"};
+            if (in->n_points > 0 && (!in->x || !in->y)) throw Error{HH_EINVAL, "x and y must not be NULL"};
+            if (!in->on_device) {
+                for (int64_t q = 0; q < in->n_points; ++q)
+                    if (in->x[q] < 0 || in->x[q] >= in->width || in->y[q] < 0 || in->y[q] >= in->height)
+                        throw Error{HH_EINVAL, "point " + std::to_string(q) + " of input " + std::to_string(k) +
+                                                   " outside the image"};
+                host_points += in->n_points;
             }
-            dx = hx.as<int32_t>();
-            dy = hy.as<int32_t>();
+            ip[(size_t)k].n_points = in->n_points;
+            ip[(size_t)k].xy_base = total_points;
+            total_points += in->n_points;
         }
-        res->points = DevBuf(pool, (size_t)std::max<int64_t>(E_host, 1) * 4);
-    } else if (in->kind == 1) {
-        if (!in->image) throw Error{HH_EINVAL, "image must not be NULL"};
-        const int64_t stride = in->row_stride ? in->row_stride : plan.W;
-        if (stride < plan.W) throw Error{HH_EINVAL, "row_stride < width"};
-        n_pix = (int64_t)plan.W * plan.H;
-        dimg = in->image;
-        dstride = stride;
-        if (!in->on_device) {
-            himg = DevBuf(pool, (size_t)n_pix);
-            check(hipMemcpy2DAsync(himg.get(), (size_t)plan.W, in->image, (size_t)stride, (size_t)plan.W,
-                                   (size_t)plan.H, hipMemcpyHostToDevice, st),
-                  "copy image");
-            dimg = himg.as<uint8_t>();
-            dstride = plan.W;
+        if (host_points > 0) {
+            std::vector<int32_t> hxv((size_t)host_points), hyv((size_t)host_points);
+            int64_t at = 0;
+            for (int32_t k = 0; k < n; ++k) {
+                const hh_input* in = &inputs[k];
+                if (in->on_device || in->n_points == 0) continue;
+                std::copy(in->x, in->x + in->n_points, hxv.begin() + at);
+                std::copy(in->y, in->y + in->n_points, hyv.begin() + at);
+                at += in->n_points;
+            }
+            hx = DevBuf(pool, (size_t)host_points * 4);
+            hy = DevBuf(pool, (size_t)host_points * 4);
+            check(hipMemcpyAsync(hx.get(), hxv.data(), (size_t)host_points * 4, hipMemcpyHostToDevice, st), "copy x");
+            check(hipMemcpyAsync(hy.get(), hyv.data(), (size_t)host_points * 4, hipMemcpyHostToDevice, st), "copy y");
+            check(hipStreamSynchronize(st), "copy points");   // the host vectors end here
         }
-        res->points = DevBuf(pool, (size_t)n_pix * 4);
-        const int64_t nt = cdiv(n_pix, kPixTile);
-        tcount = DevBuf(pool, (size_t)nt * 4);
-        tpre = DevBuf(pool, (size_t)nt * 8);
+        int64_t at = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const hh_input* in = &inputs[k];
+            PointsDesc& d = ctx->h_lists[k];
+            d.x = in->on_device ? in->x : hx.as<int32_t>() + at;
+            d.y = in->on_device ? in->y : hy.as<int32_t>() + at;
+            if (!in->on_device) at += in->n_points;
+            d.n = in->n_points;
+            d.base = ip[(size_t)k].xy_base;
+            d.width = in->width;
+            d.height = in->height;
+        }
+        d_desc = DevBuf(pool, sizeof(PointsDesc) * (size_t)n);
+        check(hipMemcpyAsync(d_desc.get(), ctx->h_lists, sizeof(PointsDesc) * (size_t)n, hipMemcpyHostToDevice, st),
+              "copy point lists");
+        store->points = DevBuf(pool, (size_t)std::max<int64_t>(total_points, 1) * 4);
     } else {
-        throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
+        // binary images: host images are packed into one upload
+        int64_t host_bytes = 0, pix_all = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const hh_input* in = &inputs[k];
+            if (!in->image) throw Error{HH_EINVAL, "image must not be NULL"};
+            const int64_t stride = in->row_stride ? in->row_stride : in->width;
+            if (stride < in->width) throw Error{HH_EINVAL, "row_stride < width"};
+            if (!in->on_device) host_bytes += (int64_t)in->width * in->height;
+            pix_all += (int64_t)in->width * in->height;
+        }
+        if (host_bytes > 0) himg = DevBuf(pool, (size_t)host_bytes);
+        int64_t at = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const hh_input* in = &inputs[k];
+            const int64_t stride = in->row_stride ? in->row_stride : in->width;
+            ImageDesc& d = ctx->h_images[k];
+            d.width = in->width;
+            d.height = in->height;
+            d.n_pix = (int64_t)in->width * in->height;
+            d.tile0 = n_tiles;
+            n_tiles += cdiv(d.n_pix, kPixTile);
+            if (in->on_device) {
+                d.image = in->image;
+                d.row_stride = stride;
+            } else {
+                check(hipMemcpy2DAsync(himg.as<uint8_t>() + at, (size_t)in->width, in->image, (size_t)stride,
+                                       (size_t)in->width, (size_t)in->height, hipMemcpyHostToDevice, st),
+                      "copy image");
+                d.image = himg.as<uint8_t>() + at;
+                d.row_stride = in->width;
+                at += d.n_pix;
+            }
+            ip[(size_t)k].n_points = -1;
+        }
+        d_desc = DevBuf(pool, sizeof(ImageDesc) * (size_t)n);
+        check(hipMemcpyAsync(d_desc.get(), ctx->h_images, sizeof(ImageDesc) * (size_t)n, hipMemcpyHostToDevice, st),
+              "copy image table");
+        store->points = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
+        tcount = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 4);
+        tpre = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 8);
     }
-    res->entry_bytes = entry_bytes;
-    uint32_t* xy = res->points.as<uint32_t>();
+    uint32_t* xy = store->points.as<uint32_t>();
 
-    // ---- trees (one per enabled pass)
-    int32_t n_trees = 0;
-    for (int p = 0; p < 2; ++p) {
-        if (!(plan.passes & (1u << p))) continue;
-        TreeDesc& t = ctx->h_trees[n_trees];
-        t.xy_base = 0;
-        t.n_points = E_host;   // image inputs: set on the device once the edges are counted
-        t.s_log2 = plan.s_log2;
-        t.dmax = plan.dmax;
-        t.threshold = plan.T;
-        t.pass = p;
-        t.image = 0;
-        t.pad = 0;
-        res->tree_pass[n_trees] = p;
-        ++n_trees;
+    // ---- trees: image k, enabled pass p
+    int32_t tree_pass[2] = {-1, -1};
+    {
+        int32_t t = 0;
+        for (int32_t k = 0; k < n; ++k)
+            for (int p = 0; p < 2; ++p) {
+                if (!(passes & (1u << p))) continue;
+                TreeDesc& T = ctx->h_trees[t++];
+                const Plan& pl = ip[(size_t)k].plan;
+                T.xy_base = kind == 0 ? ip[(size_t)k].xy_base : 0;   // images: set on the device
+                T.n_points = kind == 0 ? ip[(size_t)k].n_points : 0;
+                T.s_log2 = pl.s_log2;
+                T.dmax = pl.dmax;
+                T.threshold = pl.T;
+                T.pass = p;
+                T.image = k;
+                T.pad = 0;
+            }
+        int32_t c = 0;
+        for (int p = 0; p < 2; ++p)
+            if (passes & (1u << p)) tree_pass[c++] = p;
     }
-    res->n_trees = n_trees;
-    DevBuf d_trees(pool, sizeof(TreeDesc) * kMaxTrees);
-    check(hipMemcpyAsync(d_trees.get(), ctx->h_trees, sizeof(TreeDesc) * n_trees, hipMemcpyHostToDevice, st),
+    DevBuf d_trees(pool, sizeof(TreeDesc) * (size_t)n_trees);
+    check(hipMemcpyAsync(d_trees.get(), ctx->h_trees, sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyHostToDevice, st),
           "copy trees");
     const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
 
@@ -423,187 +572,197 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     Arena ar{};
     FixedLayout fl{};
     uint32_t err = 0;
+    hh_timing tm{};
     for (int attempt = 0;; ++attempt) {
         if (attempt >= 8) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
-        const Caps caps{ctx->cells_cap, plan.membership ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        const Caps caps{ctx->cells_cap, p0.membership ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
         fl = fixed_layout(n_trees, caps.cells);
         arena.reset();
         arena = DevBuf(pool, (size_t)arena_bytes(fl, caps, entry_bytes));
         ar = carve(arena.as<char>(), fl, n_trees, caps, entry_bytes);
-        res->timing = hh_timing{};
-        hh_timing& tm = res->timing;
+        tm = hh_timing{};
 
         mark(ctx, 0);
         check(launch_clear(ar, n_rec, st), "clear");
-        if (in->kind == 0) {
-            check(launch_pack_points(dx, dy, E_host, plan.W, plan.H, xy, ar.error, st), "pack");
+        if (kind == 0) {
+            check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, ar.error, st), "pack");
         } else {
             ExtractArgs ea{};
-            ea.image = dimg;
-            ea.row_stride = dstride;
-            ea.width = plan.W;
-            ea.height = plan.H;
-            ea.n_pix = n_pix;
+            ea.images = d_desc.as<ImageDesc>();
+            ea.n_images = n;
+            ea.n_tiles = n_tiles;
             ea.xy = xy;
             ea.tile_count = tcount.as<int32_t>();
             ea.tile_pre = tpre.as<int64_t>();
-            ea.n_tiles = (int32_t)cdiv(n_pix, kPixTile);
-            ea.total = ar.scalar;
+            ea.trees = d_trees.as<TreeDesc>();
+            ea.n_trees = n_trees;
             check(launch_extract(ea, st), "extract");
         }
         mark(ctx, 1);
-        check(launch_begin(ar, d_trees.as<TreeDesc>(), n_trees, E_host, plan.T, plan.dmax, xy, ctx->grid, st),
-              "begin");
+        check(launch_roots(ar, d_trees.as<TreeDesc>(), n_trees, xy, ctx->grid, st), "roots");
         LevelArgs la{};
         la.ar = ar;
         la.trees = d_trees.as<TreeDesc>();
         la.xy = xy;
-        la.keep_members = plan.membership ? 1 : 0;
-        const int count_grid = level_grid(0, plan.variant, plan.wide, entry_bytes, ctx->cu_count);
-        const int write_grid = level_grid(1, plan.variant, plan.wide, entry_bytes, ctx->cu_count);
-        for (int l = 0; l < plan.dmax; ++l) {
+        la.keep_members = p0.membership ? 1 : 0;
+        const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+        const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+        for (int l = 0; l < dmax_all; ++l) {
             la.level = l;
             mark(ctx, 3 + 4 * l);
-            check(launch_count(la, plan.variant, plan.wide, count_grid, st), "count");
+            check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
             mark(ctx, 4 + 4 * l);
             check(launch_decide(la, kRangeGrid, st), "decide");
             check(launch_emit(la, kRangeGrid, st), "emit");
             mark(ctx, 5 + 4 * l);
-            if (l + 1 < plan.dmax || plan.membership)
-                check(launch_write(la, write_grid, st), "write");
+            if (l + 1 < dmax_all || p0.membership) check(launch_write(la, write_grid, st), "write");
             mark(ctx, 6 + 4 * l);
         }
         mark(ctx, 2);
         check(hipMemcpyAsync(ctx->h_fixed, arena.get(), (size_t)fl.head_bytes, hipMemcpyDeviceToHost, st),
               "copy level records");
+        check(hipMemcpyAsync(ctx->h_trees, d_trees.get(), sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyDeviceToHost,
+                             st),
+              "copy trees back");
         sync(ctx);
         err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + fl.error);
         const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
         if (timing) {
             tm.total_ms = elapsed(ctx, 0, 2);
             tm.extract_ms = elapsed(ctx, 0, 1);
-            for (int l = 0; l < plan.dmax; ++l) {
+            for (int l = 0; l < dmax_all; ++l) {
                 const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
                 tm.count_ms += c;
                 tm.write_ms += w;
                 tm.vote_ms += c + w;
                 tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
             }
-            tm.vote_launches = plan.dmax + (plan.membership ? plan.dmax : plan.dmax - 1);
-            tm.decide_launches = 2 * plan.dmax;
+            tm.vote_launches = dmax_all + (p0.membership ? dmax_all : dmax_all - 1);
+            tm.decide_launches = 2 * dmax_all;
         }
-        for (int l = 0; l < plan.dmax; ++l) {
+        for (int l = 0; l < dmax_all; ++l) {
             tm.vote_entries += info[l].L;
-            if (l + 1 < plan.dmax) tm.vote_written += info[l + 1].L;
-            else if (plan.membership) tm.vote_written += info[l + 1].mem;
+            if (l + 1 < dmax_all) tm.vote_written += info[l + 1].L;
+            if (p0.membership) tm.vote_written += info[l + 1].mem;
         }
         if ((err & kErrArena) && !(err & (kErrPointRange | kErrInternal))) {
-            grow_sizes(ctx, info, plan.dmax, entry_bytes);
+            grow_sizes(ctx, info, dmax_all, entry_bytes);
             continue;
         }
         break;
     }
     if (err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
     if (err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
+    store->arena = std::move(arena);
 
     const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
     const int64_t* rec = reinterpret_cast<const int64_t*>(ctx->h_fixed + fl.rec);
-    const int64_t E = *reinterpret_cast<const int64_t*>(ctx->h_fixed + fl.scalar);
-    const bool root_votes = E > plan.T;   // every line crosses the root (code 0011)
+    const Cell* dcells = ar.cells;
 
-    int64_t n_cells_total = 0;
-    if (plan.dmax > 0) {
-        const int D = plan.dmax;
-        n_cells_total = info[D].cells_base + info[D].cells;
-        res->cells = ar.cells;
-        if (plan.membership) {
-            res->members = ar.members;
-            res->info.member_slots = info[D].mem_base + info[D].mem;
-        }
-    } else if (root_votes) {
-        // depth 0: the root is the finest region, every line votes for it
-        res->extra = DevBuf(pool, 256 + (size_t)E * (size_t)entry_bytes);
-        Cell* dcells = res->extra.as<Cell>();
-        std::vector<Cell> hc((size_t)n_trees);
-        for (int t = 0; t < n_trees; ++t) {
-            hc[(size_t)t].i = 0;
-            hc[(size_t)t].j = 0;
-            hc[(size_t)t].votes = (int32_t)E;
-            hc[(size_t)t].pass = res->tree_pass[t];
-            hc[(size_t)t].key = 0;
-            hc[(size_t)t].member_off = plan.membership ? 0 : -1;
-        }
-        check(hipMemcpyAsync(dcells, hc.data(), sizeof(Cell) * n_trees, hipMemcpyHostToDevice, st), "copy cells");
-        n_cells_total = n_trees;
-        res->cells = dcells;
-        res->depth0 = true;
-        if (plan.membership) {
-            // the root's voters are all points: ids 0..E-1
-            res->entry_bytes = 4;
-            res->dev_ids = DevBuf(pool, (size_t)std::max<int64_t>(E, 1) * 4);
-            check(launch_iota(res->dev_ids.as<int32_t>(), E, st), "iota");
-            res->members = xy;
-            res->info.member_slots = E;
-        }
-        sync(ctx);
-    }
-
-    res->info.n_points = E;
-    res->info.width = plan.W;
-    res->info.height = plan.H;
-    res->info.side_pow2 = (int32_t)plan.S;
-    res->info.depth = plan.dmax;
-    res->info.threshold = plan.T;
-    res->info.passes = plan.passes;
-    res->info.compare_bits = (plan.variant == HH_VARIANT_CIRCLE || plan.wide) ? 64 : 32;
-
-    // per-pass statistics: level 0 is the root; level l+1 sums the parents of
-    // the tree at level l, delimited by the tree records
-    int64_t code_tests = 0;
-    for (int t = 0; t < n_trees; ++t) {
-        const int p = res->tree_pass[t];
-        auto& v = res->stats[p];
-        v.assign((size_t)plan.dmax + 1, hh_level_stats{});
-        v[0].evaluated = 1;
-        v[0].votes = E;
-        v[0].code_tests = E;
-        if (root_votes && plan.dmax > 0) {
-            v[0].split = 1;
-            v[0].entries = E;
-        }
-        if (root_votes && plan.dmax == 0) v[0].detected = 1;
-        for (int l = 0; l < plan.dmax; ++l) {
-            const int64_t* r = rec + ((int64_t)t * kMaxLevels + l) * kRecCh;
-            if (r[0] < 0) continue;   // the tree had no parent at level l
-            int64_t nx[kRecCh] = {info[l].P, info[l].L, info[l + 1].P, info[l + 1].L, info[l + 1].cells,
-                                  info[l].votes};
-            for (int t2 = t + 1; t2 < n_trees; ++t2) {
-                const int64_t* r2 = rec + ((int64_t)t2 * kMaxLevels + l) * kRecCh;
-                if (r2[0] >= 0) {
-                    for (int c = 0; c < kRecCh; ++c) nx[c] = r2[c];
-                    break;
+    // ---- one result per image
+    std::vector<std::unique_ptr<hh_result>> res((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        auto r = std::make_unique<hh_result>();
+        r->ctx = ctx;
+        r->store = store;
+        r->n_trees = n_pass;
+        r->tree_pass[0] = tree_pass[0];
+        r->tree_pass[1] = tree_pass[1];
+        r->entry_bytes = entry_bytes;
+        r->have_members = p0.membership;
+        r->timing = tm;
+        const Plan& pl = ip[(size_t)k].plan;
+        const int32_t t0 = k * n_pass;
+        const int64_t E = ctx->h_trees[t0].n_points;
+        r->xy = xy + ctx->h_trees[t0].xy_base;
+        r->members_base = ar.members;
+        int64_t code_tests = 0, cells_lo = -1, cells_hi = -1, mem_lo = -1, mem_hi = -1;
+        for (int32_t q = 0; q < n_pass; ++q) {
+            const int32_t t = t0 + q;
+            const int p = tree_pass[q];
+            r->stats[p] = tree_stats(info, rec, t, n_trees, pl.dmax, E, pl.T);
+            for (const auto& lv : r->stats[p]) code_tests += lv.code_tests;
+            r->info.n_cells[p] = r->stats[p][(size_t)pl.dmax].detected;
+            if (pl.dmax > 0 && r->info.n_cells[p] > 0) {
+                int64_t lo, hi, mlo, mhi;
+                tree_range(info, rec, t, n_trees, pl.dmax, 4, lo, hi);
+                tree_range(info, rec, t, n_trees, pl.dmax, 6, mlo, mhi);
+                if (hi - lo != r->info.n_cells[p]) throw Error{HH_EINTERNAL, "cell count does not match the statistics"};
+                if (cells_lo < 0) {
+                    cells_lo = lo;
+                    mem_lo = mlo;
                 }
+                cells_hi = hi;
+                mem_hi = mhi;
             }
-            hh_level_stats& s = v[(size_t)l + 1];
-            s.evaluated = 4 * (nx[0] - r[0]);
-            s.code_tests = 4 * (nx[1] - r[1]);
-            s.split = nx[2] - r[2];
-            s.entries = nx[3] - r[3];
-            s.detected = nx[4] - r[4];
-            s.votes = nx[5] - r[5];
         }
-        for (const auto& lv : v) code_tests += lv.code_tests;
-        res->info.n_cells[p] = v[(size_t)plan.dmax].detected;
+        r->n_cells_total = r->info.n_cells[0] + r->info.n_cells[1];
+        if (pl.dmax > 0) {
+            r->cells = cells_lo >= 0 ? dcells + cells_lo : nullptr;
+            if (cells_lo >= 0 && cells_hi - cells_lo != r->n_cells_total)
+                throw Error{HH_EINTERNAL, "an image's cells are not contiguous"};
+            if (p0.membership && mem_lo >= 0) {
+                r->mem_base = mem_lo;
+                r->members = static_cast<const char*>(ar.members) + mem_lo * entry_bytes;
+                r->info.member_slots = mem_hi - mem_lo;
+            }
+        } else if (r->n_cells_total > 0) {
+            // depth 0: the root is the finest region; every line votes for it
+            r->depth0 = true;
+            r->depth0_cells = DevBuf(pool, sizeof(Cell) * (size_t)n_pass);
+            std::vector<Cell> hc;
+            for (int32_t q = 0; q < n_pass; ++q) {
+                if (r->info.n_cells[tree_pass[q]] == 0) continue;
+                Cell c{};
+                c.votes = (int32_t)E;
+                c.pass = tree_pass[q];
+                c.member_off = p0.membership ? 0 : -1;
+                hc.push_back(c);
+            }
+            check(hipMemcpyAsync(r->depth0_cells.get(), hc.data(), sizeof(Cell) * hc.size(), hipMemcpyHostToDevice,
+                                 st),
+                  "copy cells");
+            r->cells = r->depth0_cells.as<Cell>();
+            if (p0.membership) {
+                r->members = r->xy;   // the voters are all points, in order
+                r->entry_bytes = 4;
+                r->info.member_slots = E;
+            }
+            sync(ctx);
+        }
+        r->info.n_points = E;
+        r->info.width = pl.W;
+        r->info.height = pl.H;
+        r->info.side_pow2 = (int32_t)pl.S;
+        r->info.depth = pl.dmax;
+        r->info.threshold = pl.T;
+        r->info.passes = passes;
+        r->info.compare_bits = (p0.variant == HH_VARIANT_CIRCLE || p0.wide) ? 64 : 32;
+        r->info.code_tests = code_tests;
+        res[(size_t)k] = std::move(r);
     }
-    res->info.code_tests = code_tests;
-    res->n_cells_total = n_cells_total;
-    if (res->info.n_cells[0] + res->info.n_cells[1] != n_cells_total)
-        throw Error{HH_EINTERNAL, "cell count does not match the statistics"};
-    res->arena = std::move(arena);
-    res->have_members = plan.membership;
-    ctx->live_results.insert(res.get());
-    *out = res.release();
+    for (int32_t k = 0; k < n; ++k) {
+        out[k] = res[(size_t)k].release();
+        ctx->live_results.insert(out[k]);
+    }
     return HH_OK;
+}
+
+// Cells of a result whose member_off index this result's members (made on
+// request when its voters do not start the call's member buffer).
+const Cell* engine_device_cells(hh_result* res)
+{
+    if (res->depth0 || res->mem_base == 0 || !res->have_members || res->n_cells_total == 0) return res->cells;
+    if (!res->dev_cells) {
+        hh_ctx* ctx = res->ctx;
+        check(hipSetDevice(ctx->device), "hipSetDevice");
+        DevBuf d(&ctx->pool, sizeof(Cell) * (size_t)res->n_cells_total);
+        check(launch_rebase_cells(res->cells, res->n_cells_total, res->mem_base, d.as<Cell>(), ctx->stream),
+              "rebase cells");
+        sync(ctx);
+        res->dev_cells = std::move(d);
+    }
+    return res->dev_cells.as<Cell>();
 }
 
 hh_status engine_device_ids(hh_result* res)
@@ -613,9 +772,14 @@ hh_status engine_device_ids(hh_result* res)
     check(hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t slots = std::max<int64_t>(res->info.member_slots, 1);
     res->dev_ids = DevBuf(&ctx->pool, (size_t)slots * 4);
-    check(launch_member_ids(res->cells, res->n_cells_total, nullptr, res->members, res->entry_bytes,
-                            res->points.as<uint32_t>(), res->info.n_points, res->dev_ids.as<int32_t>(), ctx->stream),
-          "member ids");
+    if (res->depth0) {
+        check(launch_iota(res->dev_ids.as<int32_t>(), res->info.member_slots, ctx->stream), "iota");
+    } else {
+        check(launch_member_ids(res->cells, res->n_cells_total, nullptr, res->mem_base, res->members_base,
+                                res->entry_bytes, res->xy, res->info.n_points, res->dev_ids.as<int32_t>(),
+                                ctx->stream),
+              "member ids");
+    }
     sync(ctx);
     return HH_OK;
 }
@@ -640,20 +804,19 @@ hh_status engine_host_copy(hh_result* res)
         total += res->host_cells[(size_t)c].votes;
     }
     if (res->have_members && n > 0) {
-        DevBuf d_off(&ctx->pool, (size_t)n * 8);
-        DevBuf d_dst(&ctx->pool, (size_t)std::max<int64_t>(total, 1) * 4);
         res->host_members.resize((size_t)total);
         if (res->depth0) {   // every point votes for the root: ids 0 .. E-1 per cell
             for (int64_t c = 0; c < n; ++c)
                 for (int32_t k = 0; k < res->host_cells[(size_t)c].votes; ++k)
                     res->host_members[(size_t)(off[(size_t)c] + k)] = k;
         } else {
+            DevBuf d_off(&ctx->pool, (size_t)n * 8);
+            DevBuf d_dst(&ctx->pool, (size_t)std::max<int64_t>(total, 1) * 4);
             check(hipMemcpyAsync(d_off.get(), off.data(), (size_t)n * 8, hipMemcpyHostToDevice, st), "copy offsets");
-            check(launch_member_ids(res->cells, n, d_off.as<int64_t>(), res->members, res->entry_bytes,
-                                    res->points.as<uint32_t>(), res->info.n_points, d_dst.as<int32_t>(), st),
+            check(launch_member_ids(res->cells, n, d_off.as<int64_t>(), 0, res->members_base, res->entry_bytes,
+                                    res->xy, res->info.n_points, d_dst.as<int32_t>(), st),
                   "member ids");
-            check(hipMemcpyAsync(res->host_members.data(), d_dst.get(), (size_t)total * 4, hipMemcpyDeviceToHost,
-                                 st),
+            check(hipMemcpyAsync(res->host_members.data(), d_dst.get(), (size_t)total * 4, hipMemcpyDeviceToHost, st),
                   "copy members");
             sync(ctx);
         }

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -15,8 +16,6 @@
 #include "hh_types.hpp"
 
 namespace hh {
-
-constexpr int kMaxTrees = 2;
 
 // Caching allocator over hipMalloc.  Sizes are rounded up to one of eight
 // steps per power of two; freed blocks wait in per-size free lists and are
@@ -67,22 +66,37 @@ struct Error {
 
 }  // namespace hh
 
+namespace hh {
+
+// Device memory of one call, shared by the results of its images and
+// released with the last of them.
+struct CallStore {
+    DevBuf arena;              // levels, cells and the member buffer
+    DevBuf points;             // packed edge points, image after image
+};
+
+}  // namespace hh
+
+// The result of one image of a call.
 struct hh_result {
     hh_ctx* ctx = nullptr;
+    std::shared_ptr<hh::CallStore> store;
     hh_result_info info{};
     int32_t n_trees = 0;
     int32_t tree_pass[2] = {-1, -1};
     std::vector<hh_level_stats> stats[2];
-    hh::DevBuf arena;          // device memory of the call: cells and voter lists live here
-    hh::DevBuf points;         // packed edge points (row-major for image inputs)
-    hh::DevBuf extra;          // depth-0 results
-    hh::DevBuf dev_ids;        // point ids in the layout of `members` (made on request)
-    const hh::Cell* cells = nullptr;     // all cells, (pass, key) order
+    const hh::Cell* cells = nullptr;     // this image's cells, (pass, key) order, member_off into the call's buffer
     int64_t n_cells_total = 0;
-    const void* members = nullptr;       // voter entries of the cells, cell after cell
+    const void* members = nullptr;       // this image's voter entries, cell after cell
+    const void* members_base = nullptr;  // the call's member buffer
+    int64_t mem_base = 0;                // member_off of this image's first voter
+    const uint32_t* xy = nullptr;        // this image's packed edge points
     int32_t entry_bytes = 4;             // 4: packed point; 8: id << 32 | packed point
     bool have_members = false;
     bool depth0 = false;                 // the root is the only level: every point votes
+    hh::DevBuf depth0_cells;             // depth 0: the cells, made on the host
+    hh::DevBuf dev_cells;                // cells with member_off relative to this image (made on request)
+    hh::DevBuf dev_ids;                  // point ids in the layout of member_off (made on request)
     hh_timing timing{};
     // lazily filled host copies
     bool host_ready = false;
@@ -97,9 +111,12 @@ struct hh_ctx {
     std::string last_error;
     hh::DevicePool pool;
     int cu_count = 0;
-    // pinned host copy of an arena's fixed part (level records, tree records, error)
+    // pinned host copies: an arena's fixed part (level records, tree records,
+    // error), the trees of a call, the descriptors of its inputs
     char* h_fixed = nullptr;
     hh::TreeDesc* h_trees = nullptr;
+    hh::ImageDesc* h_images = nullptr;
+    hh::PointsDesc* h_lists = nullptr;
     // arena sizes that worked before (grown when a call overflows)
     int64_t half_cap = 64ll << 20;      // bytes per level half
     int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
@@ -118,7 +135,11 @@ namespace hh {
 hh_status engine_create(const hh_config* cfg, hh_ctx** out);
 void engine_destroy(hh_ctx* ctx);
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
+// n inputs in one call; out[k] is the result of in[k] (all or none are made)
+hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* in, int32_t n, hh_result** out);
 hh_status engine_host_copy(hh_result* res);
 hh_status engine_device_ids(hh_result* res);
+// The result's device cells with member_off counted from its own first voter.
+const Cell* engine_device_cells(hh_result* res);
 
 }  // namespace hh

@@ -920,6 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                     rc[3] = ex[1];
                     rc[4] = ex[2];
                     rc[5] = ex[4];
+                    rc[6] = ex[3];
                 }
             }
 #pragma unroll
@@ -1192,19 +1193,31 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     if (__any(bad) && lane == 0) raise_error(ar.error, kErrInternal);
 }
 
-// Edge staging: nonzero pixels of a row-major binary image in row-major order.
-__device__ inline uint32_t pixel_bits(const ExtractArgs& a, int64_t p0, int32_t& row, int32_t& col)
+// Edge staging: nonzero pixels of each image of a batch, row-major.  A
+// pixel tile (kPixTile pixels) belongs to one image, found by binary search
+// over the images' first tiles.
+__device__ inline int image_of_tile(const ImageDesc* images, int32_t n_images, int64_t tile)
+{
+    int lo = 0, hi = n_images - 1;   // last image with tile0 <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (images[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline uint32_t pixel_bits(const ImageDesc& im, int64_t p0, int32_t& row, int32_t& col)
 {
     uint32_t bits = 0;
     row = 0;
     col = 0;
-    if (p0 < a.n_pix) {
-        row = (int32_t)(p0 / a.width);
-        col = (int32_t)(p0 - (int64_t)row * a.width);
+    if (p0 < im.n_pix) {
+        row = (int32_t)(p0 / im.width);
+        col = (int32_t)(p0 - (int64_t)row * im.width);
         int32_t r = row, c = col;
-        for (int k = 0; k < kPixPerThread && p0 + k < a.n_pix; ++k) {
-            if (a.image[(int64_t)r * a.row_stride + c]) bits |= 1u << k;
-            if (++c == a.width) {
+        for (int k = 0; k < kPixPerThread && p0 + k < im.n_pix; ++k) {
+            if (im.image[(int64_t)r * im.row_stride + c]) bits |= 1u << k;
+            if (++c == im.width) {
                 c = 0;
                 ++r;
             }
@@ -1232,8 +1245,10 @@ __global__ __launch_bounds__(kBlock) void k_extract_count(ExtractArgs a)
 {
     __shared__ int32_t s_w[kWaves];
     for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const ImageDesc im = a.images[image_of_tile(a.images, a.n_images, tile)];
         int32_t row, col;
-        const uint32_t bits = pixel_bits(a, tile * kPixTile + (int64_t)threadIdx.x * kPixPerThread, row, col);
+        const uint32_t bits =
+            pixel_bits(im, (tile - im.tile0) * kPixTile + (int64_t)threadIdx.x * kPixPerThread, row, col);
         int32_t total;
         __syncthreads();
         block_excl_scan32(__popc(bits), s_w, total);
@@ -1241,40 +1256,54 @@ __global__ __launch_bounds__(kBlock) void k_extract_count(ExtractArgs a)
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_counts(const int32_t* cnt, int64_t n, int64_t* pre,
-                                                              int64_t* total)
+// One workgroup: exclusive prefix of the tile counts, then each tree's point
+// range (its image's first tile prefix and edge count).
+__global__ __launch_bounds__(kScanThreads) void k_scan_counts(ExtractArgs a)
 {
     __shared__ int64_t s_w[kScanThreads / kWave];
+    __shared__ int64_t s_total;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t n = a.n_tiles;
     const int64_t chunk = cdiv(n, kScanThreads);
     const int64_t b = std::min<int64_t>(n, tid * chunk), e = std::min<int64_t>(n, b + chunk);
     int64_t sum = 0;
-    for (int64_t t = b; t < e; ++t) sum += cnt[t];
+    for (int64_t t = b; t < e; ++t) sum += a.tile_count[t];
     const int64_t incl = wave_incl_scan64(sum, lane);
     if (lane == kWave - 1) s_w[wave] = incl;
     __syncthreads();
     int64_t run = incl - sum;
     for (int w = 0; w < wave; ++w) run += s_w[w];
     for (int64_t t = b; t < e; ++t) {
-        pre[t] = run;
-        run += cnt[t];
+        a.tile_pre[t] = run;
+        run += a.tile_count[t];
     }
-    if (tid == kScanThreads - 1) *total = run;
+    if (tid == kScanThreads - 1) s_total = run;
+    __syncthreads();   // tile_pre is complete (workgroup-scope ordering of global memory)
+    for (int t = tid; t < a.n_trees; t += kScanThreads) {
+        const int k = a.trees[t].image;
+        const int64_t lo = a.images[k].tile0 < n ? a.tile_pre[a.images[k].tile0] : s_total;
+        const int64_t hi = k + 1 < a.n_images && a.images[k + 1].tile0 < n ? a.tile_pre[a.images[k + 1].tile0]
+                                                                            : s_total;
+        a.trees[t].xy_base = lo;
+        a.trees[t].n_points = hi - lo;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_extract_write(ExtractArgs a)
 {
     __shared__ int32_t s_w[kWaves];
     for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const ImageDesc im = a.images[image_of_tile(a.images, a.n_images, tile)];
         int32_t row, col;
-        const uint32_t bits = pixel_bits(a, tile * kPixTile + (int64_t)threadIdx.x * kPixPerThread, row, col);
+        const uint32_t bits =
+            pixel_bits(im, (tile - im.tile0) * kPixTile + (int64_t)threadIdx.x * kPixPerThread, row, col);
         int32_t total;
         __syncthreads();
         int64_t pos = a.tile_pre[tile] + block_excl_scan32(__popc(bits), s_w, total);
         int32_t r = row, c = col;
         for (int k = 0; k < kPixPerThread; ++k) {
             if ((bits >> k) & 1u) a.xy[pos++] = pack_xy(c, r);
-            if (++c == a.width) {
+            if (++c == im.width) {
                 c = 0;
                 ++r;
             }
@@ -1293,33 +1322,67 @@ __global__ void k_clear(Arena ar, int64_t n_rec)
     if (g == 0) *ar.error = 0;
 }
 
-__global__ void k_pack_points(const int32_t* x, const int32_t* y, int64_t n, int32_t W, int32_t H,
-                              uint32_t* xy, uint32_t* error)
+__global__ void k_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t n_total, uint32_t* xy,
+                              uint32_t* error)
 {
     bool bad = false;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t xk = x[k], yk = y[k];
-        const bool outside = (xk < 0) | (xk >= W) | (yk < 0) | (yk >= H);
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_lists - 1;   // last list with base <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lists[mid].base <= g) lo = mid; else hi = mid - 1;
+        }
+        const PointsDesc d = lists[lo];
+        const int64_t k = g - d.base;
+        const int32_t xk = d.x[k], yk = d.y[k];
+        const bool outside = (xk < 0) | (xk >= d.width) | (yk < 0) | (yk >= d.height);
         bad |= outside;
-        xy[k] = outside ? 0u : pack_xy(xk, yk);
+        xy[g] = outside ? 0u : pack_xy(xk, yk);
     }
     if (__any(bad) && (threadIdx.x & (kWave - 1)) == 0) raise_error(error, kErrPointRange | kErrInternal);
 }
 
-// Root setup: level 0 holds one region per tree (the whole parameter space;
-// every line crosses it, code 0011) whose list is the tree's points in
-// input order.
-template <typename Entry>
-__global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
-                        int32_t dmax, const uint32_t* xy)
+// Root setup: level 0 holds one region per tree whose root splits (every
+// line crosses the root, code 0011, so it splits iff the tree has more than T
+// points and depth > 0), its list the tree's points in input order.
+// k_roots (one workgroup) lays the regions out; k_root_lists writes the lists
+// and the tile map.
+constexpr int kRootThreads = 1024;
+
+__global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc* trees, int32_t n_trees)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t E = n_points >= 0 ? n_points : ar.scalar[0];
-    const int64_t P0 = (E > threshold && dmax > 0) ? n_trees : 0;
-    const int64_t L0 = P0 * E;
-    if (g == 0) {
+    __shared__ int64_t s_w[kRootThreads / kWave][2];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr int kPer = kMaxTrees / kRootThreads;   // trees per thread
+    int64_t len[kPer], cnt = 0, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int t = tid * kPer + k;
+        len[k] = 0;
+        if (t < n_trees) {
+            const TreeDesc T = trees[t];
+            if (T.n_points > T.threshold && T.dmax > 0) len[k] = T.n_points;
+        }
+        cnt += len[k] > 0;
+        sum += len[k];
+    }
+    const int64_t ci = wave_incl_scan64(cnt, lane), si = wave_incl_scan64(sum, lane);
+    if (lane == kWave - 1) {
+        s_w[wave][0] = ci;
+        s_w[wave][1] = si;
+    }
+    __syncthreads();
+    int64_t r = ci - cnt, start = si - sum, P0 = 0, L0 = 0;
+    for (int w = 0; w < kRootThreads / kWave; ++w) {
+        if (w < wave) {
+            r += s_w[w][0];
+            start += s_w[w][1];
+        }
+        P0 += s_w[w][0];
+        L0 += s_w[w][1];
+    }
+    if (tid == 0) {
         LevelInfo& in = ar.info[0];
         in.P = P0;
         in.L = L0;
@@ -1328,32 +1391,70 @@ __global__ void k_begin(Arena ar, TreeDesc* trees, int32_t n_trees, int64_t n_po
         in.cells_base = 0;
         in.mem = 0;
         in.mem_base = 0;
-        if (n_points >= 0) ar.scalar[0] = E;
     }
-    if (g < n_trees) trees[g].n_points = E;
     if (P0 == 0) return;
     const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
     if (hl.end > ar.half_cap || work_layout(ar.work, P0, L0).end > ar.work_cap) {
-        if (g == 0) raise_error(ar.error, kErrArena);
+        if (tid == 0) raise_error(ar.error, kErrArena);
         return;
     }
-    for (int64_t t = g; t < P0; t += stride) {
-        for (int q = 0; q < 4; ++q) hl.cv[t * 4 + q] = 0;
-        const int32_t pass = trees[t].pass, s_log2 = trees[t].s_log2, td = trees[t].dmax;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int t = tid * kPer + k;
+        if (len[k] == 0) continue;
+        const TreeDesc T = trees[t];
         Region R;
-        R.start = t * E;
+        R.start = start;
         R.ij = 0;
-        R.len = (int32_t)E;
-        R.tree = (int32_t)t;
-        R.meta = (pass ? kMetaPass : 0u) | ((uint32_t)s_log2 << kMetaSlogShift) | (td == 1 ? kMetaChildFinest : 0u);
-        hl.regions[t] = R;
-        hl.cc[t] = code_consts(R.ij, R.meta, 1);
+        R.len = (int32_t)len[k];
+        R.tree = t;
+        R.meta = (T.pass ? kMetaPass : 0u) | ((uint32_t)T.s_log2 << kMetaSlogShift) |
+                 (T.dmax == 1 ? kMetaChildFinest : 0u);
+        G(hl.regions)[r] = R;
+        G(hl.cc)[r] = code_consts(R.ij, R.meta, 1);
+        reinterpret_cast<int4*>(G(hl.cv))[r] = int4{0, 0, 0, 0};
+        ++r;
+        start += len[k];
     }
-    for (int64_t k = g; k < cdiv(L0, kTile); k += stride) hl.tile_first[k] = (int32_t)((k * kTile) / E);
-    Entry* const list = static_cast<Entry*>(hl.list);
-    for (int64_t k = g; k < L0; k += stride) {
-        const int64_t t = k / E;
-        list[k] = EntryOps<Entry>::root(xy + trees[t].xy_base, k - t * E, trees[t].pass != 0);
+}
+
+template <typename Entry>
+__global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc* trees, const uint32_t* xy)
+{
+    __shared__ int64_t s_start[kMaxTrees];
+    if (stopped(ar.error)) return;
+    const int64_t P0 = ar.info[0].P, L0 = ar.info[0].L;
+    if (P0 == 0) return;
+    const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    for (int64_t r = threadIdx.x; r < P0; r += kBlock) s_start[r] = regions[r].start;
+    __syncthreads();
+    auto region_of = [&](int64_t e) {   // last region with start <= e
+        int lo = 0, hi = (int)P0 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    for (int64_t t = g; t < cdiv(L0, kTile); t += stride) G(hl.tile_first)[t] = region_of(t * kTile);
+    Entry* const list = G(static_cast<Entry*>(hl.list));
+    int cur = -1;
+    int64_t lo = 0, hi = -1, base = 0;
+    bool swap = false;
+    for (int64_t e = g; e < L0; e += stride) {
+        if (e < lo || e >= hi) {
+            cur = region_of(e);
+            const Region R = regions[cur];
+            const TreeDesc T = trees[R.tree];
+            lo = R.start;
+            hi = R.start + R.len;
+            base = T.xy_base;
+            swap = T.pass != 0;
+        }
+        list[e] = EntryOps<Entry>::root(xy + base, e - lo, swap);
     }
 }
 
@@ -1374,8 +1475,8 @@ __device__ inline int32_t entry_id(uint32_t v, const uint32_t* xy, int64_t n_poi
 __device__ inline int32_t entry_id(uint64_t v, const uint32_t*, int64_t) { return (int32_t)(v >> 32); }
 
 template <typename Entry>
-__global__ void k_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, const Entry* src,
-                             const uint32_t* xy, int64_t n_points, int32_t* dst)
+__global__ void k_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, int64_t dst_base,
+                             const Entry* src, const uint32_t* xy, int64_t n_points, int32_t* dst)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -1383,8 +1484,17 @@ __global__ void k_member_ids(const Cell* cells, int64_t n_cells, const int64_t* 
          c += waves) {
         const Cell cell = cells[c];
         const Entry* s = src + cell.member_off;
-        int32_t* d = dst + (dst_off ? dst_off[c] : cell.member_off);
+        int32_t* d = dst + (dst_off ? dst_off[c] : cell.member_off - dst_base);
         for (int32_t k = lane; k < cell.votes; k += kWave) d[k] = entry_id(s[k], xy, n_points);
+    }
+}
+
+__global__ void k_rebase_cells(const Cell* src, int64_t n, int64_t base, Cell* dst)
+{
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        Cell x = src[c];
+        if (x.member_off >= 0) x.member_off -= base;
+        dst[c] = x;
     }
 }
 
@@ -1428,11 +1538,11 @@ hipError_t launch_clear(const Arena& ar, int64_t n_rec, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pack_points(const int32_t* x, const int32_t* y, int64_t n, int32_t W, int32_t H,
-                              uint32_t* xy, uint32_t* error, hipStream_t s)
+hipError_t launch_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t n_total, uint32_t* xy,
+                              uint32_t* error, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    k_pack_points<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, y, n, W, H, xy, error);
+    if (n_total <= 0) return hipSuccess;
+    k_pack_points<<<grid_for(n_total, kBlock), kBlock, 0, s>>>(lists, n_lists, n_total, xy, error);
     return hipGetLastError();
 }
 
@@ -1441,18 +1551,18 @@ hipError_t launch_extract(const ExtractArgs& a, hipStream_t s)
     if (a.n_tiles <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>(a.n_tiles, 2048);
     k_extract_count<<<grid, kBlock, 0, s>>>(a);
-    k_scan_counts<<<1, kScanThreads, 0, s>>>(a.tile_count, a.n_tiles, a.tile_pre, a.total);
+    k_scan_counts<<<1, kScanThreads, 0, s>>>(a);
     k_extract_write<<<grid, kBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
-                        int32_t dmax, const uint32_t* xy, int grid, hipStream_t s)
+hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy, int grid,
+                        hipStream_t s)
 {
-    if (ar.entry_bytes == 8)
-        k_begin<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, n_trees, n_points, threshold, dmax, xy);
-    else
-        k_begin<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, n_trees, n_points, threshold, dmax, xy);
+    if (n_trees > kMaxTrees) return hipErrorInvalidValue;
+    k_roots<<<1, kRootThreads, 0, s>>>(ar, trees, n_trees);
+    if (ar.entry_bytes == 8) k_root_lists<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, xy);
+    else k_root_lists<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, xy);
     return hipGetLastError();
 }
 
@@ -1514,16 +1624,24 @@ hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, const void* src,
-                             int entry_bytes, const uint32_t* xy, int64_t n_points, int32_t* dst, hipStream_t s)
+hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, int64_t dst_base,
+                             const void* src, int entry_bytes, const uint32_t* xy, int64_t n_points, int32_t* dst,
+                             hipStream_t s)
 {
     if (n_cells <= 0) return hipSuccess;
     if (entry_bytes == 8)
         k_member_ids<uint64_t><<<grid_for(n_cells, kWaves), kBlock, 0, s>>>(
-            cells, n_cells, dst_off, static_cast<const uint64_t*>(src), xy, n_points, dst);
+            cells, n_cells, dst_off, dst_base, static_cast<const uint64_t*>(src), xy, n_points, dst);
     else
         k_member_ids<uint32_t><<<grid_for(n_cells, kWaves), kBlock, 0, s>>>(
-            cells, n_cells, dst_off, static_cast<const uint32_t*>(src), xy, n_points, dst);
+            cells, n_cells, dst_off, dst_base, static_cast<const uint32_t*>(src), xy, n_points, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebase_cells(const Cell* src, int64_t n, int64_t base, Cell* dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_rebase_cells<<<grid_for(n, kBlock), kBlock, 0, s>>>(src, n, base, dst);
     return hipGetLastError();
 }
 

@@ -17,31 +17,36 @@ struct LevelArgs {
     int32_t keep_members;      // 0: detected cells get member_off = -1 and keep no voters
 };
 
+// Edge staging of a batch of binary images: the nonzero pixels of image k,
+// row-major, become its packed points at xy[trees' xy_base], and every tree of
+// image k (tree.image == k) receives its point range.
 struct ExtractArgs {
-    const uint8_t* image;
-    int64_t row_stride;
-    int32_t width, height;
-    int64_t n_pix;
-    uint32_t* xy;              // packed output points
+    const ImageDesc* images;
+    int32_t n_images;
+    int64_t n_tiles;           // pixel tiles of all images
+    uint32_t* xy;              // packed output points, image after image
     int32_t* tile_count;       // [n_tiles] edge pixels per tile
     int64_t* tile_pre;         // [n_tiles] exclusive prefix of tile_count
-    int32_t n_tiles;
-    int64_t* total;            // edge count
+    TreeDesc* trees;
+    int32_t n_trees;
 };
 
 // Zero the fixed part of an arena (level records, error word, scratch) and
 // mark every tree record as absent.
 hipError_t launch_clear(const Arena& ar, int64_t n_rec, hipStream_t s);
-hipError_t launch_pack_points(const int32_t* x, const int32_t* y, int64_t n, int32_t W, int32_t H,
-                              uint32_t* xy, uint32_t* error, hipStream_t s);
+// Pack the point lists of a batch (total points n_total) into xy; a point
+// outside its image raises kErrPointRange.
+hipError_t launch_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t n_total, uint32_t* xy,
+                              uint32_t* error, hipStream_t s);
 // Edge staging in three launches: edge pixels per tile, their exclusive
-// prefix, then the row-major compaction.
+// prefix (which also fills the trees' point ranges), then the row-major
+// compaction.
 hipError_t launch_extract(const ExtractArgs& a, hipStream_t s);
-// Root setup: level-0 sizes, root regions, tile map and root lists.
-// n_points < 0 takes the edge count from ar.scalar[0] (left there by the
-// edge staging).
-hipError_t launch_begin(const Arena& ar, TreeDesc* trees, int32_t n_trees, int64_t n_points, int32_t threshold,
-                        int32_t dmax, const uint32_t* xy, int grid, hipStream_t s);
+// Root setup: level-0 sizes and root regions of every tree whose root splits
+// (more than T points and depth > 0), from the trees' point ranges; then the
+// root lists (the trees' points in input order) and the level-0 tile map.
+hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy, int grid,
+                        hipStream_t s);
 // One level: child-vote counts per tile, per-region totals and decisions,
 // the next level's tables, then the compaction of the voters of the kept
 // children (skipped by the host at the finest level without members).
@@ -53,10 +58,14 @@ hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hi
 hipError_t launch_decide(const LevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s);
-// Point ids of the voters of detected cells (see k_member_ids): into the
-// member buffer's layout (dst_off == nullptr) or compacted at dst_off[c].
-hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, const void* src,
-                             int entry_bytes, const uint32_t* xy, int64_t n_points, int32_t* dst, hipStream_t s);
+// Point ids of the voters of detected cells (see k_member_ids): cell c's
+// voters are src[cells[c].member_off ...]; they go to dst[dst_off[c] ...], or
+// with dst_off == nullptr to dst[cells[c].member_off - dst_base ...].
+hipError_t launch_member_ids(const Cell* cells, int64_t n_cells, const int64_t* dst_off, int64_t dst_base,
+                             const void* src, int entry_bytes, const uint32_t* xy, int64_t n_points, int32_t* dst,
+                             hipStream_t s);
+// dst[c] = src[c] with member_off - base (cells whose member_off < 0 keep it).
+hipError_t launch_rebase_cells(const Cell* src, int64_t n, int64_t base, Cell* dst, hipStream_t s);
 hipError_t launch_iota(int32_t* dst, int64_t n, hipStream_t s);
 
 }  // namespace hh

@@ -20,8 +20,9 @@ constexpr int kPixTile = kBlock * kPixPerThread;
 constexpr int kMaxLevels = 16;              // depth <= 15
 constexpr int kNumStats = 6;                // evaluated, votes, split, detected, code_tests, entries
 constexpr int kAggCh = 5;                   // decision sums: next regions, next entries, cells, member entries, votes
-constexpr int kRecCh = 6;                   // tree record: p, start, then the decision prefixes
+constexpr int kRecCh = 7;                   // tree record: p, start, then the decision prefixes
 constexpr int kRangeGrid = 512;             // region ranges of the split-decision launches
+constexpr int kMaxTrees = 2048;             // trees (image passes) in one call
 
 // Error bits set by kernels (the host reports them after the call).
 constexpr uint32_t kErrPointRange = 2u;     // an input point lies outside [0,W)x[0,H)
@@ -41,8 +42,28 @@ struct TreeDesc {
     int32_t dmax;       // finest level
     int32_t threshold;  // a region splits (or is detected) iff votes > threshold
     int32_t pass;       // 0: (u, v) = (x, y); 1: (u, v) = (y, x)
-    int32_t image;
+    int32_t image;      // index of the image in its batch
     int32_t pad;
+};
+
+// One point list of a batch: n points (x[k], y[k]) in [0, W) x [0, H), packed
+// to xy[base + k].
+struct PointsDesc {
+    const int32_t* x;
+    const int32_t* y;
+    int64_t n;
+    int64_t base;
+    int32_t width, height;
+};
+
+// One image of a batch for the edge staging: its pixel tiles are
+// tile0 .. tile0 + ceil(n_pix / kPixTile) - 1 of the batch's tile range.
+struct ImageDesc {
+    const uint8_t* image;
+    int64_t row_stride;
+    int32_t width, height;
+    int64_t tile0;
+    int64_t n_pix;
 };
 
 // Region.meta bits
