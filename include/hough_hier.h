@@ -102,7 +102,10 @@ typedef struct {
     void* stream;             /* hipStream_t for all work, or NULL for the null stream  */
     int32_t flags;            /* HH_FLAG_*                                              */
     int32_t reserved0;
-    uint64_t reserved1;
+    uint64_t arena_hint;      /* initial bytes of each level-list half of a call's arena
+                                 (0: 64 MiB); the other parts start in proportion.  A
+                                 call whose levels outgrow the arena continues in a
+                                 larger one, and later calls keep the larger sizes.   */
 } hh_config;
 
 typedef struct {

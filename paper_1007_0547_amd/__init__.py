@@ -56,7 +56,7 @@ class _Config(C.Structure):
     _fields_ = [("threshold", C.c_int32), ("max_depth", C.c_int32), ("passes", C.c_uint32),
                 ("variant", C.c_int32), ("membership", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("flags", C.c_int32), ("reserved0", C.c_int32),
-                ("reserved1", C.c_uint64)]
+                ("arena_hint", C.c_uint64)]
 
 
 class _Input(C.Structure):
@@ -220,7 +220,8 @@ class HoughHier:
 
     def __init__(self, threshold: int = 0, max_depth: int = 0, passes: int = 3,
                  variant: str = "code", membership: bool = True, device: int = 0,
-                 stream=None, wide_compare: bool = False, timing: bool = False):
+                 stream=None, wide_compare: bool = False, timing: bool = False,
+                 arena_hint: int = 0):
         cfg = _Config()
         cfg.threshold = int(threshold)
         cfg.max_depth = int(max_depth)
@@ -230,6 +231,7 @@ class HoughHier:
         cfg.device = int(device)
         cfg.stream = self._stream_handle(stream)
         cfg.flags = (1 if wide_compare else 0) | (2 if timing else 0)
+        cfg.arena_hint = int(arena_hint)
         h = C.c_void_p()
         s = _lib.hough_hier_create(C.byref(cfg), C.byref(h))
         if s != 0:

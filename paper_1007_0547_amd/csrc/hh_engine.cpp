@@ -198,6 +198,9 @@ Arena carve(char* base, const FixedLayout& f, int32_t n_trees, const Caps& c, in
     a.work_cap = c.work;
     a.n_trees = n_trees;
     a.entry_bytes = entry_bytes;
+    for (const void* q : {(const void*)a.cells, (const void*)a.members, (const void*)a.half[0], (const void*)a.half[1],
+                          (const void*)a.work})
+        if (reinterpret_cast<uintptr_t>(q) & 255u) throw Error{HH_EINTERNAL, "arena part not 256-byte aligned"};
     return a;
 }
 
@@ -223,6 +226,13 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
             throw Error{HH_EDEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950"};
         ctx->cu_count = prop.multiProcessorCount;
+        if (cfg->arena_hint) {
+            const int64_t h = std::max<int64_t>(4096, align256((int64_t)std::min<uint64_t>(cfg->arena_hint, 1ull << 40)));
+            ctx->half_cap = h;
+            ctx->work_cap = std::max<int64_t>(4096, align256(h / 4));
+            ctx->mem_cap = std::max<int64_t>(1024, h / 16);
+            ctx->cells_cap = std::max<int64_t>(256, h / 256);
+        }
         ctx->grid = std::max(1, ctx->cu_count) * 8;
         const FixedLayout f = fixed_layout(kMaxTrees, 0);
         check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
@@ -301,38 +311,38 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
     return p;
 }
 
-// After an arena overflow: size the arena from the level records the call
-// left.  Levels up to the failure are exact (a split decision records the
-// next level's sizes before it checks that they fit); deeper levels are
-// estimated: a full tree doubles its list length per level.
-void grow_sizes(hh_ctx* ctx, const LevelInfo* info, int32_t dmax, int32_t entry_bytes)
+// The stage of a call whose sizes did not fit the caps c, from the level
+// records the call left (the same checks the kernels make): -1 the root setup
+// (level 0), l >= 0 the split decision of level l (its children's sizes are
+// in info[l + 1]), -2 if every recorded size fits.
+int failing_stage(const LevelInfo* info, int32_t dmax, const Caps& c, bool members, int32_t eb)
 {
-    int64_t need_half = 0, need_work = 0, need_cells = 0, need_mem = 0;
-    int last = -1;
-    for (int l = 0; l <= dmax && l < kMaxLevels; ++l) {
-        if (l > 0 && info[l].P <= 0 && info[l].cells <= 0) break;
-        last = l;
-        need_half = std::max(need_half, half_layout(nullptr, info[l].P, info[l].L, entry_bytes).end);
-        need_work = std::max(need_work, work_layout(nullptr, info[l].P, info[l].L).end);
-        need_cells = std::max(need_cells, info[l].cells_base + info[l].cells);
-        need_mem = std::max(need_mem, info[l].mem_base + info[l].mem);
-    }
-    const int64_t growth = last >= 0 ? ((int64_t)1 << std::max(0, dmax - last)) : 4;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-        (void)hipGetLastError();
-        total_b = (size_t)1 << 40;
-    }
-    const int64_t limit = (int64_t)((double)total_b * 0.3);
-    auto grow = [&](int64_t cur, int64_t need) {
-        const int64_t want = need * growth + need / 4;
-        return std::min(std::max(cur * 2, want), std::max(limit, cur));
+    auto fits = [&](const LevelInfo& x) {
+        return half_layout(nullptr, x.P, x.L, eb).end <= c.half && work_layout(nullptr, x.P, x.L).end <= c.work;
     };
-    ctx->half_cap = grow(ctx->half_cap, need_half);
-    ctx->work_cap = grow(ctx->work_cap, need_work);
-    ctx->mem_cap = std::min(std::max(ctx->mem_cap * 2, (need_mem + need_half / entry_bytes) * 2),
-                            std::max(limit / entry_bytes, ctx->mem_cap));
-    ctx->cells_cap = std::max(ctx->cells_cap * 2, need_cells * 2 + 4 * info[std::max(last, 0)].P);
+    if (!fits(info[0])) return -1;
+    for (int l = 0; l < dmax; ++l) {
+        const LevelInfo& x = info[l + 1];
+        if (!fits(x) || x.cells_base + x.cells > c.cells || (members && x.mem_base + x.mem > c.mem)) return l;
+    }
+    return -2;
+}
+
+// Caps that hold the sizes x of the failing stage: each size that did not
+// fit becomes `factor` times its need (the next levels are not known yet; a
+// later overflow resumes again), rounded so that every part of an arena
+// starts on a 256-byte boundary.
+Caps grown_caps(const Caps& c, const LevelInfo& x, bool members, int32_t eb, double factor)
+{
+    auto grow = [&](int64_t cur, int64_t need) {
+        return need <= cur ? cur : align256((int64_t)((double)need * factor));
+    };
+    Caps g = c;
+    g.half = grow(c.half, half_layout(nullptr, x.P, x.L, eb).end);
+    g.work = grow(c.work, work_layout(nullptr, x.P, x.L).end);
+    g.cells = grow(c.cells, x.cells_base + x.cells);
+    if (members) g.mem = grow(c.mem, x.mem_base + x.mem);
+    return g;
 }
 
 }  // namespace
@@ -567,55 +577,92 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
           "copy trees");
     const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
 
-    // ---- the call, repeated with a larger arena if a level overflowed
+    // ---- the call.  When a level does not fit the arena, the call resumes
+    // at that level in a larger arena holding a copy of everything the
+    // finished stages left (level records, cells, voters, the level's tables,
+    // list and count results); a failure of the root setup reruns it.
+    const bool members = p0.membership;
     DevBuf arena;
     Arena ar{};
     FixedLayout fl{};
+    Caps caps{};
     uint32_t err = 0;
     hh_timing tm{};
-    for (int attempt = 0;; ++attempt) {
-        if (attempt >= 8) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
-        const Caps caps{ctx->cells_cap, p0.membership ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
-        fl = fixed_layout(n_trees, caps.cells);
-        arena.reset();
-        arena = DevBuf(pool, (size_t)arena_bytes(fl, caps, entry_bytes));
-        ar = carve(arena.as<char>(), fl, n_trees, caps, entry_bytes);
-        tm = hh_timing{};
-
-        mark(ctx, 0);
-        check(launch_clear(ar, n_rec, st), "clear");
-        if (kind == 0) {
-            check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, ar.error, st), "pack");
-        } else {
-            ExtractArgs ea{};
-            ea.images = d_desc.as<ImageDesc>();
-            ea.n_images = n;
-            ea.n_tiles = n_tiles;
-            ea.xy = xy;
-            ea.tile_count = tcount.as<int32_t>();
-            ea.tile_pre = tpre.as<int64_t>();
-            ea.trees = d_trees.as<TreeDesc>();
-            ea.n_trees = n_trees;
-            check(launch_extract(ea, st), "extract");
+    size_t total_b = 0;
+    {
+        size_t free_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            total_b = (size_t)64 << 30;
         }
+    }
+    const double budget = 0.45 * (double)total_b;   // one arena; a resume holds two for a moment
+    int from = -1;                                  // -1: from the root setup; l: from level l's split decision
+    const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    for (int run = 0;; ++run) {
+        if (run >= 64) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
+        caps = Caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
+        DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
+        const Arena nar = carve(narena.as<char>(), nfl, n_trees, caps, entry_bytes);
+        tm = hh_timing{};
+        mark(ctx, 0);
+        if (run == 0) {
+            check(launch_clear(nar, n_rec, st), "clear");
+            if (kind == 0) {
+                check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, nar.error, st), "pack");
+            } else {
+                ExtractArgs ea{};
+                ea.images = d_desc.as<ImageDesc>();
+                ea.n_images = n;
+                ea.n_tiles = n_tiles;
+                ea.xy = xy;
+                ea.tile_count = tcount.as<int32_t>();
+                ea.tile_pre = tpre.as<int64_t>();
+                ea.trees = d_trees.as<TreeDesc>();
+                ea.n_trees = n_trees;
+                check(launch_extract(ea, st), "extract");
+            }
+        } else if (from < 0) {
+            check(launch_clear(nar, n_rec, st), "clear");
+        } else {
+            // carry the finished stages over (both arenas have the same fixed head)
+            const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
+            const LevelInfo& lv = info[from];
+            const LevelInfo& nx = info[from + 1];
+            auto copy = [&](void* dst, const void* src, int64_t bytes) {
+                if (bytes > 0) check(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, st), "resume copy");
+            };
+            copy(nar.info, ar.info, fl.head_bytes);
+            check(hipMemsetAsync(nar.error, 0, sizeof(uint32_t), st), "resume clear");
+            copy(nar.cells, ar.cells, nx.cells_base * (int64_t)sizeof(Cell));
+            if (members) copy(nar.members, ar.members, nx.mem_base * entry_bytes);
+            copy(nar.half[from & 1], ar.half[from & 1], half_layout(nullptr, lv.P, lv.L, entry_bytes).end);
+            copy(nar.work, ar.work, work_layout(nullptr, lv.P, lv.L).end);
+            sync(ctx);   // the old arena goes back to the pool only once it is read
+        }
+        arena = std::move(narena);
+        ar = nar;
+        fl = nfl;
+        if (run > 0) pool->trim();   // drop the smaller arenas of earlier runs
         mark(ctx, 1);
-        check(launch_roots(ar, d_trees.as<TreeDesc>(), n_trees, xy, ctx->grid, st), "roots");
+        if (from < 0) check(launch_roots(ar, d_trees.as<TreeDesc>(), n_trees, xy, ctx->grid, st), "roots");
         LevelArgs la{};
         la.ar = ar;
         la.trees = d_trees.as<TreeDesc>();
         la.xy = xy;
-        la.keep_members = p0.membership ? 1 : 0;
-        const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
-        const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
-        for (int l = 0; l < dmax_all; ++l) {
+        la.keep_members = members ? 1 : 0;
+        const int first = std::max(from, 0);
+        for (int l = first; l < dmax_all; ++l) {
             la.level = l;
             mark(ctx, 3 + 4 * l);
-            check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
+            if (l != from) check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
             mark(ctx, 4 + 4 * l);
-            check(launch_decide(la, kRangeGrid, st), "decide");
+            if (l != from) check(launch_decide(la, kRangeGrid, st), "decide");
             check(launch_emit(la, kRangeGrid, st), "emit");
             mark(ctx, 5 + 4 * l);
-            if (l + 1 < dmax_all || p0.membership) check(launch_write(la, write_grid, st), "write");
+            if (l + 1 < dmax_all || members) check(launch_write(la, write_grid, st), "write");
             mark(ctx, 6 + 4 * l);
         }
         mark(ctx, 2);
@@ -630,26 +677,44 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         if (timing) {
             tm.total_ms = elapsed(ctx, 0, 2);
             tm.extract_ms = elapsed(ctx, 0, 1);
-            for (int l = 0; l < dmax_all; ++l) {
+            for (int l = first; l < dmax_all; ++l) {
                 const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
                 tm.count_ms += c;
                 tm.write_ms += w;
                 tm.vote_ms += c + w;
                 tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
             }
-            tm.vote_launches = dmax_all + (p0.membership ? dmax_all : dmax_all - 1);
+            tm.vote_launches = dmax_all + (members ? dmax_all : dmax_all - 1);
             tm.decide_launches = 2 * dmax_all;
         }
         for (int l = 0; l < dmax_all; ++l) {
             tm.vote_entries += info[l].L;
             if (l + 1 < dmax_all) tm.vote_written += info[l + 1].L;
-            if (p0.membership) tm.vote_written += info[l + 1].mem;
+            if (members) tm.vote_written += info[l + 1].mem;
         }
-        if ((err & kErrArena) && !(err & (kErrPointRange | kErrInternal))) {
-            grow_sizes(ctx, info, dmax_all, entry_bytes);
-            continue;
+        if (!(err & kErrArena) || (err & (kErrPointRange | kErrInternal))) break;
+        const int f = failing_stage(info, dmax_all, caps, members, entry_bytes);
+        if (f == -2) throw Error{HH_EINTERNAL, "arena overflow reported but every level fits"};
+        const LevelInfo& need = info[f + 1 > 0 ? f + 1 : 0];
+        // lists about double per level while most regions split: twice the
+        // need, less if that exceeds the budget
+        Caps g{};
+        bool ok = false;
+        for (double factor : {2.0, 1.25, 1.0}) {
+            g = grown_caps(caps, need, members, entry_bytes, factor);
+            if ((double)arena_bytes(fixed_layout(n_trees, g.cells), g, entry_bytes) <= budget) {
+                ok = true;
+                break;
+            }
         }
-        break;
+        if (!ok)
+            throw Error{HH_ECAPACITY, "the call needs more than " + std::to_string((int64_t)(budget / 1e9)) +
+                                          " GB of device memory for its level lists; split the batch"};
+        ctx->half_cap = g.half;
+        ctx->work_cap = g.work;
+        ctx->cells_cap = g.cells;
+        if (members) ctx->mem_cap = g.mem;
+        from = f;
     }
     if (err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
     if (err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};

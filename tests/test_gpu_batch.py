@@ -206,3 +206,36 @@ def test_batch_invalid(hh):
         r = ctx.detect_batch([dict(image=img, width=8, height=8)])[0]
         assert r.info["n_points"] == 0
         r.free()
+
+
+@pytest.mark.parametrize("membership", [True, False])
+def test_levels_outgrowing_the_arena(hh, membership):
+    """A context whose arena starts far too small: the call resumes at each
+    level that does not fit (and reruns a root setup that does not), with
+    results identical to the oracle; a second call starts at the grown
+    sizes."""
+    ws = synth.batch_images(seed=14, n=8, side_lo=64, side_hi=384)
+    say(f"case tiny arena, batch of 8 and single calls, membership {membership}")
+    with hh.HoughHier(threshold=0, arena_hint=4096, membership=membership) as ctx:
+        for rep in range(2):
+            rs = ctx.detect_batch([dict(image=w.image, width=w.width, height=w.height,
+                                        threshold=w.threshold) for w in ws])
+            for w, r in zip(ws, rs):
+                x, y = oracle.edge_points(w.image)
+                ref = oracle.detect(x, y, w.width, w.height, w.threshold, 0, "code", 3, membership)
+                if membership:
+                    check_against_oracle(host_view(r), ref)
+                else:
+                    for p in (0, 1):
+                        c = r.cells(p)
+                        want = ref.pass_cells(p)
+                        for f in ("i", "j", "key", "votes"):
+                            np.testing.assert_array_equal(c[f], want[f])
+                        np.testing.assert_array_equal(r.stats_array(p), ref.stats[p])
+                r.free()
+    with hh.HoughHier(threshold=40, max_depth=8, arena_hint=4096) as ctx:
+        w = synth.workload("line256", 2)
+        r = ctx.detect(image=w.image, width=w.width, height=w.height)
+        x, y = oracle.edge_points(w.image)
+        check_against_oracle(host_view(r), oracle.detect(x, y, w.width, w.height, 40, 8))
+        r.free()
