@@ -101,7 +101,10 @@ typedef struct {
     int32_t device;           /* HIP device ordinal; the device must be a gfx950        */
     void* stream;             /* hipStream_t for all work, or NULL for the null stream  */
     int32_t flags;            /* HH_FLAG_*                                              */
-    int32_t reserved0;
+    int32_t arena_limit_mib;  /* most MiB one arena may take (0: 45% of the device
+                                 memory).  A batch whose level lists need more runs in
+                                 groups of inputs; one input that needs more fails
+                                 with HH_ECAPACITY.                                    */
     uint64_t arena_hint;      /* initial bytes of each level-list half of a call's arena
                                  (0: 64 MiB); the other parts start in proportion.  A
                                  call whose levels outgrow the arena continues in a
@@ -158,7 +161,8 @@ typedef struct {
 
 /* Kernel timings of one call (HH_FLAG_TIMING), from HIP events recorded on
  * the context's stream around the launches of each level; zero without the
- * flag.  The events themselves add a few microseconds per level. */
+ * flag.  The events themselves add a few microseconds per level.  The entry
+ * counts, groups and resumes are filled in with or without the flag. */
 typedef struct {
     int32_t vote_launches;    /* per-level count and compaction launches            */
     int32_t decide_launches;  /* per-level split-decision launches                  */
@@ -170,6 +174,8 @@ typedef struct {
     int64_t vote_written;     /* entries written by the compaction launches         */
     double count_ms;          /* summed duration of the count launches              */
     double write_ms;          /* summed duration of the compaction launches         */
+    int32_t groups;           /* groups of inputs whose levels ran in one arena     */
+    int32_t resumes;          /* levels that outgrew the arena and resumed larger   */
 } hh_timing;
 
 /* Create a context on cfg->device.  Checks the device is a gfx950.

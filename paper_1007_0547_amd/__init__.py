@@ -55,7 +55,7 @@ class HHError(RuntimeError):
 class _Config(C.Structure):
     _fields_ = [("threshold", C.c_int32), ("max_depth", C.c_int32), ("passes", C.c_uint32),
                 ("variant", C.c_int32), ("membership", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("flags", C.c_int32), ("reserved0", C.c_int32),
+                ("stream", C.c_void_p), ("flags", C.c_int32), ("arena_limit_mib", C.c_int32),
                 ("arena_hint", C.c_uint64)]
 
 
@@ -77,7 +77,8 @@ class _Timing(C.Structure):
     _fields_ = [("vote_launches", C.c_int32), ("decide_launches", C.c_int32),
                 ("vote_ms", C.c_double), ("decide_ms", C.c_double), ("extract_ms", C.c_double),
                 ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64),
-                ("count_ms", C.c_double), ("write_ms", C.c_double)]
+                ("count_ms", C.c_double), ("write_ms", C.c_double), ("groups", C.c_int32),
+                ("resumes", C.c_int32)]
 
 
 CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),
@@ -221,7 +222,7 @@ class HoughHier:
     def __init__(self, threshold: int = 0, max_depth: int = 0, passes: int = 3,
                  variant: str = "code", membership: bool = True, device: int = 0,
                  stream=None, wide_compare: bool = False, timing: bool = False,
-                 arena_hint: int = 0):
+                 arena_hint: int = 0, arena_limit_mib: int = 0):
         cfg = _Config()
         cfg.threshold = int(threshold)
         cfg.max_depth = int(max_depth)
@@ -232,6 +233,7 @@ class HoughHier:
         cfg.stream = self._stream_handle(stream)
         cfg.flags = (1 if wide_compare else 0) | (2 if timing else 0)
         cfg.arena_hint = int(arena_hint)
+        cfg.arena_limit_mib = int(arena_limit_mib)
         h = C.c_void_p()
         s = _lib.hough_hier_create(C.byref(cfg), C.byref(h))
         if s != 0:

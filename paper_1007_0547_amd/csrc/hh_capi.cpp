@@ -41,7 +41,8 @@ hh_status hough_hier_create(const hh_config* cfg, hh_ctx** out)
     *out = nullptr;
     if (cfg->threshold < 0 || cfg->max_depth < -1 || cfg->max_depth > HH_MAX_DEPTH ||
         (cfg->variant != HH_VARIANT_CODE && cfg->variant != HH_VARIANT_CIRCLE) ||
-        (cfg->passes & ~(HH_PASS_0 | HH_PASS_1)) != 0 || (cfg->membership != 0 && cfg->membership != 1))
+        (cfg->passes & ~(HH_PASS_0 | HH_PASS_1)) != 0 || (cfg->membership != 0 && cfg->membership != 1) ||
+        cfg->arena_limit_mib < 0)
         return HH_EINVAL;
     try {
         return hh::engine_create(cfg, out);

@@ -233,6 +233,17 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
             ctx->mem_cap = std::max<int64_t>(1024, h / 16);
             ctx->cells_cap = std::max<int64_t>(256, h / 256);
         }
+        if (cfg->arena_limit_mib > 0) {
+            // start within a quarter of the limit (the arena grows up to the limit)
+            const int64_t lim = (int64_t)cfg->arena_limit_mib << 18;
+            while (2 * ctx->half_cap + ctx->work_cap + 8 * ctx->mem_cap + 32 * ctx->cells_cap > lim &&
+                   ctx->half_cap > 4096) {
+                ctx->half_cap = std::max<int64_t>(4096, align256(ctx->half_cap / 2));
+                ctx->work_cap = std::max<int64_t>(4096, align256(ctx->work_cap / 2));
+                ctx->mem_cap = std::max<int64_t>(1024, ctx->mem_cap / 2);
+                ctx->cells_cap = std::max<int64_t>(256, ctx->cells_cap / 2);
+            }
+        }
         ctx->grid = std::max(1, ctx->cu_count) * 8;
         const FixedLayout f = fixed_layout(kMaxTrees, 0);
         check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
@@ -242,6 +253,7 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
               "hipHostMalloc");
         check(hipHostMalloc((void**)&ctx->h_lists, kMaxTrees * sizeof(PointsDesc), hipHostMallocDefault),
               "hipHostMalloc");
+        check(hipHostMalloc((void**)&ctx->h_scratch, 256, hipHostMallocDefault), "hipHostMalloc");
         if (cfg->flags & HH_FLAG_TIMING) {
             ctx->events.resize(3 + 4 * kMaxLevels, nullptr);
             for (auto& e : ctx->events) check(hipEventCreate(&e), "hipEventCreate");
@@ -267,6 +279,7 @@ void engine_destroy(hh_ctx* ctx)
     if (ctx->h_trees) (void)hipHostFree(ctx->h_trees);
     if (ctx->h_images) (void)hipHostFree(ctx->h_images);
     if (ctx->h_lists) (void)hipHostFree(ctx->h_lists);
+    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
     delete ctx;
 }
 
@@ -416,6 +429,146 @@ void tree_range(const LevelInfo* info, const int64_t* rec, int32_t t, int32_t n_
             hi = base + r2[ch];
             break;
         }
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// A group's level pipeline needs more device memory than one arena may take.
+struct BudgetExceeded {
+    double budget;
+};
+
+// The level pipeline of one group of trees (trees[0 .. n_trees), points
+// staged in xy) in an arena of its own.  When a level does not fit the
+// arena, the group resumes at that level in a larger arena holding a copy of
+// everything the finished stages left (level records, cells, voters, the
+// level's tables, list and count results); a failure of the root setup
+// reruns it.  On return the level and tree records are in ctx->h_fixed and
+// the trees (with their point counts) in h_trees.
+struct GroupRun {
+    DevBuf arena;
+    FixedLayout fl{};
+    Arena ar{};
+    uint32_t err = 0;
+};
+
+void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees, int32_t n_trees, int32_t dmax,
+               const uint32_t* xy, TreeDesc* h_trees, hh_timing& tm, GroupRun& g)
+{
+    hipStream_t st = ctx->stream;
+    DevicePool* pool = &ctx->pool;
+    const bool members = p0.membership;
+    const bool timing = !ctx->events.empty();
+    const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        total_b = (size_t)64 << 30;
+    }
+    // one arena; a resume holds two for a moment
+    const double budget =
+        ctx->cfg.arena_limit_mib > 0 ? (double)ctx->cfg.arena_limit_mib * (1 << 20) : 0.45 * (double)total_b;
+    int from = -1;   // -1: from the root setup; l: from level l's split decision
+    const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    for (int run = 0;; ++run) {
+        if (run >= 64) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
+        const Caps caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
+        if (run == 0 && (double)arena_bytes(nfl, caps, entry_bytes) > budget) throw BudgetExceeded{budget};
+        DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
+        const Arena nar = carve(narena.as<char>(), nfl, n_trees, caps, entry_bytes);
+        if (from < 0) {
+            check(launch_clear(nar, n_rec, st), "clear");
+        } else {
+            // carry the finished stages over (both arenas have the same fixed head)
+            const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
+            const LevelInfo& lv = info[from];
+            const LevelInfo& nx = info[from + 1];
+            auto copy = [&](void* dst, const void* src, int64_t bytes) {
+                if (bytes > 0) check(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, st), "resume copy");
+            };
+            copy(nar.info, g.ar.info, g.fl.head_bytes);
+            check(hipMemsetAsync(nar.error, 0, sizeof(uint32_t), st), "resume clear");
+            copy(nar.cells, g.ar.cells, nx.cells_base * (int64_t)sizeof(Cell));
+            if (members) copy(nar.members, g.ar.members, nx.mem_base * entry_bytes);
+            copy(nar.half[from & 1], g.ar.half[from & 1], half_layout(nullptr, lv.P, lv.L, entry_bytes).end);
+            copy(nar.work, g.ar.work, work_layout(nullptr, lv.P, lv.L).end);
+            sync(ctx);   // the old arena goes back to the pool only once it is read
+        }
+        g.arena = std::move(narena);
+        g.ar = nar;
+        g.fl = nfl;
+        if (run > 0) pool->trim();   // drop the smaller arenas of earlier runs
+        if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ctx->grid, st), "roots");
+        LevelArgs la{};
+        la.ar = g.ar;
+        la.trees = trees;
+        la.xy = xy;
+        la.keep_members = members ? 1 : 0;
+        const int first = std::max(from, 0);
+        for (int l = first; l < dmax; ++l) {
+            la.level = l;
+            mark(ctx, 3 + 4 * l);
+            if (l != from) check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
+            mark(ctx, 4 + 4 * l);
+            if (l != from) check(launch_decide(la, kRangeGrid, st), "decide");
+            check(launch_emit(la, kRangeGrid, st), "emit");
+            mark(ctx, 5 + 4 * l);
+            if (l + 1 < dmax || members) check(launch_write(la, write_grid, st), "write");
+            mark(ctx, 6 + 4 * l);
+        }
+        mark(ctx, 2);
+        check(hipMemcpyAsync(ctx->h_fixed, g.arena.get(), (size_t)g.fl.head_bytes, hipMemcpyDeviceToHost, st),
+              "copy level records");
+        check(hipMemcpyAsync(h_trees, trees, sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyDeviceToHost, st),
+              "copy trees back");
+        sync(ctx);
+        g.err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + g.fl.error);
+        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
+        if (!(g.err & kErrArena) || (g.err & (kErrPointRange | kErrInternal))) {
+            if (timing) {
+                for (int l = first; l < dmax; ++l) {
+                    const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
+                    tm.count_ms += c;
+                    tm.write_ms += w;
+                    tm.vote_ms += c + w;
+                    tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
+                }
+                tm.vote_launches += dmax + (members ? dmax : dmax - 1);
+                tm.decide_launches += 2 * dmax;
+            }
+            for (int l = 0; l < dmax; ++l) {
+                tm.vote_entries += info[l].L;
+                if (l + 1 < dmax) tm.vote_written += info[l + 1].L;
+                if (members) tm.vote_written += info[l + 1].mem;
+            }
+            return;
+        }
+        const int f = failing_stage(info, dmax, caps, members, entry_bytes);
+        if (f == -2) throw Error{HH_EINTERNAL, "arena overflow reported but every level fits"};
+        const LevelInfo& need = info[f + 1];   // f = -1: the root level
+        // lists about double per level while most regions split: twice the
+        // need, less if that exceeds the budget
+        Caps grown{};
+        bool ok = false;
+        for (double factor : {2.0, 1.25, 1.0}) {
+            grown = grown_caps(caps, need, members, entry_bytes, factor);
+            if ((double)arena_bytes(fixed_layout(n_trees, grown.cells), grown, entry_bytes) <= budget) {
+                ok = true;
+                break;
+            }
+        }
+        if (!ok) throw BudgetExceeded{budget};
+        ++tm.resumes;
+        ctx->half_cap = grown.half;
+        ctx->work_cap = grown.work;
+        ctx->cells_cap = grown.cells;
+        if (members) ctx->mem_cap = grown.mem;
+        from = f;
     }
 }
 
@@ -575,238 +728,194 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     DevBuf d_trees(pool, sizeof(TreeDesc) * (size_t)n_trees);
     check(hipMemcpyAsync(d_trees.get(), ctx->h_trees, sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyHostToDevice, st),
           "copy trees");
-    const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
 
-    // ---- the call.  When a level does not fit the arena, the call resumes
-    // at that level in a larger arena holding a copy of everything the
-    // finished stages left (level records, cells, voters, the level's tables,
-    // list and count results); a failure of the root setup reruns it.
-    const bool members = p0.membership;
-    DevBuf arena;
-    Arena ar{};
-    FixedLayout fl{};
-    Caps caps{};
-    uint32_t err = 0;
+    // ---- edge staging of every input (the groups below share it)
     hh_timing tm{};
-    size_t total_b = 0;
-    {
-        size_t free_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-            (void)hipGetLastError();
-            total_b = (size_t)64 << 30;
-        }
+    mark(ctx, 0);
+    DevBuf stage_err(pool, 256);
+    check(hipMemsetAsync(stage_err.get(), 0, sizeof(uint32_t), st), "clear");
+    if (kind == 0) {
+        check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, stage_err.as<uint32_t>(), st), "pack");
+    } else {
+        ExtractArgs ea{};
+        ea.images = d_desc.as<ImageDesc>();
+        ea.n_images = n;
+        ea.n_tiles = n_tiles;
+        ea.xy = xy;
+        ea.tile_count = tcount.as<int32_t>();
+        ea.tile_pre = tpre.as<int64_t>();
+        ea.trees = d_trees.as<TreeDesc>();
+        ea.n_trees = n_trees;
+        check(launch_extract(ea, st), "extract");
     }
-    const double budget = 0.45 * (double)total_b;   // one arena; a resume holds two for a moment
-    int from = -1;                                  // -1: from the root setup; l: from level l's split decision
-    const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
-    const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
-    for (int run = 0;; ++run) {
-        if (run >= 64) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
-        caps = Caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
-        const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
-        DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
-        const Arena nar = carve(narena.as<char>(), nfl, n_trees, caps, entry_bytes);
-        tm = hh_timing{};
-        mark(ctx, 0);
-        if (run == 0) {
-            check(launch_clear(nar, n_rec, st), "clear");
-            if (kind == 0) {
-                check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, nar.error, st), "pack");
-            } else {
-                ExtractArgs ea{};
-                ea.images = d_desc.as<ImageDesc>();
-                ea.n_images = n;
-                ea.n_tiles = n_tiles;
-                ea.xy = xy;
-                ea.tile_count = tcount.as<int32_t>();
-                ea.tile_pre = tpre.as<int64_t>();
-                ea.trees = d_trees.as<TreeDesc>();
-                ea.n_trees = n_trees;
-                check(launch_extract(ea, st), "extract");
-            }
-        } else if (from < 0) {
-            check(launch_clear(nar, n_rec, st), "clear");
-        } else {
-            // carry the finished stages over (both arenas have the same fixed head)
-            const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
-            const LevelInfo& lv = info[from];
-            const LevelInfo& nx = info[from + 1];
-            auto copy = [&](void* dst, const void* src, int64_t bytes) {
-                if (bytes > 0) check(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, st), "resume copy");
-            };
-            copy(nar.info, ar.info, fl.head_bytes);
-            check(hipMemsetAsync(nar.error, 0, sizeof(uint32_t), st), "resume clear");
-            copy(nar.cells, ar.cells, nx.cells_base * (int64_t)sizeof(Cell));
-            if (members) copy(nar.members, ar.members, nx.mem_base * entry_bytes);
-            copy(nar.half[from & 1], ar.half[from & 1], half_layout(nullptr, lv.P, lv.L, entry_bytes).end);
-            copy(nar.work, ar.work, work_layout(nullptr, lv.P, lv.L).end);
-            sync(ctx);   // the old arena goes back to the pool only once it is read
-        }
-        arena = std::move(narena);
-        ar = nar;
-        fl = nfl;
-        if (run > 0) pool->trim();   // drop the smaller arenas of earlier runs
-        mark(ctx, 1);
-        if (from < 0) check(launch_roots(ar, d_trees.as<TreeDesc>(), n_trees, xy, ctx->grid, st), "roots");
-        LevelArgs la{};
-        la.ar = ar;
-        la.trees = d_trees.as<TreeDesc>();
-        la.xy = xy;
-        la.keep_members = members ? 1 : 0;
-        const int first = std::max(from, 0);
-        for (int l = first; l < dmax_all; ++l) {
-            la.level = l;
-            mark(ctx, 3 + 4 * l);
-            if (l != from) check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
-            mark(ctx, 4 + 4 * l);
-            if (l != from) check(launch_decide(la, kRangeGrid, st), "decide");
-            check(launch_emit(la, kRangeGrid, st), "emit");
-            mark(ctx, 5 + 4 * l);
-            if (l + 1 < dmax_all || members) check(launch_write(la, write_grid, st), "write");
-            mark(ctx, 6 + 4 * l);
-        }
-        mark(ctx, 2);
-        check(hipMemcpyAsync(ctx->h_fixed, arena.get(), (size_t)fl.head_bytes, hipMemcpyDeviceToHost, st),
-              "copy level records");
+    check(hipMemcpyAsync(ctx->h_scratch, stage_err.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, st),
+          "copy staging error");
+    mark(ctx, 1);
+
+    // ---- groups of consecutive inputs whose level lists fit one arena.
+    // One group holds the whole call unless an earlier call on the context
+    // learnt a point limit; a group that exceeds the budget halves the limit
+    // and the remaining inputs are grouped again.
+    bool counts_known = kind == 0;
+    auto points_of = [&](int32_t k) { return ctx->h_trees[(size_t)k * n_pass].n_points; };
+    auto ensure_counts = [&] {
+        if (counts_known) return;
         check(hipMemcpyAsync(ctx->h_trees, d_trees.get(), sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyDeviceToHost,
                              st),
               "copy trees back");
         sync(ctx);
-        err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + fl.error);
-        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
-        if (timing) {
-            tm.total_ms = elapsed(ctx, 0, 2);
-            tm.extract_ms = elapsed(ctx, 0, 1);
-            for (int l = first; l < dmax_all; ++l) {
-                const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
-                tm.count_ms += c;
-                tm.write_ms += w;
-                tm.vote_ms += c + w;
-                tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
-            }
-            tm.vote_launches = dmax_all + (members ? dmax_all : dmax_all - 1);
-            tm.decide_launches = 2 * dmax_all;
-        }
-        for (int l = 0; l < dmax_all; ++l) {
-            tm.vote_entries += info[l].L;
-            if (l + 1 < dmax_all) tm.vote_written += info[l + 1].L;
-            if (members) tm.vote_written += info[l + 1].mem;
-        }
-        if (!(err & kErrArena) || (err & (kErrPointRange | kErrInternal))) break;
-        const int f = failing_stage(info, dmax_all, caps, members, entry_bytes);
-        if (f == -2) throw Error{HH_EINTERNAL, "arena overflow reported but every level fits"};
-        const LevelInfo& need = info[f + 1 > 0 ? f + 1 : 0];
-        // lists about double per level while most regions split: twice the
-        // need, less if that exceeds the budget
-        Caps g{};
-        bool ok = false;
-        for (double factor : {2.0, 1.25, 1.0}) {
-            g = grown_caps(caps, need, members, entry_bytes, factor);
-            if ((double)arena_bytes(fixed_layout(n_trees, g.cells), g, entry_bytes) <= budget) {
-                ok = true;
-                break;
-            }
-        }
-        if (!ok)
-            throw Error{HH_ECAPACITY, "the call needs more than " + std::to_string((int64_t)(budget / 1e9)) +
-                                          " GB of device memory for its level lists; split the batch"};
-        ctx->half_cap = g.half;
-        ctx->work_cap = g.work;
-        ctx->cells_cap = g.cells;
-        if (members) ctx->mem_cap = g.mem;
-        from = f;
-    }
-    if (err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
-    if (err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
-    store->arena = std::move(arena);
-
-    const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + fl.info);
-    const int64_t* rec = reinterpret_cast<const int64_t*>(ctx->h_fixed + fl.rec);
-    const Cell* dcells = ar.cells;
-
-    // ---- one result per image
+        counts_known = true;
+    };
     std::vector<std::unique_ptr<hh_result>> res((size_t)n);
-    for (int32_t k = 0; k < n; ++k) {
-        auto r = std::make_unique<hh_result>();
-        r->ctx = ctx;
-        r->store = store;
-        r->n_trees = n_pass;
-        r->tree_pass[0] = tree_pass[0];
-        r->tree_pass[1] = tree_pass[1];
-        r->entry_bytes = entry_bytes;
-        r->have_members = p0.membership;
-        r->timing = tm;
-        const Plan& pl = ip[(size_t)k].plan;
-        const int32_t t0 = k * n_pass;
-        const int64_t E = ctx->h_trees[t0].n_points;
-        r->xy = xy + ctx->h_trees[t0].xy_base;
-        r->members_base = ar.members;
-        int64_t code_tests = 0, cells_lo = -1, cells_hi = -1, mem_lo = -1, mem_hi = -1;
-        for (int32_t q = 0; q < n_pass; ++q) {
-            const int32_t t = t0 + q;
-            const int p = tree_pass[q];
-            r->stats[p] = tree_stats(info, rec, t, n_trees, pl.dmax, E, pl.T);
-            for (const auto& lv : r->stats[p]) code_tests += lv.code_tests;
-            r->info.n_cells[p] = r->stats[p][(size_t)pl.dmax].detected;
-            if (pl.dmax > 0 && r->info.n_cells[p] > 0) {
-                int64_t lo, hi, mlo, mhi;
-                tree_range(info, rec, t, n_trees, pl.dmax, 4, lo, hi);
-                tree_range(info, rec, t, n_trees, pl.dmax, 6, mlo, mhi);
-                if (hi - lo != r->info.n_cells[p]) throw Error{HH_EINTERNAL, "cell count does not match the statistics"};
-                if (cells_lo < 0) {
-                    cells_lo = lo;
-                    mem_lo = mlo;
-                }
-                cells_hi = hi;
-                mem_hi = mhi;
-            }
+    int32_t n_groups = 0;
+    for (int32_t k0 = 0; k0 < n;) {
+        int32_t k1 = n;
+        if (ctx->group_points > 0 && n > 1) {
+            ensure_counts();
+            int64_t sum = points_of(k0);
+            for (k1 = k0 + 1; k1 < n && sum + points_of(k1) <= ctx->group_points; ++k1) sum += points_of(k1);
         }
-        r->n_cells_total = r->info.n_cells[0] + r->info.n_cells[1];
-        if (pl.dmax > 0) {
-            r->cells = cells_lo >= 0 ? dcells + cells_lo : nullptr;
-            if (cells_lo >= 0 && cells_hi - cells_lo != r->n_cells_total)
-                throw Error{HH_EINTERNAL, "an image's cells are not contiguous"};
-            if (p0.membership && mem_lo >= 0) {
-                r->mem_base = mem_lo;
-                r->members = static_cast<const char*>(ar.members) + mem_lo * entry_bytes;
-                r->info.member_slots = mem_hi - mem_lo;
+        int32_t dmax = 0;
+        for (int32_t k = k0; k < k1; ++k) dmax = std::max(dmax, ip[(size_t)k].plan.dmax);
+        const int32_t t0g = k0 * n_pass, ntg = (k1 - k0) * n_pass;
+        GroupRun g;
+        try {
+            run_group(ctx, p0, entry_bytes, d_trees.as<TreeDesc>() + t0g, ntg, dmax, xy, ctx->h_trees + t0g, tm, g);
+        } catch (const BudgetExceeded& b) {
+            if (k1 - k0 <= 1)
+                throw Error{HH_ECAPACITY, "input " + std::to_string(k0) + " needs more than " +
+                                              std::to_string((int64_t)(b.budget / 1e9)) +
+                                              " GB of device memory for its level lists"};
+            counts_known = true;   // run_group copied the group's trees back
+            int64_t sum = 0;
+            for (int32_t k = k0; k < k1; ++k) sum += points_of(k);
+            ctx->group_points = std::max<int64_t>(1, sum / 2);
+            continue;
+        }
+        if (g.err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
+        if (*ctx->h_scratch & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
+        counts_known = true;
+
+        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
+        const int64_t* rec = reinterpret_cast<const int64_t*>(ctx->h_fixed + g.fl.rec);
+        auto gs = std::make_shared<GroupStore>();
+        gs->call = store;
+        const Cell* gcells = g.ar.cells;
+        const void* gmembers = g.ar.members;
+        if (k0 == 0 && k1 == n) {
+            gs->arena = std::move(g.arena);   // one group: results point into its arena
+        } else {
+            // several groups: keep exact copies of the cells and voters, and
+            // let the next group reuse the arena
+            const int64_t nc = info[dmax].cells_base + info[dmax].cells;
+            const int64_t nm = p0.membership ? info[dmax].mem_base + info[dmax].mem : 0;
+            gs->cells = DevBuf(pool, (size_t)std::max<int64_t>(nc, 1) * sizeof(Cell));
+            if (nc > 0)
+                check(hipMemcpyAsync(gs->cells.get(), g.ar.cells, (size_t)nc * sizeof(Cell), hipMemcpyDeviceToDevice,
+                                     st),
+                      "copy cells");
+            if (nm > 0) {
+                gs->members = DevBuf(pool, (size_t)nm * entry_bytes);
+                check(hipMemcpyAsync(gs->members.get(), g.ar.members, (size_t)nm * entry_bytes,
+                                     hipMemcpyDeviceToDevice, st),
+                      "copy members");
             }
-        } else if (r->n_cells_total > 0) {
-            // depth 0: the root is the finest region; every line votes for it
-            r->depth0 = true;
-            r->depth0_cells = DevBuf(pool, sizeof(Cell) * (size_t)n_pass);
-            std::vector<Cell> hc;
+            gcells = gs->cells.as<Cell>();
+            gmembers = gs->members.get();
+        }
+        ++n_groups;
+
+        // ---- one result per image of the group
+        for (int32_t k = k0; k < k1; ++k) {
+            auto r = std::make_unique<hh_result>();
+            r->ctx = ctx;
+            r->store = gs;
+            r->n_trees = n_pass;
+            r->tree_pass[0] = tree_pass[0];
+            r->tree_pass[1] = tree_pass[1];
+            r->entry_bytes = entry_bytes;
+            r->have_members = p0.membership;
+            const Plan& pl = ip[(size_t)k].plan;
+            const int32_t tl = (k - k0) * n_pass;   // the image's first tree in the group
+            const int64_t E = points_of(k);
+            r->xy = xy + ctx->h_trees[(size_t)k * n_pass].xy_base;
+            r->members_base = gmembers;
+            int64_t code_tests = 0, cells_lo = -1, cells_hi = -1, mem_lo = -1, mem_hi = -1;
             for (int32_t q = 0; q < n_pass; ++q) {
-                if (r->info.n_cells[tree_pass[q]] == 0) continue;
-                Cell c{};
-                c.votes = (int32_t)E;
-                c.pass = tree_pass[q];
-                c.member_off = p0.membership ? 0 : -1;
-                hc.push_back(c);
+                const int32_t t = tl + q;
+                const int p = tree_pass[q];
+                r->stats[p] = tree_stats(info, rec, t, ntg, pl.dmax, E, pl.T);
+                for (const auto& lv : r->stats[p]) code_tests += lv.code_tests;
+                r->info.n_cells[p] = r->stats[p][(size_t)pl.dmax].detected;
+                if (pl.dmax > 0 && r->info.n_cells[p] > 0) {
+                    int64_t lo, hi, mlo, mhi;
+                    tree_range(info, rec, t, ntg, pl.dmax, 4, lo, hi);
+                    tree_range(info, rec, t, ntg, pl.dmax, 6, mlo, mhi);
+                    if (hi - lo != r->info.n_cells[p])
+                        throw Error{HH_EINTERNAL, "cell count does not match the statistics"};
+                    if (cells_lo < 0) {
+                        cells_lo = lo;
+                        mem_lo = mlo;
+                    }
+                    cells_hi = hi;
+                    mem_hi = mhi;
+                }
             }
-            check(hipMemcpyAsync(r->depth0_cells.get(), hc.data(), sizeof(Cell) * hc.size(), hipMemcpyHostToDevice,
-                                 st),
-                  "copy cells");
-            r->cells = r->depth0_cells.as<Cell>();
-            if (p0.membership) {
-                r->members = r->xy;   // the voters are all points, in order
-                r->entry_bytes = 4;
-                r->info.member_slots = E;
+            r->n_cells_total = r->info.n_cells[0] + r->info.n_cells[1];
+            if (pl.dmax > 0) {
+                r->cells = cells_lo >= 0 ? gcells + cells_lo : nullptr;
+                if (cells_lo >= 0 && cells_hi - cells_lo != r->n_cells_total)
+                    throw Error{HH_EINTERNAL, "an image's cells are not contiguous"};
+                if (p0.membership && mem_lo >= 0) {
+                    r->mem_base = mem_lo;
+                    r->members = static_cast<const char*>(gmembers) + mem_lo * entry_bytes;
+                    r->info.member_slots = mem_hi - mem_lo;
+                }
+            } else if (r->n_cells_total > 0) {
+                // depth 0: the root is the finest region; every line votes for it
+                r->depth0 = true;
+                r->depth0_cells = DevBuf(pool, sizeof(Cell) * (size_t)n_pass);
+                std::vector<Cell> hc;
+                for (int32_t q = 0; q < n_pass; ++q) {
+                    if (r->info.n_cells[tree_pass[q]] == 0) continue;
+                    Cell c{};
+                    c.votes = (int32_t)E;
+                    c.pass = tree_pass[q];
+                    c.member_off = p0.membership ? 0 : -1;
+                    hc.push_back(c);
+                }
+                check(hipMemcpyAsync(r->depth0_cells.get(), hc.data(), sizeof(Cell) * hc.size(),
+                                     hipMemcpyHostToDevice, st),
+                      "copy cells");
+                r->cells = r->depth0_cells.as<Cell>();
+                if (p0.membership) {
+                    r->members = r->xy;   // the voters are all points, in order
+                    r->entry_bytes = 4;
+                    r->info.member_slots = E;
+                }
+                sync(ctx);
             }
-            sync(ctx);
+            r->info.n_points = E;
+            r->info.width = pl.W;
+            r->info.height = pl.H;
+            r->info.side_pow2 = (int32_t)pl.S;
+            r->info.depth = pl.dmax;
+            r->info.threshold = pl.T;
+            r->info.passes = passes;
+            r->info.compare_bits = (p0.variant == HH_VARIANT_CIRCLE || p0.wide) ? 64 : 32;
+            r->info.code_tests = code_tests;
+            res[(size_t)k] = std::move(r);
         }
-        r->info.n_points = E;
-        r->info.width = pl.W;
-        r->info.height = pl.H;
-        r->info.side_pow2 = (int32_t)pl.S;
-        r->info.depth = pl.dmax;
-        r->info.threshold = pl.T;
-        r->info.passes = passes;
-        r->info.compare_bits = (p0.variant == HH_VARIANT_CIRCLE || p0.wide) ? 64 : 32;
-        r->info.code_tests = code_tests;
-        res[(size_t)k] = std::move(r);
+        k0 = k1;
+    }
+    sync(ctx);   // the copies of the last group
+    if (timing) {
+        tm.total_ms = elapsed(ctx, 0, 2);
+        tm.extract_ms = elapsed(ctx, 0, 1);
     }
     for (int32_t k = 0; k < n; ++k) {
+        res[(size_t)k]->timing = tm;
+        res[(size_t)k]->timing.groups = n_groups;
         out[k] = res[(size_t)k].release();
         ctx->live_results.insert(out[k]);
     }

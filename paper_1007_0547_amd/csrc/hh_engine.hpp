@@ -69,10 +69,20 @@ struct Error {
 namespace hh {
 
 // Device memory of one call, shared by the results of its images and
-// released with the last of them.
+// released with the last of them: the packed edge points, image after image.
 struct CallStore {
-    DevBuf arena;              // levels, cells and the member buffer
-    DevBuf points;             // packed edge points, image after image
+    DevBuf points;
+};
+
+// Device memory of one group of a call's images (the images whose levels
+// ran in one arena).  A call in one group keeps the arena (its cells and
+// voters are inside); a call in several groups keeps exact copies of each
+// group's cells and voters and reuses the arena for the next group.
+struct GroupStore {
+    std::shared_ptr<CallStore> call;
+    DevBuf arena;
+    DevBuf cells;
+    DevBuf members;
 };
 
 }  // namespace hh
@@ -80,7 +90,7 @@ struct CallStore {
 // The result of one image of a call.
 struct hh_result {
     hh_ctx* ctx = nullptr;
-    std::shared_ptr<hh::CallStore> store;
+    std::shared_ptr<hh::GroupStore> store;
     hh_result_info info{};
     int32_t n_trees = 0;
     int32_t tree_pass[2] = {-1, -1};
@@ -117,11 +127,15 @@ struct hh_ctx {
     hh::TreeDesc* h_trees = nullptr;
     hh::ImageDesc* h_images = nullptr;
     hh::PointsDesc* h_lists = nullptr;
+    uint32_t* h_scratch = nullptr;      // 256 bytes: the staging error word of a call
     // arena sizes that worked before (grown when a call overflows)
     int64_t half_cap = 64ll << 20;      // bytes per level half
     int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
     int64_t mem_cap = 16ll << 20;       // member entries
     int64_t cells_cap = 1ll << 20;
+    // most edge points one group of a batch may hold (0: no limit), learnt
+    // when a group's level lists exceeded the memory budget
+    int64_t group_points = 0;
     int32_t grid = 0;          // workgroups of the level kernels (fixed grid, tiles strided)
     // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
     // then four per level: before count, after count, after emit, after the compaction

@@ -53,7 +53,7 @@ def test_null_arguments_and_bad_config():
     cfg = hh._Config()
     assert lib.hough_hier_create(C.byref(cfg), None) == -1
     for field, bad in (("threshold", -1), ("max_depth", 16), ("max_depth", -2), ("variant", 2),
-                       ("passes", 4), ("membership", 2)):
+                       ("passes", 4), ("membership", 2), ("arena_limit_mib", -1)):
         cfg = hh._Config()
         setattr(cfg, field, bad)
         assert lib.hough_hier_create(C.byref(cfg), C.byref(h)) == -1, field

@@ -239,3 +239,35 @@ def test_levels_outgrowing_the_arena(hh, membership):
         x, y = oracle.edge_points(w.image)
         check_against_oracle(host_view(r), oracle.detect(x, y, w.width, w.height, 40, 8))
         r.free()
+
+
+def test_batch_in_groups_under_a_memory_limit(hh):
+    """An arena limit far below what the whole batch needs: the call runs in
+    groups of images (the limit is learnt for the next call), every result
+    equals the oracle, and one image that alone exceeds the limit fails
+    cleanly."""
+    ws = synth.batch_images(seed=15, n=16, side_lo=64, side_hi=512)
+    say("case batch in groups, 400 MiB arena limit")
+    with hh.HoughHier(threshold=0, arena_hint=1 << 16, arena_limit_mib=400) as ctx:
+        for rep in range(2):
+            rs = ctx.detect_batch([dict(image=w.image, width=w.width, height=w.height,
+                                        threshold=w.threshold) for w in ws])
+            t = rs[0].timing()
+            say(f"  rep {rep}: groups {t['groups']}, resumes {t['resumes']}")
+            assert t["groups"] > 1
+            for k, (w, r) in enumerate(zip(ws, rs)):
+                x, y = oracle.edge_points(w.image)
+                check_against_oracle(host_view(r), oracle.detect(x, y, w.width, w.height, w.threshold, 0))
+                if k % 5 == 0:
+                    check_device_views(hh, r)
+            for r in rs:
+                r.free()
+    with hh.HoughHier(threshold=40, max_depth=8, arena_limit_mib=1) as ctx:
+        w = synth.workload("line256", 4)
+        with pytest.raises(hh.HHError) as e:
+            ctx.detect(image=w.image, width=w.width, height=w.height)
+        assert e.value.status == -3
+        # the context stays usable
+        small = np.zeros((16, 16), np.uint8)
+        small[3, :] = 1
+        ctx.detect(image=small, width=16, height=16, threshold=2).free()
