@@ -95,6 +95,86 @@ def cpu_baseline(image, W, H, T, depth, budget_s=12.0):
             "seconds_per_image": t_total / runs}
 
 
+def bench_batched(seed, reps=3):
+    """The 512-image batch (sides log-uniform in 128..2048, Poisson(24)
+    segments, noise U[0.5%, 3%], T = floor(side / 10), depth
+    ceil(log2(side))): one hough_hier_detect_batch call per step against the
+    same images in one hough_hier_detect call each."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ws = synth.batch_images(seed=seed, n=512)
+    imgs = [torch.from_numpy(w.image).to(dev) for w in ws]
+    inputs = [dict(image=d, width=w.width, height=w.height, threshold=w.threshold)
+              for d, w in zip(imgs, ws)]
+    ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
+    for _ in range(2):   # the first call learns the arena sizes and groups
+        for r in ctx.detect_batch(inputs):
+            r.free()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rs = ctx.detect_batch(inputs)
+        for r in rs:
+            r.free()
+    torch.cuda.synchronize(dev)
+    batch_s = (time.perf_counter() - t0) / reps
+    rs = ctx.detect_batch(inputs)
+    code_tests = sum(r.info["code_tests"] for r in rs)
+    points = sum(r.info["n_points"] for r in rs)
+    cells = sum(sum(r.info["n_cells"]) for r in rs)
+    tmb = rs[0].timing()
+    for r in rs:
+        r.free()
+    ctx.close()
+
+    ctx_t = HoughHier(threshold=0, membership=True, device=0, stream=stream, timing=True)
+    for _ in range(2):
+        for r in ctx_t.detect_batch(inputs):
+            r.free()
+    rs = ctx_t.detect_batch(inputs)
+    kt = rs[0].timing()
+    for r in rs:
+        r.free()
+    ctx_t.close()
+
+    ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
+    for inp in inputs[:16]:
+        ctx.detect(**inp).free()
+    torch.cuda.synchronize(dev)
+    lat = []
+    t0 = time.perf_counter()
+    for inp in inputs:
+        t1 = time.perf_counter()
+        ctx.detect(**inp).free()
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize(dev)
+    plain_s = time.perf_counter() - t0
+    ctx.close()
+    sides = [max(w.width, w.height) for w in ws]
+    return {
+        "workload": f"512 images, seed {seed}, sides log-uniform 128..2048 (max side {max(sides)}), "
+                    "Poisson(24) segments, noise U[0.5%,3%], T=floor(side/10), depth ceil(log2 side), "
+                    "both passes, voters kept on device",
+        "edge_points": points, "cells": cells, "code_tests": code_tests,
+        "batched": {"ms_per_batch": batch_s * 1e3, "images_per_s": 512 / batch_s,
+                    "code_tests_per_s": code_tests / batch_s, "groups": tmb["groups"],
+                    "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"],
+                                  "decide": kt["decide_ms"], "extract": kt["extract_ms"]},
+                    "vote_entries": kt["vote_entries"], "vote_written": kt["vote_written"]},
+        "plain": {"s_per_512": plain_s, "images_per_s": 512 / plain_s,
+                  "code_tests_per_s": code_tests / plain_s,
+                  "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                 "p99": float(np.percentile(lat, 99) * 1e3)}},
+        "batched_over_plain": plain_s / batch_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +185,7 @@ def main():
     ap.add_argument("--variant", default="code", choices=["code", "circle"])
     ap.add_argument("--wide", action="store_true", help="64-bit corner compares")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling HBM byte counters")
@@ -224,6 +305,8 @@ def main():
                      "id_list_design_alg_bytes_per_step": survey_alg_bytes(stats, det_votes, E)},
     }
     ctx.close()
+    if not args.no_batched:
+        out["batch512"] = bench_batched(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.image, w.width, w.height, w.threshold, w.max_depth)
     print(json.dumps(out), flush=True)

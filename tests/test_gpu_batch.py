@@ -271,3 +271,41 @@ def test_batch_in_groups_under_a_memory_limit(hh):
         small = np.zeros((16, 16), np.uint8)
         small[3, :] = 1
         ctx.detect(image=small, width=16, height=16, threshold=2).free()
+
+
+def test_batch512_full_size_sampled(hh):
+    """The 512-image batch at full size in the launch configuration the
+    benchmark times: six sampled images (the smallest, the largest and four
+    drawn by seed) against the oracle, and for every image the properties
+    that hold at any size (edge count, root statistics, sorted keys, votes
+    above the threshold, per-level consistency of the statistics)."""
+    import torch
+    ws = synth.batch_images(seed=0, n=512)
+    px = np.array([w.width * w.height for w in ws])
+    rng = np.random.default_rng(99)
+    pick = sorted(set([int(np.argmin(px)), int(np.argmax(px))] + rng.choice(512, 4, replace=False).tolist()))
+    say(f"case batch of 512 at full size, sampled images {pick}")
+    imgs = [torch.from_numpy(w.image).cuda() for w in ws]
+    with hh.HoughHier(threshold=0) as ctx:
+        rs = ctx.detect_batch([dict(image=d, width=w.width, height=w.height, threshold=w.threshold)
+                               for d, w in zip(imgs, ws)])
+        say(f"  groups {rs[0].timing()['groups']}")
+        for k, (w, r) in enumerate(zip(ws, rs)):
+            E = int(np.count_nonzero(w.image))
+            assert r.info["n_points"] == E
+            for p in (0, 1):
+                st = r.stats(p)
+                assert st["evaluated"][0] == 1 and st["votes"][0] == E
+                c = r.cells(p)
+                assert np.all(np.diff(c["key"]) > 0)
+                assert np.all(c["votes"] > w.threshold)
+                assert len(c) == st["detected"][-1]
+                # a level's evaluated regions are four per region split above it
+                np.testing.assert_array_equal(st["evaluated"][1:], 4 * st["split"][:-1])
+        for k in pick:
+            w = ws[k]
+            x, y = oracle.edge_points(w.image)
+            say(f"  oracle image {k} ({w.width}x{w.height}, {len(x)} points)")
+            check_against_oracle(host_view(rs[k]), oracle.detect(x, y, w.width, w.height, w.threshold, 0))
+        for r in rs:
+            r.free()
