@@ -39,8 +39,8 @@
  *     ascending point ids.
  *   - All GPU work of a call runs on the context's stream.  A call returns
  *     when its result (cells, members, statistics) is complete on the device.
- *   - A context is not thread-safe across concurrent calls; use one context
- *     per thread, or serialise calls.
+ *   - Calls on one context are serialised by a lock inside the context;
+ *     hough_hier_submit and hough_hier_poll may be called from any thread.
  */
 #ifndef HOUGH_HIER_H
 #define HOUGH_HIER_H
@@ -61,6 +61,7 @@ typedef struct hh_ctx hh_ctx;
 typedef struct hh_result hh_result;
 
 typedef enum {
+    HH_PENDING = 1,      /* hough_hier_poll: the request has not completed (not an error) */
     HH_OK = 0,
     HH_EINVAL = -1,      /* bad argument: null pointer, W or H < 1, point outside
                             [0,W)x[0,H), threshold < 0, depth out of range, size limit */
@@ -176,6 +177,9 @@ typedef struct {
     double write_ms;          /* summed duration of the compaction launches         */
     int32_t groups;           /* groups of inputs whose levels ran in one arena     */
     int32_t resumes;          /* levels that outgrew the arena and resumed larger   */
+    double queue_ms;          /* served requests: submission to the start of its batch */
+    double service_ms;        /* served requests: batch start to cells and statistics
+                                 on the host                                           */
 } hh_timing;
 
 /* Create a context on cfg->device.  Checks the device is a gfx950.
@@ -211,6 +215,46 @@ HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** 
  * kinds, HH_ECAPACITY for more than 2048 trees.  On an error no handle is
  * returned (out[] is all NULL). */
 HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out);
+
+/* ---- Serving: continuous batching of requests on one context.
+ *
+ * hough_hier_serve_start starts `lanes` worker lanes, each with its own HIP
+ * stream and arena (default-priority streams).  A free lane takes the
+ * pending requests in arrival order, as many as fit its admission budget
+ * (at most max_batch requests and max_batch_pixels image pixels, or points
+ * for point lists; the first request is always admitted), runs them as one
+ * batch (hough_hier_detect_batch), copies each result's cells and
+ * statistics to the host and completes the tickets.  Requests that arrive
+ * while batches run are admitted by the next free lane, so batches of
+ * different lanes overlap on the device.  A request's result is identical to
+ * what hough_hier_detect returns for the same input.  The context stays
+ * usable for plain calls.  Served results carry queue_ms and service_ms in
+ * hh_timing. */
+typedef struct {
+    int32_t lanes;            /* concurrent batches, 1..8 (0: 2)                       */
+    int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 64)           */
+    int64_t max_batch_pixels; /* admission budget of one batch (0: 2^26)               */
+    int32_t queue_capacity;   /* most tickets not yet claimed by poll (0: 4096)        */
+    int32_t reserved;
+} hh_serve_config;
+
+/* Start serving on ctx (once per context).  cfg may be NULL for defaults.
+ * Errors: HH_EINVAL (bad config, already serving), HH_EDEVICE, HH_ENOMEM. */
+HH_API hh_status hough_hier_serve_start(hh_ctx* ctx, const hh_serve_config* cfg);
+
+/* Queue one input (borrowed until its ticket completes; device inputs must be
+ * ready, since lanes run on their own streams).  *ticket identifies it.
+ * Errors: HH_EINVAL (not serving, bad input form), HH_EBUSY (queue_capacity
+ * tickets outstanding). */
+HH_API hh_status hough_hier_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket);
+
+/* Wait up to wait_us microseconds (< 0: until done, 0: do not wait) for a
+ * ticket.  HH_PENDING: not completed yet (ask again).  Otherwise the ticket
+ * is consumed: on HH_OK *out owns the result (free it with
+ * hough_hier_result_free), on an error the request's status is returned
+ * and hough_hier_last_error() holds its text.
+ * Errors: HH_EINVAL (unknown ticket, not serving), any error of the request. */
+HH_API hh_status hough_hier_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out);
 
 /* Cells of one pass (0 or 1), sorted by key.  on_device = 1 returns a device
  * pointer (member_off indexes the device members array); on_device = 0 copies

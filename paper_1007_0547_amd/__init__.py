@@ -37,7 +37,7 @@ except ImportError:
 
 _lib = C.CDLL(LIB_PATH)
 
-STATUS = {0: "HH_OK", -1: "HH_EINVAL", -2: "HH_ENOMEM", -3: "HH_ECAPACITY", -4: "HH_EDEVICE",
+STATUS = {1: "HH_PENDING", 0: "HH_OK", -1: "HH_EINVAL", -2: "HH_ENOMEM", -3: "HH_ECAPACITY", -4: "HH_EDEVICE",
           -5: "HH_EBUSY", -6: "HH_ECANCELED", -7: "HH_EINTERNAL"}
 INT32_MIN = -(1 << 31)
 
@@ -78,7 +78,12 @@ class _Timing(C.Structure):
                 ("vote_ms", C.c_double), ("decide_ms", C.c_double), ("extract_ms", C.c_double),
                 ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64),
                 ("count_ms", C.c_double), ("write_ms", C.c_double), ("groups", C.c_int32),
-                ("resumes", C.c_int32)]
+                ("resumes", C.c_int32), ("queue_ms", C.c_double), ("service_ms", C.c_double)]
+
+
+class _ServeConfig(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("max_batch_pixels", C.c_int64),
+                ("queue_capacity", C.c_int32), ("reserved", C.c_int32)]
 
 
 CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),
@@ -98,6 +103,12 @@ _lib.hough_hier_detect.restype = C.c_int
 _lib.hough_hier_detect.argtypes = [_p, C.POINTER(_Input), C.POINTER(_p)]
 _lib.hough_hier_detect_batch.restype = C.c_int
 _lib.hough_hier_detect_batch.argtypes = [_p, C.POINTER(_Input), C.c_int32, C.POINTER(_p)]
+_lib.hough_hier_serve_start.restype = C.c_int
+_lib.hough_hier_serve_start.argtypes = [_p, C.POINTER(_ServeConfig)]
+_lib.hough_hier_submit.restype = C.c_int
+_lib.hough_hier_submit.argtypes = [_p, C.POINTER(_Input), C.POINTER(C.c_uint64)]
+_lib.hough_hier_poll.restype = C.c_int
+_lib.hough_hier_poll.argtypes = [_p, C.c_uint64, C.c_int32, C.POINTER(_p)]
 _lib.hough_hier_result_cells.restype = C.c_int
 _lib.hough_hier_result_cells.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_p), C.POINTER(C.c_int64)]
 _lib.hough_hier_result_members.restype = C.c_int
@@ -327,6 +338,44 @@ class HoughHier:
         if s != 0:
             raise HHError(s, self.last_error())
         return [Result(self, out[k]) for k in range(n)]
+
+    # ---- serving (continuous batching)
+
+    def serve_start(self, lanes: int = 0, max_batch: int = 0, max_batch_pixels: int = 0,
+                    queue_capacity: int = 0):
+        """Start the serving lanes (``hough_hier_serve_start``)."""
+        cfg = _ServeConfig()
+        cfg.lanes, cfg.max_batch = int(lanes), int(max_batch)
+        cfg.max_batch_pixels, cfg.queue_capacity = int(max_batch_pixels), int(queue_capacity)
+        s = _lib.hough_hier_serve_start(self._h, C.byref(cfg))
+        if s != 0:
+            raise HHError(s, self.last_error())
+        self._inflight = {}
+
+    def submit(self, x=None, y=None, *, image=None, width: int, height: int,
+               threshold: int = -1, max_depth: Optional[int] = None) -> int:
+        """Queue one input (``hough_hier_submit``); returns its ticket.  The
+        input objects are kept alive until the ticket is polled."""
+        inp, keep = self._input(x, y, image=image, width=width, height=height, threshold=threshold,
+                                max_depth=max_depth)
+        t = C.c_uint64()
+        s = _lib.hough_hier_submit(self._h, C.byref(inp), C.byref(t))
+        if s != 0:
+            raise HHError(s, self.last_error())
+        self._inflight[t.value] = keep
+        return t.value
+
+    def poll(self, ticket: int, wait_us: int = -1) -> Optional[Result]:
+        """The result of a ticket, or ``None`` while it is pending
+        (``hough_hier_poll``)."""
+        out = C.c_void_p()
+        s = _lib.hough_hier_poll(self._h, int(ticket), int(wait_us), C.byref(out))
+        if s == 1:
+            return None
+        self._inflight.pop(int(ticket), None)
+        if s != 0:
+            raise HHError(s, self.last_error())
+        return Result(self, out.value)
 
     def close(self):
         if self._h:

@@ -8,11 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhough_hier.so")
-SOURCES = ["hh_kernels.hip", "hh_engine.cpp", "hh_capi.cpp"]
+SOURCES = ["hh_kernels.hip", "hh_engine.cpp", "hh_serve.cpp", "hh_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-fvisibility=hidden", "-Wall",
+    "-fvisibility=hidden", "-Wall", "-pthread",
     # no packed fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -2,6 +2,7 @@
 // include/hough_hier.h).  Every entry point converts internal errors into an
 // hh_status and records the message on the context.
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -11,8 +12,17 @@ namespace {
 
 hh_status fail(hh_ctx* ctx, hh_status s, const std::string& msg)
 {
-    if (ctx) ctx->last_error = msg;
+    if (ctx) {
+        std::lock_guard<std::mutex> g(ctx->err_mu);
+        ctx->last_error = msg;
+    }
     return s;
+}
+
+void clear_error(hh_ctx* ctx)
+{
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    ctx->last_error.clear();
 }
 
 template <typename F>
@@ -65,12 +75,35 @@ const char* hough_hier_last_error(const hh_ctx* ctx)
     return ctx->last_error.c_str();
 }
 
+hh_status hough_hier_serve_start(hh_ctx* ctx, const hh_serve_config* cfg)
+{
+    if (!ctx) return HH_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return guarded(ctx, [&] { return hh::serve_start(ctx, cfg); });
+}
+
+hh_status hough_hier_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!in || !ticket) return fail(ctx, HH_EINVAL, "input and ticket pointers must not be NULL");
+    return guarded(ctx, [&] { return hh::serve_submit(ctx, in, ticket); });
+}
+
+hh_status hough_hier_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!out) return fail(ctx, HH_EINVAL, "output pointer must not be NULL");
+    *out = nullptr;
+    return guarded(ctx, [&] { return hh::serve_poll(ctx, ticket, wait_us, out); });
+}
+
 hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
 {
     if (!ctx) return HH_EINVAL;
     if (!in || !out) return fail(ctx, HH_EINVAL, "input and output pointers must not be NULL");
     *out = nullptr;
-    ctx->last_error.clear();
+    clear_error(ctx);
+    std::lock_guard<std::mutex> g(ctx->mu);
     return guarded(ctx, [&] { return hh::engine_detect(ctx, in, out); });
 }
 
@@ -80,7 +113,8 @@ hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n
     if (!inputs || !out) return fail(ctx, HH_EINVAL, "input and output pointers must not be NULL");
     if (n < 1) return fail(ctx, HH_EINVAL, "a batch needs at least one input");
     for (int32_t k = 0; k < n; ++k) out[k] = nullptr;
-    ctx->last_error.clear();
+    clear_error(ctx);
+    std::lock_guard<std::mutex> g(ctx->mu);
     return guarded(ctx, [&] { return hh::engine_detect_batch(ctx, inputs, n, out); });
 }
 
@@ -101,6 +135,7 @@ hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_devic
     }
     if (!enabled) return HH_OK;
     const int64_t count = res->info.n_cells[pass];
+    std::lock_guard<std::mutex> g(res->ctx->mu);
     if (on_device) {
         const hh::Cell* dc = nullptr;
         hh_status s = guarded(res->ctx, [&] {
@@ -112,7 +147,7 @@ hh_status hough_hier_result_cells(hh_result* res, int32_t pass, int32_t on_devic
         *n = count;
         return HH_OK;
     }
-    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_copy(res); });
+    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_cells(res); });
     if (s != HH_OK) return s;
     if (count > 0) *cells = res->host_cells.data() + before;
     *n = count;
@@ -125,6 +160,7 @@ hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int
     *ids = nullptr;
     *n = 0;
     if (!res->have_members) return fail(res->ctx, HH_EINVAL, "membership was not kept");
+    std::lock_guard<std::mutex> g(res->ctx->mu);
     if (on_device) {
         hh_status s = guarded(res->ctx, [&] { return hh::engine_device_ids(res); });
         if (s != HH_OK) return s;
@@ -132,7 +168,7 @@ hh_status hough_hier_result_members(hh_result* res, int32_t on_device, const int
         *n = res->info.member_slots;
         return HH_OK;
     }
-    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_copy(res); });
+    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_members(res); });
     if (s != HH_OK) return s;
     *ids = res->host_members.data();
     *n = (int64_t)res->host_members.size();
@@ -179,6 +215,7 @@ void hough_hier_result_free(hh_result* res)
 {
     if (!res) return;
     try {
+        std::lock_guard<std::mutex> g(res->ctx->mu);
         (void)hipSetDevice(res->ctx->device);
         res->ctx->live_results.erase(res);
         delete res;

@@ -17,6 +17,7 @@
 #include <new>
 
 #include "hh_kernels.hpp"
+#include "hh_serve.hpp"
 
 namespace hh {
 
@@ -269,6 +270,7 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
 void engine_destroy(hh_ctx* ctx)
 {
     if (!ctx) return;
+    serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -958,32 +960,49 @@ hh_status engine_device_ids(hh_result* res)
     return HH_OK;
 }
 
-hh_status engine_host_copy(hh_result* res)
+// Host copy of the cells, member_off rewritten to the compact host layout
+// (cells after cells, in (pass, key) order).
+hh_status engine_host_cells(hh_result* res)
 {
-    if (res->host_ready) return HH_OK;
+    if (res->host_cells_ready) return HH_OK;
     hh_ctx* ctx = res->ctx;
-    hipStream_t st = ctx->stream;
     check(hipSetDevice(ctx->device), "hipSetDevice");
     const int64_t n = res->n_cells_total;
     res->host_cells.resize((size_t)n);
     if (n > 0)
         check(hipMemcpyAsync(res->host_cells.data(), res->cells, (size_t)n * sizeof(hh_cell), hipMemcpyDeviceToHost,
-                             st),
+                             ctx->stream),
               "copy cells");
     sync(ctx);
-    std::vector<int64_t> off((size_t)n);
     int64_t total = 0;
     for (int64_t c = 0; c < n; ++c) {
-        off[(size_t)c] = total;
-        total += res->host_cells[(size_t)c].votes;
+        hh_cell& h = res->host_cells[(size_t)c];
+        h.member_off = res->have_members ? total : -1;
+        total += h.votes;
     }
+    res->host_member_total = total;
+    res->host_cells_ready = true;
+    return HH_OK;
+}
+
+// Host copy of the voters' point ids in the compact host layout.
+hh_status engine_host_members(hh_result* res)
+{
+    if (res->host_members_ready) return HH_OK;
+    engine_host_cells(res);
+    hh_ctx* ctx = res->ctx;
+    hipStream_t st = ctx->stream;
+    const int64_t n = res->n_cells_total, total = res->host_member_total;
     if (res->have_members && n > 0) {
         res->host_members.resize((size_t)total);
         if (res->depth0) {   // every point votes for the root: ids 0 .. E-1 per cell
-            for (int64_t c = 0; c < n; ++c)
-                for (int32_t k = 0; k < res->host_cells[(size_t)c].votes; ++k)
-                    res->host_members[(size_t)(off[(size_t)c] + k)] = k;
+            for (int64_t c = 0; c < n; ++c) {
+                const hh_cell& h = res->host_cells[(size_t)c];
+                for (int32_t k = 0; k < h.votes; ++k) res->host_members[(size_t)(h.member_off + k)] = k;
+            }
         } else {
+            std::vector<int64_t> off((size_t)n);
+            for (int64_t c = 0; c < n; ++c) off[(size_t)c] = res->host_cells[(size_t)c].member_off;
             DevBuf d_off(&ctx->pool, (size_t)n * 8);
             DevBuf d_dst(&ctx->pool, (size_t)std::max<int64_t>(total, 1) * 4);
             check(hipMemcpyAsync(d_off.get(), off.data(), (size_t)n * 8, hipMemcpyHostToDevice, st), "copy offsets");
@@ -995,9 +1014,7 @@ hh_status engine_host_copy(hh_result* res)
             sync(ctx);
         }
     }
-    for (int64_t c = 0; c < n; ++c)
-        res->host_cells[(size_t)c].member_off = res->have_members ? off[(size_t)c] : -1;
-    res->host_ready = true;
+    res->host_members_ready = true;
     return HH_OK;
 }
 

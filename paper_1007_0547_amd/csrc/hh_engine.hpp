@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -109,13 +110,24 @@ struct hh_result {
     hh::DevBuf dev_ids;                  // point ids in the layout of member_off (made on request)
     hh_timing timing{};
     // lazily filled host copies
-    bool host_ready = false;
+    bool host_cells_ready = false;
+    bool host_members_ready = false;
+    int64_t host_member_total = 0;
     std::vector<hh_cell> host_cells;
     std::vector<int32_t> host_members;
 };
 
+namespace hh {
+struct Server;
+}
+
 struct hh_ctx {
     hh_config cfg{};
+    // serialises the calls that use this context's stream, pool and results
+    std::mutex mu;
+    std::mutex err_mu;   // last_error
+    // serving lanes (hough_hier_serve_start); stopped before the context goes
+    std::unique_ptr<hh::Server> server;
     int device = 0;
     hipStream_t stream = nullptr;
     std::string last_error;
@@ -151,9 +163,16 @@ void engine_destroy(hh_ctx* ctx);
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
 // n inputs in one call; out[k] is the result of in[k] (all or none are made)
 hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* in, int32_t n, hh_result** out);
-hh_status engine_host_copy(hh_result* res);
+hh_status engine_host_cells(hh_result* res);
+hh_status engine_host_members(hh_result* res);
 hh_status engine_device_ids(hh_result* res);
 // The result's device cells with member_off counted from its own first voter.
 const Cell* engine_device_cells(hh_result* res);
+
+// Serving (hh_serve.cpp).
+hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg);
+hh_status serve_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket);
+hh_status serve_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out);
+void serve_stop(hh_ctx* ctx);
 
 }  // namespace hh

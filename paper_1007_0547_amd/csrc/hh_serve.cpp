@@ -1,0 +1,233 @@
+// Continuous batching of detection requests on one context.
+//
+// Each lane is a worker thread with a context of its own (own HIP stream,
+// pool and arena).  A free lane takes the pending requests in arrival order
+// while they fit its admission budget, runs them as one batch, brings every
+// result's cells and statistics to the host and completes the tickets.
+// Requests arriving while batches run wait for the next free lane, so
+// batches of different lanes overlap on the device.  A batch that fails as a
+// whole is run again request by request, so that each request gets its own
+// status.
+#include "hh_serve.hpp"
+
+#include <algorithm>
+#include <exception>
+#include <new>
+
+#include "hh_engine.hpp"
+
+namespace hh {
+
+namespace {
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+template <typename F>
+hh_status capture(F&& f, std::string& error)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        error = e.what;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        error = "host allocation failed";
+        return HH_ENOMEM;
+    } catch (const std::exception& e) {
+        error = e.what();
+        return HH_EINTERNAL;
+    }
+}
+
+void run_lane(Server* sv, int lane)
+{
+    hh_ctx* c = sv->lanes[(size_t)lane];
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> batch;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->work_cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+            if (sv->stop) return;
+            const int32_t kind = sv->pending.front()->in.kind;
+            int64_t cost = 0;
+            while (!sv->pending.empty() && (int32_t)batch.size() < sv->cfg.max_batch) {
+                const auto& r = sv->pending.front();
+                if (r->in.kind != kind) break;   // one kind per batch
+                if (!batch.empty() && cost + r->cost > sv->cfg.max_batch_pixels) break;
+                cost += r->cost;
+                batch.push_back(r);
+                sv->pending.pop_front();
+            }
+            if (!sv->pending.empty()) sv->work_cv.notify_one();   // another lane may take the rest
+        }
+        const Clock::time_point t_start = Clock::now();
+        const int32_t n = (int32_t)batch.size();
+        std::vector<hh_input> ins((size_t)n);
+        for (int32_t k = 0; k < n; ++k) ins[(size_t)k] = batch[(size_t)k]->in;
+        std::vector<hh_result*> outs((size_t)n, nullptr);
+        std::vector<hh_status> status((size_t)n, HH_OK);
+        std::vector<std::string> error((size_t)n);
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            std::string err;
+            hh_status st = capture([&] { return engine_detect_batch(c, ins.data(), n, outs.data()); }, err);
+            if (st == HH_OK) {
+                for (int32_t k = 0; k < n; ++k) {
+                    status[(size_t)k] = capture([&] { return engine_host_cells(outs[(size_t)k]); }, error[(size_t)k]);
+                }
+            } else if (n == 1) {
+                status[0] = st;
+                error[0] = err;
+            } else {
+                for (int32_t k = 0; k < n; ++k) {
+                    hh_result* r = nullptr;
+                    status[(size_t)k] = capture([&] { return engine_detect(c, &ins[(size_t)k], &r); }, error[(size_t)k]);
+                    outs[(size_t)k] = r;
+                    if (status[(size_t)k] == HH_OK)
+                        status[(size_t)k] = capture([&] { return engine_host_cells(r); }, error[(size_t)k]);
+                }
+            }
+            for (int32_t k = 0; k < n; ++k) {
+                if (status[(size_t)k] != HH_OK && outs[(size_t)k]) {
+                    c->live_results.erase(outs[(size_t)k]);
+                    delete outs[(size_t)k];
+                    outs[(size_t)k] = nullptr;
+                }
+            }
+        }
+        const Clock::time_point t_done = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (int32_t k = 0; k < n; ++k) {
+                Request& r = *batch[(size_t)k];
+                r.t_start = t_start;
+                r.t_done = t_done;
+                r.status = status[(size_t)k];
+                r.error = error[(size_t)k];
+                r.result = outs[(size_t)k];
+                if (r.result) {
+                    r.result->timing.queue_ms = ms_between(r.t_submit, t_start);
+                    r.result->timing.service_ms = ms_between(t_start, t_done);
+                }
+                r.done = true;
+            }
+        }
+        sv->done_cv.notify_all();
+    }
+}
+
+}  // namespace
+
+hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
+{
+    if (ctx->server) throw Error{HH_EINVAL, "the context is already serving"};
+    hh_serve_config cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.lanes == 0) cfg.lanes = 2;
+    if (cfg.max_batch == 0) cfg.max_batch = 64;
+    if (cfg.max_batch_pixels == 0) cfg.max_batch_pixels = (int64_t)1 << 26;
+    if (cfg.queue_capacity == 0) cfg.queue_capacity = 4096;
+    if (cfg.lanes < 1 || cfg.lanes > 8 || cfg.max_batch < 1 || cfg.max_batch > kMaxTrees ||
+        cfg.max_batch_pixels < 1 || cfg.queue_capacity < 1)
+        throw Error{HH_EINVAL, "bad serving configuration"};
+    if ((int64_t)cfg.max_batch * __builtin_popcount(ctx->cfg.passes) > kMaxTrees)
+        throw Error{HH_EINVAL, "max_batch times the enabled passes exceeds 2048 trees"};
+    auto sv = std::make_unique<Server>();
+    sv->cfg = cfg;
+    auto cleanup = [&] {
+        for (hh_ctx* l : sv->lanes) engine_destroy(l);
+        for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+    };
+    for (int i = 0; i < cfg.lanes; ++i) {
+        hipStream_t s = nullptr;
+        if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            throw Error{HH_EDEVICE, "hipStreamCreateWithFlags failed"};
+        }
+        sv->streams.push_back(s);
+        hh_config lc = ctx->cfg;
+        lc.stream = s;
+        hh_ctx* lane = nullptr;
+        const hh_status st = engine_create(&lc, &lane);
+        if (st != HH_OK) {
+            cleanup();
+            throw Error{st, "lane context creation failed"};
+        }
+        lane->half_cap = ctx->half_cap;   // start from the sizes the context learnt
+        lane->work_cap = ctx->work_cap;
+        lane->mem_cap = ctx->mem_cap;
+        lane->cells_cap = ctx->cells_cap;
+        lane->group_points = ctx->group_points;
+        sv->lanes.push_back(lane);
+    }
+    Server* raw = sv.get();
+    for (int i = 0; i < cfg.lanes; ++i) raw->workers.emplace_back(run_lane, raw, i);
+    ctx->server = std::move(sv);
+    return HH_OK;
+}
+
+hh_status serve_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket)
+{
+    Server* sv = ctx->server.get();
+    if (!sv) throw Error{HH_EINVAL, "the context is not serving (hough_hier_serve_start)"};
+    if (in->kind != 0 && in->kind != 1) throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
+    if (in->width < 1 || in->height < 1) throw Error{HH_EINVAL, "width and height must be >= 1"};
+    auto r = std::make_shared<Request>();
+    r->in = *in;
+    r->cost = in->kind == 1 ? (int64_t)in->width * in->height : std::max<int64_t>(in->n_points, 1);
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if ((int64_t)sv->tickets.size() >= sv->cfg.queue_capacity) return HH_EBUSY;
+        r->ticket = sv->next_ticket++;
+        sv->tickets.emplace(r->ticket, r);
+        sv->pending.push_back(r);
+    }
+    sv->work_cv.notify_one();
+    *ticket = r->ticket;
+    return HH_OK;
+}
+
+hh_status serve_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out)
+{
+    Server* sv = ctx->server.get();
+    if (!sv) throw Error{HH_EINVAL, "the context is not serving (hough_hier_serve_start)"};
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) throw Error{HH_EINVAL, "unknown ticket"};
+    std::shared_ptr<Request> r = it->second;
+    if (!r->done && wait_us != 0) {
+        auto ready = [&] { return r->done || sv->stop; };
+        if (wait_us < 0) sv->done_cv.wait(lk, ready);
+        else sv->done_cv.wait_for(lk, std::chrono::microseconds(wait_us), ready);
+    }
+    if (!r->done) return HH_PENDING;
+    sv->tickets.erase(ticket);
+    if (r->status != HH_OK) throw Error{r->status, r->error};
+    *out = r->result;
+    return HH_OK;
+}
+
+void serve_stop(hh_ctx* ctx)
+{
+    Server* sv = ctx->server.get();
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->work_cv.notify_all();
+    sv->done_cv.notify_all();
+    for (auto& t : sv->workers)
+        if (t.joinable()) t.join();
+    // unclaimed results live in their lane's context and go with it
+    for (hh_ctx* l : sv->lanes) engine_destroy(l);
+    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+    ctx->server.reset();
+}
+
+}  // namespace hh

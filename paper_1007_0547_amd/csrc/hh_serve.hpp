@@ -1,0 +1,48 @@
+// Serving state of a context: worker lanes, request queue and tickets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hough_hier.h"
+
+namespace hh {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    hh_input in{};
+    int64_t cost = 0;              // admission cost: image pixels, or points of a list
+    Clock::time_point t_submit, t_start, t_done;
+    bool done = false;
+    hh_status status = HH_OK;
+    std::string error;
+    hh_result* result = nullptr;
+};
+
+struct Server {
+    hh_serve_config cfg{};
+    std::vector<hh_ctx*> lanes;        // one context per lane, each on its own stream
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> workers;
+    std::mutex mu;                     // queue, tickets and the stop flag
+    std::condition_variable work_cv;   // a request was queued, or stop
+    std::condition_variable done_cv;   // a request completed, or stop
+    std::deque<std::shared_ptr<Request>> pending;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;   // not yet claimed by poll
+    uint64_t next_ticket = 1;
+    bool stop = false;
+};
+
+}  // namespace hh

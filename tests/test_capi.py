@@ -20,7 +20,8 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("hough_hier_create", "hough_hier_destroy", "hough_hier_detect", "hough_hier_detect_batch",
               "hough_hier_result_cells", "hough_hier_result_members", "hough_hier_result_stats",
-              "hough_hier_result_info", "hough_hier_result_free", "hough_hier_last_error"):
+              "hough_hier_result_info", "hough_hier_result_free", "hough_hier_last_error",
+              "hough_hier_serve_start", "hough_hier_submit", "hough_hier_poll"):
         assert n in names
 
 
@@ -61,6 +62,10 @@ def test_null_arguments_and_bad_config():
     assert lib.hough_hier_last_error(None) == b""
     assert lib.hough_hier_detect(None, None, None) == -1
     assert lib.hough_hier_detect_batch(None, None, 0, None) == -1
+    assert lib.hough_hier_serve_start(None, None) == -1
+    t, out = C.c_uint64(), C.c_void_p()
+    assert lib.hough_hier_submit(None, None, C.byref(t)) == -1
+    assert lib.hough_hier_poll(None, 1, 0, C.byref(out)) == -1
     p, n = C.c_void_p(), C.c_int64()
     assert lib.hough_hier_result_cells(None, 0, 0, C.byref(p), C.byref(n)) == -1
     assert lib.hough_hier_result_members(None, 0, C.byref(p), C.byref(n)) == -1
