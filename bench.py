@@ -175,6 +175,109 @@ def bench_batched(seed, reps=3):
     }
 
 
+def bench_serving(seed, seconds, pool_size=128):
+    """Serving: Poisson arrivals of images (sides log-uniform 256..4096,
+    Poisson(48) segments, 1% noise, T = floor(side / 10), default depth),
+    drawn in turn from a pool of `pool_size` images of that distribution
+    resident on the device.  Each rate runs `seconds` of arrivals through
+    (a) continuous batching (2 lanes, up to 64 requests and 2^26 pixels per
+    batch) and (b) per-request plain launches (1 lane, batches of 1).  The
+    rates are 0.9x and 1.5x the measured plain capacity.  Latency = arrival
+    to cells and statistics on the host, measured inside the library."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    trace = synth.serving_trace(seed=seed, rate_hz=1000.0, duration_s=1e9, max_requests=pool_size)
+    pool = [w for _, w in trace]
+    imgs = [torch.from_numpy(w.image).to(dev) for w in pool]
+    torch.cuda.synchronize(dev)
+    inputs = [dict(image=d, width=w.width, height=w.height, threshold=w.threshold) for d, w in zip(imgs, pool)]
+
+    # plain capacity: back-to-back single calls over the pool, cells and
+    # statistics brought to the host as a served request's are
+    def plain_one(c, inp):
+        r = c.detect(**inp)
+        r.cells(0)
+        r.cells(1)
+        r.free()
+
+    ctx = HoughHier(threshold=0, membership=True, device=0)
+    for inp in inputs:
+        plain_one(ctx, inp)
+    t0 = time.perf_counter()
+    for _ in range(2):
+        for inp in inputs:
+            plain_one(ctx, inp)
+    capacity = 2 * len(inputs) / (time.perf_counter() - t0)
+    ctx.close()
+
+    def run(rate, lanes, max_batch):
+        rng = np.random.default_rng(seed + 1)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
+        arrivals = arrivals[arrivals < seconds]
+        srv = HoughHier(threshold=0, membership=True, device=0)
+        srv.serve_start(lanes=lanes, max_batch=max_batch, max_batch_pixels=1 << 26,
+                        queue_capacity=max(4096, len(arrivals) + 16))
+        for k in range(min(len(inputs), 2 * max_batch)):   # warm the lanes' arenas
+            srv.poll(srv.submit(**inputs[k])).free()
+        tickets = queue.Queue()
+        lat, failed = [], []
+
+        def collect():
+            while True:
+                t = tickets.get()
+                if t is None:
+                    return
+                try:
+                    r = srv.poll(t)
+                except Exception as e:   # a failed request is reported, not timed
+                    failed.append(str(e))
+                    continue
+                tm = r.timing()
+                lat.append(tm["queue_ms"] + tm["service_ms"])
+                r.free()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for k, at in enumerate(arrivals):
+            while True:
+                d = at - (time.perf_counter() - t0)
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.002))
+            tickets.put(srv.submit(**inputs[k % len(inputs)]))
+        tickets.put(None)
+        th.join()
+        wall = time.perf_counter() - t0
+        srv.close()
+        res = {"requests": len(arrivals), "images_per_s": len(lat) / wall,
+               "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
+        if failed:
+            res["failed"] = len(failed)
+            res["first_failure"] = failed[0]
+        return res
+
+    out = {"workload": f"Poisson arrivals for {seconds:g} s per rate; images from a pool of {len(pool)} "
+                       f"(seed {seed}): sides log-uniform 256..4096, Poisson(48) segments, 1% noise, "
+                       "T=floor(side/10), depth ceil(log2 side), both passes, voters kept on device",
+           "mean_edge_points": float(np.mean([np.count_nonzero(w.image) for w in pool])),
+           "plain_capacity_images_per_s": capacity, "rates": {}}
+    for f in (0.9, 1.5):
+        rate = f * capacity
+        out["rates"][f"{f}x"] = {"arrival_rate_hz": rate,
+                                 "continuous_batching": run(rate, 2, 64),
+                                 "plain_per_request": run(rate, 1, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +289,8 @@ def main():
     ap.add_argument("--wide", action="store_true", help="64-bit corner compares")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling HBM byte counters")
@@ -307,6 +412,8 @@ def main():
     ctx.close()
     if not args.no_batched:
         out["batch512"] = bench_batched(args.seed)
+    if args.serve_seconds > 0:
+        out["serving"] = bench_serving(args.seed, args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w.image, w.width, w.height, w.threshold, w.max_depth)
     print(json.dumps(out), flush=True)

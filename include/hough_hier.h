@@ -102,7 +102,7 @@ typedef struct {
     int32_t device;           /* HIP device ordinal; the device must be a gfx950        */
     void* stream;             /* hipStream_t for all work, or NULL for the null stream  */
     int32_t flags;            /* HH_FLAG_*                                              */
-    int32_t arena_limit_mib;  /* most MiB one arena may take (0: 45% of the device
+    int32_t arena_limit_mib;  /* most MiB one arena may take (0: 35% of the device
                                  memory).  A batch whose level lists need more runs in
                                  groups of inputs; one input that needs more fails
                                  with HH_ECAPACITY.                                    */
@@ -197,7 +197,9 @@ HH_API const char* hough_hier_last_error(const hh_ctx* ctx);
 /* Run the hierarchical vote (Sec. 3) on one input: edge staging (image
  * inputs), then levels 0 .. depth-1 for every enabled pass.  Inputs are
  * borrowed for the duration of the call.  On HH_OK *out owns the result;
- * release it with hough_hier_result_free().
+ * release it with hough_hier_result_free().  The result keeps the call's
+ * arena (its cells and voters are inside) until it is freed, so free results
+ * promptly when calls are many or large (served results are compact).
  * Errors: HH_EINVAL (see hh_status; also for device point lists with a point
  * out of range), HH_ENOMEM, HH_EDEVICE, HH_EINTERNAL. */
 HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
@@ -227,8 +229,10 @@ HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, in
  * statistics to the host and completes the tickets.  Requests that arrive
  * while batches run are admitted by the next free lane, so batches of
  * different lanes overlap on the device.  A request's result is identical to
- * what hough_hier_detect returns for the same input.  The context stays
- * usable for plain calls.  Served results carry queue_ms and service_ms in
+ * what hough_hier_detect returns for the same input.  The lanes share the
+ * context's arena limit equally, and a served result holds exact copies of
+ * its cells and voters only (the arena goes to the lane's next batch).  The
+ * context stays usable for plain calls.  Served results carry queue_ms and service_ms in
  * hh_timing. */
 typedef struct {
     int32_t lanes;            /* concurrent batches, 1..8 (0: 2)                       */
@@ -292,8 +296,10 @@ HH_API hh_status hough_hier_result_info(const hh_result* res, hh_result_info* in
 /* Kernel timings of the call that produced res (see hh_timing). */
 HH_API hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timing);
 
-/* Release a result (its device memory returns to the context).  NULL is
- * accepted. */
+/* Release a result (its device memory returns to the context, where the
+ * context's next call may reuse it: finish any work that reads the result's
+ * device arrays first).  Does not wait for calls running on the context.
+ * NULL is accepted. */
 HH_API void hough_hier_result_free(hh_result* res);
 
 #ifdef __cplusplus

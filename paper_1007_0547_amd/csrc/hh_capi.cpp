@@ -215,9 +215,11 @@ void hough_hier_result_free(hh_result* res)
 {
     if (!res) return;
     try {
-        std::lock_guard<std::mutex> g(res->ctx->mu);
-        (void)hipSetDevice(res->ctx->device);
-        res->ctx->live_results.erase(res);
+        // the pool has a lock of its own: a free never waits for a running call
+        {
+            std::lock_guard<std::mutex> g(res->ctx->results_mu);
+            res->ctx->live_results.erase(res);
+        }
         delete res;
     } catch (...) {
     }

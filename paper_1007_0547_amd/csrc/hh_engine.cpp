@@ -25,7 +25,7 @@ namespace hh {
 
 DevicePool::~DevicePool()
 {
-    trim();
+    trim_locked();
     for (auto& kv : size_of_) (void)hipFree(kv.first);
 }
 
@@ -39,6 +39,7 @@ size_t DevicePool::round_size(size_t bytes)
 
 void* DevicePool::alloc(size_t bytes)
 {
+    std::lock_guard<std::mutex> g(mu_);
     const size_t sz = round_size(bytes);
     auto it = free_.find(sz);
     if (it != free_.end() && !it->second.empty()) {
@@ -51,7 +52,7 @@ void* DevicePool::alloc(size_t bytes)
     void* p = nullptr;
     if (hipMalloc(&p, sz) != hipSuccess) {
         (void)hipGetLastError();
-        trim();
+        trim_locked();
         if (hipMalloc(&p, sz) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
@@ -65,6 +66,7 @@ void* DevicePool::alloc(size_t bytes)
 void DevicePool::release(void* p)
 {
     if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
     auto it = size_of_.find(p);
     if (it == size_of_.end()) return;
     free_[it->second].push_back(p);
@@ -73,6 +75,12 @@ void DevicePool::release(void* p)
 }
 
 void DevicePool::trim()
+{
+    std::lock_guard<std::mutex> g(mu_);
+    trim_locked();
+}
+
+void DevicePool::trim_locked()
 {
     for (auto& kv : free_) {
         for (void* p : kv.second) {
@@ -87,7 +95,13 @@ void DevicePool::trim()
 DevBuf::DevBuf(DevicePool* pool, size_t bytes) : pool_(pool), bytes_(bytes)
 {
     ptr_ = pool->alloc(bytes ? bytes : 1);
-    if (!ptr_) throw Error{HH_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    if (!ptr_) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) (void)hipGetLastError();
+        throw Error{HH_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (this context holds " +
+                                   std::to_string(pool->live_bytes()) + " bytes; device free " +
+                                   std::to_string(free_b) + " of " + std::to_string(total_b) + ")"};
+    }
 }
 
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept
@@ -275,8 +289,11 @@ void engine_destroy(hh_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     ctx->events.clear();
-    for (hh_result* r : ctx->live_results) delete r;
-    ctx->live_results.clear();
+    {
+        std::lock_guard<std::mutex> g(ctx->results_mu);
+        for (hh_result* r : ctx->live_results) delete r;
+        ctx->live_results.clear();
+    }
     if (ctx->h_fixed) (void)hipHostFree(ctx->h_fixed);
     if (ctx->h_trees) (void)hipHostFree(ctx->h_trees);
     if (ctx->h_images) (void)hipHostFree(ctx->h_images);
@@ -472,7 +489,7 @@ void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees
     }
     // one arena; a resume holds two for a moment
     const double budget =
-        ctx->cfg.arena_limit_mib > 0 ? (double)ctx->cfg.arena_limit_mib * (1 << 20) : 0.45 * (double)total_b;
+        ctx->cfg.arena_limit_mib > 0 ? (double)ctx->cfg.arena_limit_mib * (1 << 20) : 0.35 * (double)total_b;
     int from = -1;   // -1: from the root setup; l: from level l's split decision
     const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
     const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
@@ -804,11 +821,11 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         gs->call = store;
         const Cell* gcells = g.ar.cells;
         const void* gmembers = g.ar.members;
-        if (k0 == 0 && k1 == n) {
+        if (k0 == 0 && k1 == n && !ctx->compact_results) {
             gs->arena = std::move(g.arena);   // one group: results point into its arena
         } else {
-            // several groups: keep exact copies of the cells and voters, and
-            // let the next group reuse the arena
+            // several groups, or compact results: keep exact copies of the
+            // cells and voters, and let the next group or call reuse the arena
             const int64_t nc = info[dmax].cells_base + info[dmax].cells;
             const int64_t nm = p0.membership ? info[dmax].mem_base + info[dmax].mem : 0;
             gs->cells = DevBuf(pool, (size_t)std::max<int64_t>(nc, 1) * sizeof(Cell));
@@ -915,6 +932,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         tm.total_ms = elapsed(ctx, 0, 2);
         tm.extract_ms = elapsed(ctx, 0, 1);
     }
+    std::lock_guard<std::mutex> g(ctx->results_mu);
     for (int32_t k = 0; k < n; ++k) {
         res[(size_t)k]->timing = tm;
         res[(size_t)k]->timing.groups = n_groups;

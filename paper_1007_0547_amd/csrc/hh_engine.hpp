@@ -20,8 +20,10 @@ namespace hh {
 
 // Caching allocator over hipMalloc.  Sizes are rounded up to one of eight
 // steps per power of two; freed blocks wait in per-size free lists and are
-// handed out again without a hipMalloc.  All users of one pool work on one
-// stream, so reuse is ordered by the stream.
+// handed out again without a hipMalloc.  All device work that uses a pool's
+// blocks runs on its context's stream, so reuse is ordered by the stream.
+// The pool is locked on its own, so that releasing a result's blocks never
+// waits for a call running on the context.
 class DevicePool {
 public:
     ~DevicePool();
@@ -33,6 +35,8 @@ public:
 
 private:
     static size_t round_size(size_t bytes);
+    void trim_locked();
+    std::mutex mu_;
     std::unordered_map<size_t, std::vector<void*>> free_;
     std::unordered_map<void*, size_t> size_of_;
     size_t live_ = 0, cached_ = 0;
@@ -125,7 +129,8 @@ struct hh_ctx {
     hh_config cfg{};
     // serialises the calls that use this context's stream, pool and results
     std::mutex mu;
-    std::mutex err_mu;   // last_error
+    std::mutex err_mu;       // last_error
+    std::mutex results_mu;   // live_results
     // serving lanes (hough_hier_serve_start); stopped before the context goes
     std::unique_ptr<hh::Server> server;
     int device = 0;
@@ -145,6 +150,10 @@ struct hh_ctx {
     int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
     int64_t mem_cap = 16ll << 20;       // member entries
     int64_t cells_cap = 1ll << 20;
+    // results keep exact copies of their cells and voters and release the
+    // arena at once (serving lanes); otherwise a one-group call's results
+    // keep its arena until the last of them is freed
+    bool compact_results = false;
     // most edge points one group of a batch may hold (0: no limit), learnt
     // when a group's level lists exceeded the memory budget
     int64_t group_points = 0;

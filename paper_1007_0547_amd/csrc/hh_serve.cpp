@@ -92,7 +92,10 @@ void run_lane(Server* sv, int lane)
             }
             for (int32_t k = 0; k < n; ++k) {
                 if (status[(size_t)k] != HH_OK && outs[(size_t)k]) {
-                    c->live_results.erase(outs[(size_t)k]);
+                    {
+                        std::lock_guard<std::mutex> r(c->results_mu);
+                        c->live_results.erase(outs[(size_t)k]);
+                    }
                     delete outs[(size_t)k];
                     outs[(size_t)k] = nullptr;
                 }
@@ -137,6 +140,17 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
         throw Error{HH_EINVAL, "max_batch times the enabled passes exceeds 2048 trees"};
     auto sv = std::make_unique<Server>();
     sv->cfg = cfg;
+    // the lanes share the context's arena limit
+    int64_t limit_mib = ctx->cfg.arena_limit_mib;
+    if (limit_mib <= 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            total_b = (size_t)64 << 30;
+        }
+        limit_mib = (int64_t)(0.35 * (double)total_b) >> 20;
+    }
+    const int32_t lane_limit_mib = (int32_t)std::max<int64_t>(1, limit_mib / cfg.lanes);
     auto cleanup = [&] {
         for (hh_ctx* l : sv->lanes) engine_destroy(l);
         for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
@@ -151,17 +165,14 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
         sv->streams.push_back(s);
         hh_config lc = ctx->cfg;
         lc.stream = s;
+        lc.arena_limit_mib = lane_limit_mib;
         hh_ctx* lane = nullptr;
         const hh_status st = engine_create(&lc, &lane);
         if (st != HH_OK) {
             cleanup();
             throw Error{st, "lane context creation failed"};
         }
-        lane->half_cap = ctx->half_cap;   // start from the sizes the context learnt
-        lane->work_cap = ctx->work_cap;
-        lane->mem_cap = ctx->mem_cap;
-        lane->cells_cap = ctx->cells_cap;
-        lane->group_points = ctx->group_points;
+        lane->compact_results = true;   // a queued result holds its cells and voters only
         sv->lanes.push_back(lane);
     }
     Server* raw = sv.get();
