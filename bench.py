@@ -218,10 +218,13 @@ def bench_serving(seed, seconds, pool_size=128):
     capacity = 2 * len(inputs) / (time.perf_counter() - t0)
     ctx.close()
 
-    def run(rate, lanes, max_batch):
+    def run(rate, lanes, max_batch, burst=0):
         rng = np.random.default_rng(seed + 1)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
-        arrivals = arrivals[arrivals < seconds]
+        if burst:   # every request at once: the sustained throughput
+            arrivals = np.zeros(burst)
+        else:
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
+            arrivals = arrivals[arrivals < seconds]
         srv = HoughHier(threshold=0, membership=True, device=0)
         srv.serve_start(lanes=lanes, max_batch=max_batch, max_batch_pixels=1 << 26,
                         queue_capacity=max(4096, len(arrivals) + 16))
@@ -275,6 +278,10 @@ def bench_serving(seed, seconds, pool_size=128):
         out["rates"][f"{f}x"] = {"arrival_rate_hz": rate,
                                  "continuous_batching": run(rate, 2, 64),
                                  "plain_per_request": run(rate, 1, 1)}
+    n_burst = 4 * len(inputs)
+    out["burst"] = {"requests": n_burst,
+                    "continuous_batching": run(0, 2, 64, burst=n_burst),
+                    "plain_per_request": run(0, 1, 1, burst=n_burst)}
     return out
 
 
