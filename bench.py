@@ -180,7 +180,7 @@ def bench_serving(seed, seconds, pool_size=128):
     Poisson(48) segments, 1% noise, T = floor(side / 10), default depth),
     drawn in turn from a pool of `pool_size` images of that distribution
     resident on the device.  Each rate runs `seconds` of arrivals through
-    (a) continuous batching (2 lanes, up to 64 requests and 2^26 pixels per
+    (a) continuous batching (2 lanes, up to 32 requests and 2^24 pixels per
     batch) and (b) per-request plain launches (1 lane, batches of 1).  The
     rates are 0.9x and 1.5x the measured plain capacity.  Latency = arrival
     to cells and statistics on the host, measured inside the library."""
@@ -226,10 +226,12 @@ def bench_serving(seed, seconds, pool_size=128):
             arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
             arrivals = arrivals[arrivals < seconds]
         srv = HoughHier(threshold=0, membership=True, device=0)
-        srv.serve_start(lanes=lanes, max_batch=max_batch, max_batch_pixels=1 << 26,
+        srv.serve_start(lanes=lanes, max_batch=max_batch, max_batch_pixels=1 << 24,
                         queue_capacity=max(4096, len(arrivals) + 16))
-        for k in range(min(len(inputs), 2 * max_batch)):   # warm the lanes' arenas
-            srv.poll(srv.submit(**inputs[k])).free()
+        for _ in range(3):   # warm the lanes: arena sizes and group limits for full batches
+            warm = [srv.submit(**inp) for inp in inputs]
+            for t in warm:
+                srv.poll(t).free()
         tickets = queue.Queue()
         lat, failed = [], []
 
@@ -276,11 +278,11 @@ def bench_serving(seed, seconds, pool_size=128):
     for f in (0.9, 1.5):
         rate = f * capacity
         out["rates"][f"{f}x"] = {"arrival_rate_hz": rate,
-                                 "continuous_batching": run(rate, 2, 64),
+                                 "continuous_batching": run(rate, 2, 32),
                                  "plain_per_request": run(rate, 1, 1)}
     n_burst = 4 * len(inputs)
     out["burst"] = {"requests": n_burst,
-                    "continuous_batching": run(0, 2, 64, burst=n_burst),
+                    "continuous_batching": run(0, 2, 32, burst=n_burst),
                     "plain_per_request": run(0, 1, 1, burst=n_burst)}
     return out
 

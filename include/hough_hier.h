@@ -236,8 +236,8 @@ HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, in
  * hh_timing. */
 typedef struct {
     int32_t lanes;            /* concurrent batches, 1..8 (0: 2)                       */
-    int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 64)           */
-    int64_t max_batch_pixels; /* admission budget of one batch (0: 2^26)               */
+    int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 32)           */
+    int64_t max_batch_pixels; /* admission budget of one batch (0: 2^24)               */
     int32_t queue_capacity;   /* most tickets not yet claimed by poll (0: 4096)        */
     int32_t reserved;
 } hh_serve_config;

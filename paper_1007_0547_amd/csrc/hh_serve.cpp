@@ -130,8 +130,8 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
     hh_serve_config cfg{};
     if (cfg_in) cfg = *cfg_in;
     if (cfg.lanes == 0) cfg.lanes = 2;
-    if (cfg.max_batch == 0) cfg.max_batch = 64;
-    if (cfg.max_batch_pixels == 0) cfg.max_batch_pixels = (int64_t)1 << 26;
+    if (cfg.max_batch == 0) cfg.max_batch = 32;
+    if (cfg.max_batch_pixels == 0) cfg.max_batch_pixels = (int64_t)1 << 24;
     if (cfg.queue_capacity == 0) cfg.queue_capacity = 4096;
     if (cfg.lanes < 1 || cfg.lanes > 8 || cfg.max_batch < 1 || cfg.max_batch > kMaxTrees ||
         cfg.max_batch_pixels < 1 || cfg.queue_capacity < 1)
