@@ -977,8 +977,10 @@ struct KidSource {
 // run[q] + their rank in the row, the offset clamped to cv[q] - 1 so that no
 // store leaves the child's slot; when a region closes, run must equal cv
 // (else the call fails with an internal error).  A row without a region start
-// is one segment; a row with a few starts is taken segment by segment; a row
-// with many starts takes per-lane destinations.
+// continues the open region's counts; in a row where regions start, each lane
+// takes its destination on its own: the lanes of the region open at the row
+// start continue its counts, the others count from their region's first lane
+// in the row.
 template <typename Entry, bool kStaged>
 __device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, const KidSource<kStaged>& kids,
                                            const uint32_t* bm, const Entry (&ent)[kRows], uint32_t vword, int wave,
@@ -1023,30 +1025,17 @@ __device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, con
         for (int q = 0; q < 4; ++q) cm[q] = __ballot((vb >> q) & 1u);
         const uint64_t W = row_word(bm, wave * kRows + k);
         const int starts = (int)__popcll(W);
-        if (starts <= 3) {
-            uint64_t rest = W;
-            int prev = 0;
-            for (;;) {   // the segments of this row, one region each
-                const int p = rest ? __builtin_ctzll(rest) : kWave;
-                const bool inseg = lane >= prev && lane < p;
-                const uint32_t vk = inseg ? (vb & keep) : 0u;
-                const Entry e_out = EntryOps<Entry>::natural(ent[k], unswap);
+        if (starts == 0) {   // the whole row belongs to the open region
+            const Entry e_out = EntryOps<Entry>::natural(ent[k], unswap);
+            const uint32_t vk = vb & keep;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint64_t mq = cm[q] & (p == kWave ? ~0ull : bits_below(p)) & ~bits_below(prev);
-                    if ((vk >> q) & 1u) bq[q][std::min(run[q] + (int32_t)lanes_below(mq), cv[q] - 1)] = e_out;
-                    run[q] += (int32_t)__popcll(mq);
-                }
-                if (!rest) break;
-                rest &= rest - 1;
-                prev = p;
-                close_check();
-                ++open;
-                open_fields();
+            for (int q = 0; q < 4; ++q) {
+                if ((vk >> q) & 1u) bq[q][std::min(run[q] + (int32_t)lanes_below(cm[q]), cv[q] - 1)] = e_out;
+                run[q] += (int32_t)__popcll(cm[q]);
             }
             continue;
         }
-        // many regions in this row: per-lane destinations
+        // a region starts in this row: per-lane destinations
         const uint64_t le = W & ((2ull << lane) - 1);
         const bool seg0 = le == 0;
         const int local = std::min(open + (int)__popcll(le), nr - 1);
