@@ -144,7 +144,7 @@ def bench_batched(seed, reps=3):
     ctx_t.close()
 
     ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
-    for inp in inputs[:16]:
+    for inp in inputs:   # one untimed pass: the arena reaches the sizes the largest images need
         ctx.detect(**inp).free()
     torch.cuda.synchronize(dev)
     lat = []

@@ -74,6 +74,17 @@ void DevicePool::release(void* p)
     cached_ += it->second;
 }
 
+void DevicePool::discard(void* p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = size_of_.find(p);
+    if (it == size_of_.end()) return;
+    live_ -= it->second;
+    size_of_.erase(it);
+    (void)hipFree(p);
+}
+
 void DevicePool::trim()
 {
     std::lock_guard<std::mutex> g(mu_);
@@ -116,6 +127,14 @@ DevBuf& DevBuf::operator=(DevBuf&& o) noexcept
         o.bytes_ = 0;
     }
     return *this;
+}
+
+void DevBuf::discard()
+{
+    if (pool_ && ptr_) pool_->discard(ptr_);
+    pool_ = nullptr;
+    ptr_ = nullptr;
+    bytes_ = 0;
 }
 
 void DevBuf::reset()
@@ -518,10 +537,10 @@ void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees
             copy(nar.work, g.ar.work, work_layout(nullptr, lv.P, lv.L).end);
             sync(ctx);   // the old arena goes back to the pool only once it is read
         }
+        if (run > 0) g.arena.discard();   // a smaller arena is of no further use
         g.arena = std::move(narena);
         g.ar = nar;
         g.fl = nfl;
-        if (run > 0) pool->trim();   // drop the smaller arenas of earlier runs
         if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ctx->grid, st), "roots");
         LevelArgs la{};
         la.ar = g.ar;

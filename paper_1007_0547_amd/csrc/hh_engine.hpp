@@ -29,6 +29,7 @@ public:
     ~DevicePool();
     void* alloc(size_t bytes);
     void release(void* p);
+    void discard(void* p);   // hipFree a live block instead of caching it
     void trim();
     size_t live_bytes() const { return live_; }
     size_t cached_bytes() const { return cached_; }
@@ -53,6 +54,7 @@ public:
     DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
     DevBuf& operator=(DevBuf&& o) noexcept;
     void reset();
+    void discard();   // free the block outright (it is not cached for reuse)
     template <typename T> T* as() const { return static_cast<T*>(ptr_); }
     void* get() const { return ptr_; }
     size_t bytes() const { return bytes_; }
