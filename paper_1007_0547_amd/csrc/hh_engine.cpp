@@ -178,6 +178,21 @@ double elapsed(hh_ctx* c, int a, int b)
     return ms;
 }
 
+// A call's descriptor block (host and device alike): trees at 0, the staging
+// error word at `err`, the input table at `desc`.
+struct CallLayout {
+    int64_t err, desc, bytes;
+};
+
+CallLayout call_layout(int32_t n_trees, int32_t n_inputs)
+{
+    CallLayout c{};
+    c.err = align256((int64_t)n_trees * (int64_t)sizeof(TreeDesc));
+    c.desc = c.err + 256;
+    c.bytes = c.desc + (int64_t)n_inputs * (int64_t)std::max(sizeof(ImageDesc), sizeof(PointsDesc));
+    return c;
+}
+
 // Fixed part of an arena: level records, tree records, error word, scratch,
 // then the cells.  Everything before the cells is copied back in one piece.
 struct FixedLayout {
@@ -281,13 +296,10 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
         ctx->grid = std::max(1, ctx->cu_count) * 8;
         const FixedLayout f = fixed_layout(kMaxTrees, 0);
         check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_trees, kMaxTrees * sizeof(TreeDesc), hipHostMallocDefault),
+        check(hipHostMalloc((void**)&ctx->h_call, (size_t)call_layout(kMaxTrees * 2, kMaxTrees).bytes,
+                            hipHostMallocDefault),
               "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_images, kMaxTrees * sizeof(ImageDesc), hipHostMallocDefault),
-              "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_lists, kMaxTrees * sizeof(PointsDesc), hipHostMallocDefault),
-              "hipHostMalloc");
-        check(hipHostMalloc((void**)&ctx->h_scratch, 256, hipHostMallocDefault), "hipHostMalloc");
+        ctx->h_trees = reinterpret_cast<TreeDesc*>(ctx->h_call);
         if (cfg->flags & HH_FLAG_TIMING) {
             ctx->events.resize(3 + 4 * kMaxLevels, nullptr);
             for (auto& e : ctx->events) check(hipEventCreate(&e), "hipEventCreate");
@@ -314,10 +326,7 @@ void engine_destroy(hh_ctx* ctx)
         ctx->live_results.clear();
     }
     if (ctx->h_fixed) (void)hipHostFree(ctx->h_fixed);
-    if (ctx->h_trees) (void)hipHostFree(ctx->h_trees);
-    if (ctx->h_images) (void)hipHostFree(ctx->h_images);
-    if (ctx->h_lists) (void)hipHostFree(ctx->h_lists);
-    if (ctx->h_scratch) (void)hipHostFree(ctx->h_scratch);
+    if (ctx->h_call) (void)hipHostFree(ctx->h_call);
     delete ctx;
 }
 
@@ -485,7 +494,8 @@ struct BudgetExceeded {
 // everything the finished stages left (level records, cells, voters, the
 // level's tables, list and count results); a failure of the root setup
 // reruns it.  On return the level and tree records are in ctx->h_fixed and
-// the trees (with their point counts) in h_trees.
+// the first back_bytes of the trees' block (the trees with their point
+// counts, for the first group also the staging error word) in h_trees.
 struct GroupRun {
     DevBuf arena;
     FixedLayout fl{};
@@ -494,7 +504,7 @@ struct GroupRun {
 };
 
 void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees, int32_t n_trees, int32_t dmax,
-               const uint32_t* xy, TreeDesc* h_trees, hh_timing& tm, GroupRun& g)
+               const uint32_t* xy, TreeDesc* h_trees, int64_t back_bytes, hh_timing& tm, GroupRun& g)
 {
     hipStream_t st = ctx->stream;
     DevicePool* pool = &ctx->pool;
@@ -562,8 +572,7 @@ void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees
         mark(ctx, 2);
         check(hipMemcpyAsync(ctx->h_fixed, g.arena.get(), (size_t)g.fl.head_bytes, hipMemcpyDeviceToHost, st),
               "copy level records");
-        check(hipMemcpyAsync(h_trees, trees, sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyDeviceToHost, st),
-              "copy trees back");
+        check(hipMemcpyAsync(h_trees, trees, (size_t)back_bytes, hipMemcpyDeviceToHost, st), "copy trees back");
         sync(ctx);
         g.err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + g.fl.error);
         const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
@@ -645,8 +654,12 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     const int32_t entry_bytes = kind == 0 ? 8 : 4;   // point lists keep their own ids
 
     auto store = std::make_shared<CallStore>();
-    DevBuf hx, hy, himg, tcount, tpre, d_desc;
+    DevBuf hx, hy, himg, tcount, tpre;
     int64_t n_tiles = 0, total_points = 0;
+    const CallLayout cl = call_layout(n_trees, n);
+    PointsDesc* const h_lists = reinterpret_cast<PointsDesc*>(ctx->h_call + cl.desc);
+    ImageDesc* const h_images = reinterpret_cast<ImageDesc*>(ctx->h_call + cl.desc);
+    uint32_t* const h_err = reinterpret_cast<uint32_t*>(ctx->h_call + cl.err);
     if (kind == 0) {
         // point lists: host lists are gathered into one upload
         int64_t host_points = 0;
@@ -684,7 +697,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         int64_t at = 0;
         for (int32_t k = 0; k < n; ++k) {
             const hh_input* in = &inputs[k];
-            PointsDesc& d = ctx->h_lists[k];
+            PointsDesc& d = h_lists[k];
             d.x = in->on_device ? in->x : hx.as<int32_t>() + at;
             d.y = in->on_device ? in->y : hy.as<int32_t>() + at;
             if (!in->on_device) at += in->n_points;
@@ -693,9 +706,6 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             d.width = in->width;
             d.height = in->height;
         }
-        d_desc = DevBuf(pool, sizeof(PointsDesc) * (size_t)n);
-        check(hipMemcpyAsync(d_desc.get(), ctx->h_lists, sizeof(PointsDesc) * (size_t)n, hipMemcpyHostToDevice, st),
-              "copy point lists");
         store->points = DevBuf(pool, (size_t)std::max<int64_t>(total_points, 1) * 4);
     } else {
         // binary images: host images are packed into one upload
@@ -713,7 +723,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         for (int32_t k = 0; k < n; ++k) {
             const hh_input* in = &inputs[k];
             const int64_t stride = in->row_stride ? in->row_stride : in->width;
-            ImageDesc& d = ctx->h_images[k];
+            ImageDesc& d = h_images[k];
             d.width = in->width;
             d.height = in->height;
             d.n_pix = (int64_t)in->width * in->height;
@@ -732,9 +742,6 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             }
             ip[(size_t)k].n_points = -1;
         }
-        d_desc = DevBuf(pool, sizeof(ImageDesc) * (size_t)n);
-        check(hipMemcpyAsync(d_desc.get(), ctx->h_images, sizeof(ImageDesc) * (size_t)n, hipMemcpyHostToDevice, st),
-              "copy image table");
         store->points = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
         tcount = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 4);
         tpre = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 8);
@@ -763,31 +770,32 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         for (int p = 0; p < 2; ++p)
             if (passes & (1u << p)) tree_pass[c++] = p;
     }
-    DevBuf d_trees(pool, sizeof(TreeDesc) * (size_t)n_trees);
-    check(hipMemcpyAsync(d_trees.get(), ctx->h_trees, sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyHostToDevice, st),
-          "copy trees");
+    // trees, a cleared staging error word and the input table in one upload
+    *h_err = 0;
+    const int64_t call_bytes = cl.desc + (int64_t)n * (kind == 0 ? sizeof(PointsDesc) : sizeof(ImageDesc));
+    DevBuf d_call(pool, (size_t)call_bytes);
+    check(hipMemcpyAsync(d_call.get(), ctx->h_call, (size_t)call_bytes, hipMemcpyHostToDevice, st), "copy descriptors");
+    TreeDesc* const d_trees = d_call.as<TreeDesc>();
+    uint32_t* const d_err = reinterpret_cast<uint32_t*>(d_call.as<char>() + cl.err);
+    char* const d_desc = d_call.as<char>() + cl.desc;
 
     // ---- edge staging of every input (the groups below share it)
     hh_timing tm{};
     mark(ctx, 0);
-    DevBuf stage_err(pool, 256);
-    check(hipMemsetAsync(stage_err.get(), 0, sizeof(uint32_t), st), "clear");
     if (kind == 0) {
-        check(launch_pack_points(d_desc.as<PointsDesc>(), n, total_points, xy, stage_err.as<uint32_t>(), st), "pack");
+        check(launch_pack_points(reinterpret_cast<const PointsDesc*>(d_desc), n, total_points, xy, d_err, st), "pack");
     } else {
         ExtractArgs ea{};
-        ea.images = d_desc.as<ImageDesc>();
+        ea.images = reinterpret_cast<const ImageDesc*>(d_desc);
         ea.n_images = n;
         ea.n_tiles = n_tiles;
         ea.xy = xy;
         ea.tile_count = tcount.as<int32_t>();
         ea.tile_pre = tpre.as<int64_t>();
-        ea.trees = d_trees.as<TreeDesc>();
+        ea.trees = d_trees;
         ea.n_trees = n_trees;
         check(launch_extract(ea, st), "extract");
     }
-    check(hipMemcpyAsync(ctx->h_scratch, stage_err.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, st),
-          "copy staging error");
     mark(ctx, 1);
 
     // ---- groups of consecutive inputs whose level lists fit one arena.
@@ -798,8 +806,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     auto points_of = [&](int32_t k) { return ctx->h_trees[(size_t)k * n_pass].n_points; };
     auto ensure_counts = [&] {
         if (counts_known) return;
-        check(hipMemcpyAsync(ctx->h_trees, d_trees.get(), sizeof(TreeDesc) * (size_t)n_trees, hipMemcpyDeviceToHost,
-                             st),
+        check(hipMemcpyAsync(ctx->h_trees, d_trees, (size_t)(cl.err + 4), hipMemcpyDeviceToHost, st),
               "copy trees back");
         sync(ctx);
         counts_known = true;
@@ -818,7 +825,9 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         const int32_t t0g = k0 * n_pass, ntg = (k1 - k0) * n_pass;
         GroupRun g;
         try {
-            run_group(ctx, p0, entry_bytes, d_trees.as<TreeDesc>() + t0g, ntg, dmax, xy, ctx->h_trees + t0g, tm, g);
+            // the first group also brings back the staging error word
+            const int64_t back = k0 == 0 ? cl.err + 4 : (int64_t)ntg * (int64_t)sizeof(TreeDesc);
+            run_group(ctx, p0, entry_bytes, d_trees + t0g, ntg, dmax, xy, ctx->h_trees + t0g, back, tm, g);
         } catch (const BudgetExceeded& b) {
             if (k1 - k0 <= 1)
                 throw Error{HH_ECAPACITY, "input " + std::to_string(k0) + " needs more than " +
@@ -831,7 +840,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             continue;
         }
         if (g.err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
-        if (*ctx->h_scratch & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
+        if (*h_err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
         counts_known = true;
 
         const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);

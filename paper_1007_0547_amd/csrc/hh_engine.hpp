@@ -143,10 +143,10 @@ struct hh_ctx {
     // pinned host copies: an arena's fixed part (level records, tree records,
     // error), the trees of a call, the descriptors of its inputs
     char* h_fixed = nullptr;
-    hh::TreeDesc* h_trees = nullptr;
-    hh::ImageDesc* h_images = nullptr;
-    hh::PointsDesc* h_lists = nullptr;
-    uint32_t* h_scratch = nullptr;      // 256 bytes: the staging error word of a call
+    // a call's descriptors in one block, uploaded with one copy: the trees,
+    // the staging error word, then the input table (see call_layout)
+    char* h_call = nullptr;
+    hh::TreeDesc* h_trees = nullptr;    // = h_call
     // arena sizes that worked before (grown when a call overflows)
     int64_t half_cap = 64ll << 20;      // bytes per level half
     int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
