@@ -59,6 +59,17 @@ __device__ inline void raise_error(uint32_t* error, uint32_t bits)
     __hip_atomic_fetch_or(G(error), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup barrier that orders LDS only.  The level kernels share nothing
+// but LDS inside a workgroup, so their barriers need not wait for the
+// wavefront's outstanding global stores (a full __syncthreads would drain
+// them at every tile).
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // set bits of b at lanes below this lane
 __device__ inline uint32_t lanes_below(uint64_t b)
 {
@@ -522,8 +533,6 @@ __device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, con
         const uint64_t tail = ~bits_below(prev);
 #pragma unroll
         for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
-        // one row at a time: rows interleaved by the scheduler only cost registers
-        __builtin_amdgcn_sched_barrier(0);
     }
     wc.open = open;
     wc.closed = closed;
@@ -572,10 +581,6 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
     TileBounds tb = tile_bounds(tile_first, tile, nt, P);
     for (;;) {
         const int64_t next = tile + gridDim.x;
-        Entry nent[kRows];
-        load_rows(list, L, next, wave, lane, nent);
-        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
-
         const int64_t t0 = tile * kTile;
         const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
         if (!bounds_ok(tb, P)) {
@@ -583,11 +588,17 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
             return;
         }
         const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
-        __syncthreads();   // the previous tile is done with S (its bitmap is clear again)
+        lds_barrier();   // the previous tile is done with S (its bitmap is clear again)
         const bool carried = stage_tile(S.bm, S.sr, regions, t0, tb);
         if constexpr (kVariant == 0 && sizeof(CT) == 4)
             for (int k = tid; k < nr && k < kStage; k += kBlock) S.cc[k] = ccg[r0 + k];
-        __syncthreads();
+        lds_barrier();
+        // the next tile's entries and bounds, issued only now: loads complete in
+        // order, so a wait for this tile's region fields would otherwise wait
+        // for them too
+        Entry nent[kRows];
+        load_rows(list, L, next, wave, lane, nent);
+        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
         WaveCount wc;
         if (nr <= kStage)
             count_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0}, S.cc, S.bm, ent, rb, L, lc,
@@ -604,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
             S.wlocal[wave] = wc.open;
             S.wclosed[wave] = wc.closed ? 1 : 0;
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < 4) {   // one thread per child slot
             const int q = tid;
             int cur = 0;
@@ -1117,19 +1128,14 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     bool bad = false;
     for (int it = 0;; ++it) {
         const int64_t next = tile + gridDim.x;
-        Entry nent[kRows];
-        load_rows(list, L, next, wave, lane, nent);
-        const uint32_t nvword = next < nt ? vbits[next * kBlock + tid] : 0u;
-        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
-
         const int64_t t0 = tile * kTile;
-                if (!bounds_ok(tb, P)) {
+        if (!bounds_ok(tb, P)) {
             if (tid == 0) raise_error(ar.error, kErrInternal);
             return;
         }
         const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
         uint32_t* const bm = S.bm[it & 1];
-        __syncthreads();   // the previous tile is done with S
+        lds_barrier();   // the previous tile is done with S
         if (tid < kTile / 32) S.bm[(it + 1) & 1][tid] = 0u;   // last read two tiles ago
         const bool carried = stage_tile(bm, S.sr, regions, t0, tb);
         for (int k = tid; k < nr && k < kStage; k += kBlock) {
@@ -1153,7 +1159,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             for (int q = 0; q < 4; ++q) c[q] = wave_sum32(c[q]);
             if (lane < 4) S.tpre[lane] = pick4(c, lane) + head[(int64_t)r0 * 4 + lane];
         }
-        __syncthreads();
+        lds_barrier();
 
         const int open = starts_before(bm, wave, lane);
         int32_t run[4];
@@ -1163,6 +1169,12 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             for (int q = 0; q < 4; ++q)
                 run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? S.tpre[q] : 0);
         }
+        // the next tile's entries, vote bits and bounds, issued only once this
+        // tile's tables are read (loads complete in order)
+        Entry nent[kRows];
+        load_rows(list, L, next, wave, lane, nent);
+        const uint32_t nvword = next < nt ? vbits[next * kBlock + tid] : 0u;
+        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
         if (nr <= kStage)
             write_rows<Entry, true>(RegionSource<true>{S.sr, regions, r0},
                                     KidSource<true>{S.dst, S.cv, dsti, cvi, r0}, bm, ent, vword, wave, lane, nr, run,
