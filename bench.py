@@ -172,7 +172,67 @@ def bench_batched(seed, reps=3):
                   "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                  "p99": float(np.percentile(lat, 99) * 1e3)}},
         "batched_over_plain": plain_s / batch_s,
+        "roofline": {k: {"alg_bytes": v, "GB/s": v / (kt[f"{k}_ms"] / 1e3) / 1e9,
+                         "frac": v / (kt[f"{k}_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+                     for k, v in kernel_bytes(kt, 4).items()},
     }
+
+
+def bench_large(seed, reps=3):
+    """The 4096x4096 image (128 segments of length U[500, 4000], 1% noise,
+    T = 300, depth 12, both passes, voters kept): time per image and the
+    per-level footprint of its level lists."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("seg4096", seed)
+    img = torch.from_numpy(w.image).to(dev)
+    ctx = HoughHier(threshold=w.threshold, max_depth=w.max_depth, membership=True, device=0,
+                    stream=torch.cuda.current_stream(dev))
+    ctx.detect(image=img, width=w.width, height=w.height).free()   # learns the arena sizes
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.detect(image=img, width=w.width, height=w.height).free()
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / reps
+    ctx_t = HoughHier(threshold=w.threshold, max_depth=w.max_depth, membership=True, device=0,
+                      stream=torch.cuda.current_stream(dev), timing=True)
+    ctx_t.detect(image=img, width=w.width, height=w.height).free()
+    rt = ctx_t.detect(image=img, width=w.width, height=w.height)
+    kt = rt.timing()
+    rt.free()
+    ctx_t.close()
+    kb = kernel_bytes(kt, 4)
+    r = ctx.detect(image=img, width=w.width, height=w.height)
+    st = [r.stats(p) for p in (0, 1)]
+    info = r.info
+    levels = []
+    for l in range(info["depth"]):
+        regions = int(st[0]["split"][l] + st[1]["split"][l])
+        entries = int(st[0]["entries"][l] + st[1]["entries"][l])
+        # a level's half: region table (24 B), code constants (16 B) and child
+        # votes (16 B) per region, the tile map, and the list (4 B per entry)
+        levels.append({"level": l, "regions": regions, "list_entries": entries,
+                       "bytes": regions * 56 + (entries // 2048 + 1) * 4 + entries * 4})
+    out = {"workload": f"seg4096: 4096x4096 binary image, seed {seed}, 128 segments, 1% noise, T={w.threshold}, "
+                       f"depth {info['depth']}, both passes, voters kept on device",
+           "edge_points": info["n_points"], "cells": sum(info["n_cells"]), "code_tests": info["code_tests"],
+           "ms_per_image": dt * 1e3, "code_tests_per_s": info["code_tests"] / dt,
+           "member_entries": info["member_slots"],
+           "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"], "decide": kt["decide_ms"],
+                         "extract": kt["extract_ms"]},
+           "roofline": {k: {"alg_bytes": kb[k], "GB/s": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9,
+                            "frac": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+                        for k in ("count", "write")},
+           "level_footprint": levels}
+    r.free()
+    ctx.close()
+    return out
 
 
 def bench_serving(seed, seconds, pool_size=128):
@@ -298,6 +358,7 @@ def main():
     ap.add_argument("--wide", action="store_true", help="64-bit corner compares")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
+    ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 image")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -421,6 +482,8 @@ def main():
     ctx.close()
     if not args.no_batched:
         out["batch512"] = bench_batched(args.seed)
+    if not args.no_large:
+        out["seg4096"] = bench_large(args.seed)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(args.seed, args.serve_seconds)
     if not args.no_cpu_baseline:

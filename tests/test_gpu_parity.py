@@ -212,3 +212,64 @@ def test_repeatable_and_context_reuse(hh):
         for o in outs[1:]:
             for a, b in zip(o, outs[0]):
                 np.testing.assert_array_equal(a, b)
+
+
+class _DevView:
+    """A device byte range as a torch tensor (no copy)."""
+
+    def __init__(self, ptr, nbytes):
+        self.__cuda_array_interface__ = {"shape": (int(nbytes),), "typestr": "|u1",
+                                         "data": (int(ptr), False), "version": 2}
+
+
+def dev_array(ptr, count, dtype):
+    import torch
+    dtype = np.dtype(dtype)
+    if count == 0:
+        return np.zeros(0, dtype)
+    return torch.as_tensor(_DevView(ptr, count * dtype.itemsize), device="cuda").cpu().numpy().view(dtype).copy()
+
+
+def test_seg4096_full_size_sampled(hh):
+    """The 4096x4096 workload at full size (the oracle takes minutes on it):
+    sampled detected cells against the direct test of every line (a detected
+    finest cell's voters are exactly the lines crossing it), sampled other
+    finest cells hold at most T crossing lines, and the statistics keep
+    their invariants.  Voters are compared as the packed points the kernels
+    store, read from the device for the sampled cells only."""
+    import torch
+    w = synth.workload("seg4096", 0)
+    say("case seg4096 full size, sampled cells")
+    x, y = oracle.edge_points(w.image)
+    packed = (x.astype(np.uint32) | (y.astype(np.uint32) << 16))
+    img = torch.from_numpy(w.image).cuda()
+    rng = np.random.default_rng(7)
+    with hh.HoughHier(threshold=w.threshold, max_depth=w.max_depth) as ctx:
+        r = ctx.detect(image=img, width=w.width, height=w.height)
+        assert r.info["n_points"] == len(x)
+        ent_ptr, n_ent, eb = r.member_points()
+        assert eb == 4
+        D = r.info["depth"]
+        for p in (0, 1):
+            dptr, n = r.device_cells(p)
+            cells = dev_array(dptr, n, hh.CELL_DTYPE)
+            st = r.stats(p)
+            assert n == st["detected"][-1] and n > 0
+            assert np.all(np.diff(cells["key"]) > 0) and np.all(cells["votes"] > w.threshold)
+            np.testing.assert_array_equal(st["evaluated"][1:], 4 * st["split"][:-1])
+            for c in rng.choice(n, size=min(40, n), replace=False):
+                i, j, v, o = (int(cells[f][c]) for f in ("i", "j", "votes", "member_off"))
+                want = oracle.region_voters(x, y, w.width, w.height, p, D, i, j)
+                assert v == len(want), (p, i, j, v, len(want))
+                got = dev_array(ent_ptr + 4 * o, v, np.uint32)
+                np.testing.assert_array_equal(got, packed[want])
+            detected = set(zip(cells["i"].tolist(), cells["j"].tolist()))
+            n_side = 1 << D
+            tried = 0
+            while tried < 60:
+                i, j = int(rng.integers(0, n_side)), int(rng.integers(0, n_side))
+                if (i, j) in detected:
+                    continue
+                tried += 1
+                assert len(oracle.region_voters(x, y, w.width, w.height, p, D, i, j)) <= w.threshold
+        r.free()
