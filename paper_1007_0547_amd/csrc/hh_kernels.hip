@@ -475,8 +475,11 @@ __device__ inline uint32_t lane_votes(const RegionSource<kStaged>& src, const Co
                                       uint32_t point, uint64_t vm, int lc, int lane)
 {
     if constexpr (kVariant == 0 && sizeof(CT) == 4) {
-        // staged: cc is the tile's LDS copy; otherwise the level's table from region r0
-        return ((vm >> lane) & 1u) ? code_votes(point, cc[local], lc) : 0u;
+        // staged: cc is the tile's LDS copy; otherwise the level's table from
+        // region r0.  Lanes past the list end compute on a zero entry and are
+        // masked afterwards (no branch).
+        const uint32_t vb = code_votes(point, cc[local], lc);
+        return ((vm >> lane) & 1u) ? vb : 0u;
     } else {
         uint32_t ij, meta;
         src.fields(local, ij, meta);
@@ -518,7 +521,8 @@ __device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, con
 #pragma unroll
             for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & seg);
             if (open_here) {   // began and ended in this wavefront: its total
-                if (lane < 4) cv[(int64_t)(src.r0 + open) * 4 + lane] = pick4(run, lane);
+                if (lane == 0)
+                    *reinterpret_cast<int4*>(cv + (int64_t)(src.r0 + open) * 4) = int4{run[0], run[1], run[2], run[3]};
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) first[q] = run[q];
