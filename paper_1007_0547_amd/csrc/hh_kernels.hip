@@ -668,8 +668,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
 __device__ inline void range_of(int64_t nb, int g, int64_t& b0, int64_t& b1)
 {
-    b0 = nb * g / kRangeGrid;
-    b1 = nb * (g + 1) / kRangeGrid;
+    if (nb <= kRangeGrid) {   // one block per range, in the first workgroups dispatched
+        b0 = std::min<int64_t>(g, nb);
+        b1 = std::min<int64_t>(g + 1, nb);
+    } else {
+        b0 = nb * g / kRangeGrid;
+        b1 = nb * (g + 1) / kRangeGrid;
+    }
 }
 
 // Decision channels of one region from its child votes.
