@@ -6,8 +6,7 @@ Every step of the vote runs in the library's HIP kernels.  PyTorch is used
 only to hand over device memory (``torch.Tensor.data_ptr()``) and streams.
 
 Importing this package requires the built library; build it with
-``python -c "import __graft_entry__ as g; g.build()"`` (or
-``python paper_1007_0547_amd/_build.py``).
+``python paper_1007_0547_amd/_build.py``.
 """
 from __future__ import annotations
 
