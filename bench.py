@@ -54,16 +54,25 @@ def kernel_bytes(timing, entry_bytes):
     n_in, n_out = timing["vote_entries"], timing["vote_written"]
     return {"count": entry_bytes * n_in, "write": entry_bytes * (n_in + n_out)}
 
+def kernel_source_digest():
+    """sha256 of the kernel source with comments and blank space removed, so
+    that only a change of the code itself counts as a new kernel."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_1007_0547_amd", "csrc", "hh_kernels.hip")).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per step of `kernel` from the committed rocprofv3 summary
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_write_seg1024_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_1007_0547_amd", "csrc", "hh_kernels.hip")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_digest()
     except OSError:
         return None
     fields = {}

@@ -17,7 +17,7 @@
  *     is below the line; a corner on the line counts as above.  Corners are
  *     dyadic, so each bit is an exact integer compare with m and b scaled by
  *     2^level.
- *   - Sec. 3 pseudo-code (steps 5, 12.b, 12.v, 13): a line votes for a region
+ *   - Sec. 3 pseudo-code (vote test, descent, threshold test): a line votes for a region
  *     iff its code is neither 0000 nor 1111; a child only tests the lines
  *     that voted for its parent; a region with votes > threshold splits, and
  *     at the finest level (default ceil(log2 N)) it is reported as a

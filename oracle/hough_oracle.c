@@ -23,11 +23,11 @@
  *     1 when the corner is below the line, and a corner on the line counts as
  *     above (F = b_c + u*m_c - v >= 0).  Corners are dyadic, so each test is
  *     an exact integer compare after scaling m and b by 2^l.
- *   - Sec. 3 pseudo-code, steps 5 and 12.v: a line votes for a region iff its
+ *   - Sec. 3, the vote test of the pseudo-code: a line votes for a region iff its
  *     code is neither 0000 nor 1111.
- *   - Sec. 3 pseudo-code, step 12.b: a child region only tests the lines
+ *   - Sec. 3, the descent of the pseudo-code: a child region only tests the lines
  *     that voted for its parent.
- *   - Sec. 3 pseudo-code, step 13: a region with votes > THRESHOLD is split,
+ *   - Sec. 3, the threshold test of the pseudo-code: a region with votes > THRESHOLD is split,
  *     or, at the finest level, handed to solution(), which reports its voting
  *     edge points.  Regions are visited depth first in quad order.
  *   - Sec. 2 / Sec. 3 (comparison method of the paper's ref. [9]): the
@@ -127,7 +127,7 @@ static int votes_for_region(const or_walk* w, int l, int64_t i, int64_t j, int32
         return circle_votes(w->S, l, i, j, u, v);
     {
         const int code = getcode(w->S, l, i, j, u, v);
-        return code != 0 && code != 15;           /* steps 5 and 12.v */
+        return code != 0 && code != 15;           /* Sec. 3 vote test */
     }
 }
 

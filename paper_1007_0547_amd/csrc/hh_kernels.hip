@@ -12,11 +12,11 @@
 // Per level, four launches:
 //   k_count   one read of every entry: the 4-bit corner codes of the line for
 //             the four children (Sec. 2, getcode()) and the vote rule (code
-//             not 0000 / 1111, steps 5 and 12.v) as wavefront lane masks, and
+//             not 0000 / 1111, Sec. 3) as wavefront lane masks, and
 //             per tile of kTile entries the child-vote counts of every
 //             region piece in it.
 //   k_decide  per region: its child votes (its pieces summed), the split
-//             decisions (step 13) and their sums per range of regions.
+//             decisions (votes > T, Sec. 3) and their sums per range of regions.
 //   k_emit    per region: offsets from those sums; the next level's region
 //             table in quad order (so key order is kept) and tile map, or the
 //             detected cells at the finest level.
