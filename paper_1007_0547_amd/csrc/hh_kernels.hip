@@ -49,10 +49,11 @@ __device__ inline T* G(T* p)
     return (T*)(__attribute__((address_space(1))) T*)p;
 }
 
-__device__ inline bool stopped(uint32_t* error)
-{
-    return (__hip_atomic_load(G(error), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrStop) != 0;
-}
+// Whether an earlier launch stopped the call.  A plain load: errors of earlier
+// launches are visible at the kernel boundary, and an error raised by a
+// concurrent workgroup of this launch need not stop the others.  Kernels load
+// it together with their level sizes, so the check costs no extra round trip.
+__device__ inline bool stopped(uint32_t err) { return (err & kErrStop) != 0; }
 
 __device__ inline void raise_error(uint32_t* error, uint32_t bits)
 {
@@ -559,11 +560,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    if (stopped(ar.error)) return;
     const int l = a.level;
     const int lc = l + 1;
+    const uint32_t err = *G(ar.error);
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
-    if (P == 0) return;
+    if (stopped(err) || P == 0) return;
     const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
     const WorkLayout wl = work_layout(ar.work, P, L);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) {
@@ -717,10 +718,10 @@ __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    if (stopped(ar.error)) return;
     const int l = a.level;
+    const uint32_t err = *G(ar.error);
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
-    if (P == 0) return;
+    if (stopped(err) || P == 0) return;
     const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
     const WorkLayout wl = work_layout(ar.work, P, L);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;   // k_count raised the error
@@ -775,10 +776,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    if (stopped(ar.error)) return;
     const int l = a.level;
     const int lc = l + 1;
+    const uint32_t err = *G(ar.error);
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    if (stopped(err)) return;
     const int64_t cells_base = ar.info[l].cells_base + ar.info[l].cells;
     const int64_t mem_base = ar.info[l].mem_base + ar.info[l].mem;
     if (P == 0) {
@@ -1104,11 +1106,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    if (stopped(ar.error)) return;
     const int l = a.level;
     const int lc = l + 1;
+    const uint32_t err = *G(ar.error);
     const int64_t P = ar.info[l].P, L = ar.info[l].L;
-    if (P == 0) return;
+    if (stopped(err) || P == 0) return;
     const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
     const WorkLayout wl = work_layout(ar.work, P, L);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
@@ -1435,9 +1437,9 @@ template <typename Entry>
 __global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc* trees, const uint32_t* xy)
 {
     __shared__ int64_t s_start[kMaxTrees];
-    if (stopped(ar.error)) return;
+    const uint32_t err = *G(ar.error);
     const int64_t P0 = ar.info[0].P, L0 = ar.info[0].L;
-    if (P0 == 0) return;
+    if (stopped(err) || P0 == 0) return;
     const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     for (int64_t r = threadIdx.x; r < P0; r += kBlock) s_start[r] = regions[r].start;
