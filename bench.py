@@ -244,6 +244,59 @@ def bench_large(seed, reps=3):
     return out
 
 
+def bench_sweep(seed, reps=20):
+    """Code test against the circle test (the comparison method) at the sizes
+    of the paper's Table 1 (32..256, T = 40, both passes): total votes (sum
+    over evaluated regions) and GPU time per image, their ratios C_v and C_t,
+    and whether the GPU votes equal the oracle's.  Images: full-span lines
+    with 1% noise (the paper's own images are not available)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    out = []
+    for n in (32, 64, 128, 256):
+        img = synth.full_span_image(seed, n, n, 8, 0.01)
+        x, y = oracle.edge_points(img)
+        d_img = torch.from_numpy(img).to(dev)
+        row = {"size": n, "edge_points": int(len(x))}
+        for variant in ("code", "circle"):
+            ctx = HoughHier(threshold=40, variant=variant, membership=True, device=0,
+                            stream=torch.cuda.current_stream(dev))
+            for _ in range(3):
+                ctx.detect(image=d_img, width=n, height=n).free()
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.detect(image=d_img, width=n, height=n).free()
+            torch.cuda.synchronize(dev)
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            r = ctx.detect(image=d_img, width=n, height=n)
+            votes = int(sum(int(r.stats(p)["votes"].sum()) for p in (0, 1)))
+            r.free()
+            ctx.close()
+            t0 = time.perf_counter()
+            ref = oracle.detect(x, y, n, n, 40, 0, variant)
+            row[f"oracle_ms_{variant}"] = (time.perf_counter() - t0) * 1e3
+            ref_votes = int(sum(int(ref.stats[p][:, 1].sum()) for p in (0, 1)))
+            row[f"votes_{variant}"] = votes
+            row[f"ms_{variant}"] = ms
+            row[f"oracle_votes_equal_{variant}"] = votes == ref_votes
+        row["C_v"] = row["votes_circle"] / max(row["votes_code"], 1)
+        row["C_t"] = row["ms_circle"] / row["ms_code"]
+        row["C_t_oracle"] = row["oracle_ms_circle"] / row["oracle_ms_code"]
+        out.append(row)
+    return {"workload": f"full-span lines (8) with 1% noise, seed {seed}, T=40, default depth, both passes",
+            "sizes": out,
+            "paper_context": "the paper's Table 1 (FHT in floating point against the code test, Pentium IV): "
+                             "C_v 7.5-7.7 and C_t 1340-1873 at 256x256; the circle test here is exact "
+                             "integer arithmetic, so C_t reflects only the extra votes"}
+
+
 def bench_serving(seed, seconds, pool_size=128):
     """Serving: Poisson arrivals of images (sides log-uniform 256..4096,
     Poisson(48) segments, 1% noise, T = floor(side / 10), default depth),
@@ -368,6 +421,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 image")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the code/circle size sweep")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -493,6 +547,8 @@ def main():
         out["batch512"] = bench_batched(args.seed)
     if not args.no_large:
         out["seg4096"] = bench_large(args.seed)
+    if not args.no_sweep:
+        out["size_sweep"] = bench_sweep(args.seed)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(args.seed, args.serve_seconds)
     if not args.no_cpu_baseline:
