@@ -16,6 +16,9 @@ never does, and the two share no code.
   line against it directly, with no hierarchy.
 * :func:`solution` -- solution() of Sec. 3 with the removal of plotted edge
   points, as a greedy walk over the detected cells in depth-first order.
+* :func:`sobel_partition` -- the edge front end of Sec. 3: Sobel's gradient
+  operator on a gray image gives the edge points and, from the gradient
+  direction, the set (ALPHA or BETA) each one belongs to.
 """
 from __future__ import annotations
 
@@ -94,6 +97,42 @@ def edge_points(image: np.ndarray):
         raise ValueError("image must be 2-D (H, W)")
     ys, xs = np.nonzero(img)
     return xs.astype(np.int32), ys.astype(np.int32)
+
+
+def sobel_partition(gray: np.ndarray, edge_threshold: int):
+    """Sobel's gradient operator (Sec. 3: edge points are sorted into ALPHA
+    and BETA while the operator is applied) on a gray image.
+
+    Gx and Gy are the 3x3 Sobel sums, written out term by term:
+    Gx = (p[y-1,x+1] + 2 p[y,x+1] + p[y+1,x+1]) - (p[y-1,x-1] + 2 p[y,x-1] + p[y+1,x-1]),
+    Gy = (p[y+1,x-1] + 2 p[y+1,x] + p[y+1,x+1]) - (p[y-1,x-1] + 2 p[y-1,x] + p[y-1,x+1]).
+    A pixel with a full 3x3 neighbourhood is an edge point iff
+    Gx^2 + Gy^2 > edge_threshold^2 (exact integers); border pixels never are.
+    The image line through an edge point runs across its gradient, so its
+    slope is -Gx/Gy: the point is in ALPHA (|slope| <= 1, pass 0) iff
+    |Gx| <= |Gy|, else in BETA (pass 1, axes swapped).
+
+    Returns ``(x, y, beta)``: all edge points row-major (point id = position)
+    and a bool array, True for BETA."""
+    p = np.asarray(gray)
+    if p.ndim != 2:
+        raise ValueError("image must be 2-D (H, W)")
+    H, W = p.shape
+    xs, ys, beta = [], [], []
+    if H >= 3 and W >= 3:
+        q = p.astype(np.int64)
+        n = q[:-2, 1:-1]
+        s_ = q[2:, 1:-1]
+        w = q[1:-1, :-2]
+        e = q[1:-1, 2:]
+        nw, ne, sw, se = q[:-2, :-2], q[:-2, 2:], q[2:, :-2], q[2:, 2:]
+        gx = (ne + 2 * e + se) - (nw + 2 * w + sw)
+        gy = (sw + 2 * s_ + se) - (nw + 2 * n + ne)
+        edge = gx * gx + gy * gy > int(edge_threshold) * int(edge_threshold)
+        yy, xx = np.nonzero(edge)
+        return ((xx + 1).astype(np.int32), (yy + 1).astype(np.int32),
+                (np.abs(gx[yy, xx]) > np.abs(gy[yy, xx])))
+    return np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, bool)
 
 
 def side_pow2(W: int, H: int) -> int:
