@@ -113,17 +113,27 @@ typedef struct {
 } hh_config;
 
 typedef struct {
-    int32_t kind;             /* 0: point list (x, y, n_points); 1: binary image        */
+    int32_t kind;             /* 0: point list (x, y, n_points); 1: binary image;
+                                 2: gray image through the Sobel front end (Sec. 3):
+                                 the edge points are the pixels with a full 3x3
+                                 neighbourhood and Gx^2 + Gy^2 > edge_threshold^2;
+                                 pass 0 takes those with |Gx| <= |Gy| (ALPHA, image
+                                 lines with |slope| <= 1), pass 1 the others (BETA).
+                                 Point ids are ranks among all edge points, row-major;
+                                 depth must be >= 1                                    */
     int32_t width, height;    /* W, H >= 1                                              */
     int32_t on_device;        /* 1: x, y, image are device pointers valid on the stream */
     const int32_t* x;         /* kind 0: x[k] in [0, W)                                 */
     const int32_t* y;         /* kind 0: y[k] in [0, H)                                 */
     int64_t n_points;         /* kind 0: number of points (0 allowed)                   */
-    const uint8_t* image;     /* kind 1: H rows of W bytes, nonzero = edge pixel         */
-    int64_t row_stride;       /* kind 1: bytes between rows (>= W; 0 means W)            */
+    const uint8_t* image;     /* kind 1: H rows of W bytes, nonzero = edge pixel;
+                                 kind 2: H rows of W gray levels                        */
+    int64_t row_stride;       /* kinds 1, 2: bytes between rows (>= W; 0 means W)        */
     int32_t threshold;        /* T for this input; < 0 takes the context default        */
     int32_t max_depth;        /* depth for this input: 0 = ceil(log2(max(W,H))),
                                  -1 = depth 0, INT32_MIN takes the context default      */
+    int32_t edge_threshold;   /* kind 2: Sobel magnitude threshold (>= 0)               */
+    int32_t reserved;
 } hh_input;
 
 /* One detected finest-level cell.  member_off indexes the members array that

@@ -62,7 +62,8 @@ class _Input(C.Structure):
     _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("on_device", C.c_int32), ("x", C.c_void_p), ("y", C.c_void_p),
                 ("n_points", C.c_int64), ("image", C.c_void_p), ("row_stride", C.c_int64),
-                ("threshold", C.c_int32), ("max_depth", C.c_int32)]
+                ("threshold", C.c_int32), ("max_depth", C.c_int32), ("edge_threshold", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -264,16 +265,19 @@ class HoughHier:
         return (_lib.hough_hier_last_error(self._h) or b"").decode()
 
     @staticmethod
-    def _input(x=None, y=None, *, image=None, width: int, height: int, threshold: int = -1,
-               max_depth: Optional[int] = None):
+    def _input(x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int, height: int,
+               threshold: int = -1, max_depth: Optional[int] = None):
         """An ``hh_input`` and the objects that must outlive the call."""
         inp = _Input()
         inp.width, inp.height = int(width), int(height)
         inp.threshold = int(threshold)
         inp.max_depth = INT32_MIN if max_depth is None else int(max_depth)
         keep = []
+        if gray is not None:   # gray image through the Sobel front end
+            image = gray
+            inp.edge_threshold = int(edge_threshold)
         if image is not None:
-            inp.kind = 1
+            inp.kind = 2 if gray is not None else 1
             if _is_torch_cuda(image):
                 assert image.dtype.itemsize == 1 and image.dim() == 2
                 inp.on_device = 1
@@ -305,13 +309,15 @@ class HoughHier:
                 keep += [hx, hy]
         return inp, keep
 
-    def detect(self, x=None, y=None, *, image=None, width: int, height: int,
-               threshold: int = -1, max_depth: Optional[int] = None) -> Result:
-        """Run the vote on a point list ``(x, y)`` or a binary ``image``
-        (H x W, nonzero = edge).  Torch device tensors are passed as device
-        pointers; anything else is copied from host memory."""
-        inp, keep = self._input(x, y, image=image, width=width, height=height, threshold=threshold,
-                                max_depth=max_depth)
+    def detect(self, x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int,
+               height: int, threshold: int = -1, max_depth: Optional[int] = None) -> Result:
+        """Run the vote on a point list ``(x, y)``, a binary ``image`` (H x W,
+        nonzero = edge) or a ``gray`` image through the Sobel front end (edge
+        points by gradient magnitude, pass 0 / pass 1 by gradient direction).
+        Torch device tensors are passed as device pointers; anything else is
+        copied from host memory."""
+        inp, keep = self._input(x, y, image=image, gray=gray, edge_threshold=edge_threshold, width=width,
+                                height=height, threshold=threshold, max_depth=max_depth)
         out = C.c_void_p()
         s = _lib.hough_hier_detect(self._h, C.byref(inp), C.byref(out))
         del keep
@@ -351,12 +357,13 @@ class HoughHier:
             raise HHError(s, self.last_error())
         self._inflight = {}
 
-    def submit(self, x=None, y=None, *, image=None, width: int, height: int,
-               threshold: int = -1, max_depth: Optional[int] = None) -> int:
-        """Queue one input (``hough_hier_submit``); returns its ticket.  The
-        input objects are kept alive until the ticket is polled."""
-        inp, keep = self._input(x, y, image=image, width=width, height=height, threshold=threshold,
-                                max_depth=max_depth)
+    def submit(self, x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int,
+               height: int, threshold: int = -1, max_depth: Optional[int] = None) -> int:
+        """Queue one input (``hough_hier_submit``, the arguments of
+        :meth:`detect`); returns its ticket.  The input objects are kept alive
+        until the ticket is polled."""
+        inp, keep = self._input(x, y, image=image, gray=gray, edge_threshold=edge_threshold, width=width,
+                                height=height, threshold=threshold, max_depth=max_depth)
         t = C.c_uint64()
         s = _lib.hough_hier_submit(self._h, C.byref(inp), C.byref(t))
         if s != 0:

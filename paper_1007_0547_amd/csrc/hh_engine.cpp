@@ -504,7 +504,8 @@ struct GroupRun {
 };
 
 void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees, int32_t n_trees, int32_t dmax,
-               const uint32_t* xy, TreeDesc* h_trees, int64_t back_bytes, hh_timing& tm, GroupRun& g)
+               const uint32_t* xy, const int32_t* ids, TreeDesc* h_trees, int64_t back_bytes, hh_timing& tm,
+               GroupRun& g)
 {
     hipStream_t st = ctx->stream;
     DevicePool* pool = &ctx->pool;
@@ -551,7 +552,7 @@ void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees
         g.arena = std::move(narena);
         g.ar = nar;
         g.fl = nfl;
-        if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ctx->grid, st), "roots");
+        if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ids, ctx->grid, st), "roots");
         LevelArgs la{};
         la.ar = g.ar;
         la.trees = trees;
@@ -645,16 +646,21 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         const hh_input* in = &inputs[k];
         ip[(size_t)k].plan = make_plan(ctx, in);
         ip[(size_t)k].kind = in->kind;
-        if (in->kind != 0 && in->kind != 1) throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
+        if (in->kind != 0 && in->kind != 1 && in->kind != 2)
+            throw Error{HH_EINVAL, "input kind must be 0 (points), 1 (binary image) or 2 (gray image)"};
+        if (in->kind == 2 && in->edge_threshold < 0) throw Error{HH_EINVAL, "edge_threshold must be >= 0"};
+        if (in->kind == 2 && ip[(size_t)k].plan.dmax == 0)
+            throw Error{HH_EINVAL, "gray images need depth >= 1"};
         if (in->kind != inputs[0].kind) throw Error{HH_EINVAL, "all inputs of a call must be of one kind"};
         dmax_all = std::max(dmax_all, ip[(size_t)k].plan.dmax);
     }
     const Plan& p0 = ip[0].plan;   // variant, compares and membership are the context's
     const int32_t kind = inputs[0].kind;
-    const int32_t entry_bytes = kind == 0 ? 8 : 4;   // point lists keep their own ids
+    // point lists and gray images keep their point ids in the entries
+    const int32_t entry_bytes = kind == 1 ? 4 : 8;
 
     auto store = std::make_shared<CallStore>();
-    DevBuf hx, hy, himg, tcount, tpre;
+    DevBuf hx, hy, himg, tcount, tpre, d_ids;
     int64_t n_tiles = 0, total_points = 0;
     const CallLayout cl = call_layout(n_trees, n);
     PointsDesc* const h_lists = reinterpret_cast<PointsDesc*>(ctx->h_call + cl.desc);
@@ -708,7 +714,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         }
         store->points = DevBuf(pool, (size_t)std::max<int64_t>(total_points, 1) * 4);
     } else {
-        // binary images: host images are packed into one upload
+        // binary or gray images: host images are packed into one upload
         int64_t host_bytes = 0, pix_all = 0;
         for (int32_t k = 0; k < n; ++k) {
             const hh_input* in = &inputs[k];
@@ -728,6 +734,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             d.height = in->height;
             d.n_pix = (int64_t)in->width * in->height;
             d.tile0 = n_tiles;
+            d.edge_threshold = kind == 2 ? in->edge_threshold : 0;
+            d.pad = 0;
             n_tiles += cdiv(d.n_pix, kPixTile);
             if (in->on_device) {
                 d.image = in->image;
@@ -743,8 +751,10 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             ip[(size_t)k].n_points = -1;
         }
         store->points = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
-        tcount = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 4);
-        tpre = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles, 1) * 8);
+        const int64_t sets = kind == 2 ? 2 : 1;   // gray images count ALPHA and BETA apart
+        tcount = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles * sets, 1) * 4);
+        tpre = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles * sets, 1) * 8);
+        if (kind == 2) d_ids = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
     }
     uint32_t* xy = store->points.as<uint32_t>();
 
@@ -764,7 +774,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
                 T.threshold = pl.T;
                 T.pass = p;
                 T.image = k;
-                T.pad = 0;
+                T.image_points = kind == 0 ? (int32_t)ip[(size_t)k].n_points : 0;
             }
         int32_t c = 0;
         for (int p = 0; p < 2; ++p)
@@ -784,6 +794,18 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     mark(ctx, 0);
     if (kind == 0) {
         check(launch_pack_points(reinterpret_cast<const PointsDesc*>(d_desc), n, total_points, xy, d_err, st), "pack");
+    } else if (kind == 2) {
+        SobelArgs sa{};
+        sa.images = reinterpret_cast<const ImageDesc*>(d_desc);
+        sa.n_images = n;
+        sa.n_tiles = n_tiles;
+        sa.xy = xy;
+        sa.ids = d_ids.as<int32_t>();
+        sa.tile_count = tcount.as<int32_t>();
+        sa.tile_pre = tpre.as<int64_t>();
+        sa.trees = d_trees;
+        sa.n_trees = n_trees;
+        check(launch_sobel(sa, st), "sobel");
     } else {
         ExtractArgs ea{};
         ea.images = reinterpret_cast<const ImageDesc*>(d_desc);
@@ -803,7 +825,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     // learnt a point limit; a group that exceeds the budget halves the limit
     // and the remaining inputs are grouped again.
     bool counts_known = kind == 0;
-    auto points_of = [&](int32_t k) { return ctx->h_trees[(size_t)k * n_pass].n_points; };
+    auto points_of = [&](int32_t k) { return (int64_t)ctx->h_trees[(size_t)k * n_pass].image_points; };
     auto ensure_counts = [&] {
         if (counts_known) return;
         check(hipMemcpyAsync(ctx->h_trees, d_trees, (size_t)(cl.err + 4), hipMemcpyDeviceToHost, st),
@@ -827,7 +849,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         try {
             // the first group also brings back the staging error word
             const int64_t back = k0 == 0 ? cl.err + 4 : (int64_t)ntg * (int64_t)sizeof(TreeDesc);
-            run_group(ctx, p0, entry_bytes, d_trees + t0g, ntg, dmax, xy, ctx->h_trees + t0g, back, tm, g);
+            run_group(ctx, p0, entry_bytes, d_trees + t0g, ntg, dmax, xy, kind == 2 ? d_ids.as<int32_t>() : nullptr,
+                      ctx->h_trees + t0g, back, tm, g);
         } catch (const BudgetExceeded& b) {
             if (k1 - k0 <= 1)
                 throw Error{HH_ECAPACITY, "input " + std::to_string(k0) + " needs more than " +
@@ -891,7 +914,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             for (int32_t q = 0; q < n_pass; ++q) {
                 const int32_t t = tl + q;
                 const int p = tree_pass[q];
-                r->stats[p] = tree_stats(info, rec, t, ntg, pl.dmax, E, pl.T);
+                // a tree's own points (a gray image's passes see different sets)
+                r->stats[p] = tree_stats(info, rec, t, ntg, pl.dmax, ctx->h_trees[(size_t)(t0g + t)].n_points, pl.T);
                 for (const auto& lv : r->stats[p]) code_tests += lv.code_tests;
                 r->info.n_cells[p] = r->stats[p][(size_t)pl.dmax].detected;
                 if (pl.dmax > 0 && r->info.n_cells[p] > 0) {

@@ -1301,6 +1301,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_counts(ExtractArgs a)
                                                                             : s_total;
         a.trees[t].xy_base = lo;
         a.trees[t].n_points = hi - lo;
+        a.trees[t].image_points = (int32_t)(hi - lo);
     }
 }
 
@@ -1318,6 +1319,166 @@ __global__ __launch_bounds__(kBlock) void k_extract_write(ExtractArgs a)
         int32_t r = row, c = col;
         for (int k = 0; k < kPixPerThread; ++k) {
             if ((bits >> k) & 1u) a.xy[pos++] = pack_xy(c, r);
+            if (++c == im.width) {
+                c = 0;
+                ++r;
+            }
+        }
+    }
+}
+
+// Gray images (Sec. 3: the edge points are sorted into ALPHA and BETA while
+// Sobel's gradient operator is applied).  A pixel with a full 3x3
+// neighbourhood is an edge point iff Gx^2 + Gy^2 > t^2; the image line through
+// it runs across the gradient, with slope -Gx/Gy, so it belongs to ALPHA
+// (|slope| <= 1) iff |Gx| <= |Gy|.  Bits k of `a` / `b` mark the ALPHA / BETA
+// edge points among a lane's kPixPerThread consecutive pixels.
+__device__ inline void sobel_bits(const ImageDesc& im, int64_t p0, uint32_t& a, uint32_t& b, int32_t& row,
+                                  int32_t& col)
+{
+    a = b = 0;
+    row = col = 0;
+    if (p0 >= im.n_pix) return;
+    row = (int32_t)(p0 / im.width);
+    col = (int32_t)(p0 - (int64_t)row * im.width);
+    const int64_t t2 = (int64_t)im.edge_threshold * im.edge_threshold;
+    int32_t r = row, c = col;
+    for (int k = 0; k < kPixPerThread && p0 + k < im.n_pix; ++k) {
+        if (r >= 1 && r + 1 < im.height && c >= 1 && c + 1 < im.width) {
+            const uint8_t* const up = im.image + (int64_t)(r - 1) * im.row_stride + c;
+            const uint8_t* const mid = up + im.row_stride;
+            const uint8_t* const dn = mid + im.row_stride;
+            const int32_t nw = up[-1], n = up[0], ne = up[1];
+            const int32_t w = mid[-1], e = mid[1];
+            const int32_t sw = dn[-1], s_ = dn[0], se = dn[1];
+            const int32_t gx = (ne + 2 * e + se) - (nw + 2 * w + sw);
+            const int32_t gy = (sw + 2 * s_ + se) - (nw + 2 * n + ne);
+            if ((int64_t)gx * gx + (int64_t)gy * gy > t2) {
+                if (abs(gx) > abs(gy)) b |= 1u << k;
+                else a |= 1u << k;
+            }
+        }
+        if (++c == im.width) {
+            c = 0;
+            ++r;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sobel_count(SobelArgs a)
+{
+    __shared__ int32_t s_w[kWaves];
+    for (int64_t tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+        const ImageDesc im = a.images[image_of_tile(a.images, a.n_images, tile)];
+        uint32_t ba, bb;
+        int32_t row, col;
+        sobel_bits(im, (tile - im.tile0) * kPixTile + (int64_t)threadIdx.x * kPixPerThread, ba, bb, row, col);
+        int32_t na, nb;
+        __syncthreads();
+        block_excl_scan32(__popc(ba), s_w, na);
+        __syncthreads();
+        block_excl_scan32(__popc(bb), s_w, nb);
+        if (threadIdx.x == 0) {
+            a.tile_count[tile] = na;
+            a.tile_count[a.n_tiles + tile] = nb;
+        }
+    }
+}
+
+// One workgroup: the exclusive prefixes of both counts over the tiles, then
+// each tree's range: pass 0 the image's ALPHA points, pass 1 its BETA points.
+__global__ __launch_bounds__(kScanThreads) void k_sobel_scan(SobelArgs a)
+{
+    __shared__ int64_t s_w[kScanThreads / kWave];
+    __shared__ int64_t s_total[2];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t n = a.n_tiles;
+    const int64_t chunk = cdiv(n, kScanThreads);
+    const int64_t b = std::min<int64_t>(n, tid * chunk), e = std::min<int64_t>(n, b + chunk);
+    for (int set = 0; set < 2; ++set) {
+        const int32_t* const cnt = a.tile_count + set * n;
+        int64_t* const pre = a.tile_pre + set * n;
+        int64_t sum = 0;
+        for (int64_t t = b; t < e; ++t) sum += cnt[t];
+        const int64_t incl = wave_incl_scan64(sum, lane);
+        __syncthreads();   // s_w of the previous set has been read
+        if (lane == kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        int64_t run = incl - sum;
+        for (int w = 0; w < wave; ++w) run += s_w[w];
+        for (int64_t t = b; t < e; ++t) {
+            pre[t] = run;
+            run += cnt[t];
+        }
+        if (tid == kScanThreads - 1) s_total[set] = run;
+    }
+    __syncthreads();   // tile_pre is complete (workgroup-scope ordering of global memory)
+    const int64_t* const pa = a.tile_pre;
+    const int64_t* const pb = a.tile_pre + n;
+    for (int t = tid; t < a.n_trees; t += kScanThreads) {
+        const int k = a.trees[t].image;
+        const int64_t t0 = a.images[k].tile0, t1 = k + 1 < a.n_images ? a.images[k + 1].tile0 : n;
+        const int64_t a0 = t0 < n ? pa[t0] : s_total[0], a1 = t1 < n ? pa[t1] : s_total[0];
+        const int64_t b0 = t0 < n ? pb[t0] : s_total[1], b1 = t1 < n ? pb[t1] : s_total[1];
+        const int64_t base = a0 + b0;   // points of the images before k
+        a.trees[t].image_points = (int32_t)((a1 - a0) + (b1 - b0));
+        if (a.trees[t].pass == 0) {
+            a.trees[t].xy_base = base;
+            a.trees[t].n_points = a1 - a0;
+        } else {
+            a.trees[t].xy_base = base + (a1 - a0);
+            a.trees[t].n_points = b1 - b0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sobel_write(SobelArgs a)
+{
+    __shared__ int32_t s_w[kWaves];
+    const int64_t n = a.n_tiles;
+    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+        const int k = image_of_tile(a.images, a.n_images, tile);
+        const ImageDesc im = a.images[k];
+        uint32_t ba, bb;
+        int32_t row, col;
+        sobel_bits(im, (tile - im.tile0) * kPixTile + (int64_t)threadIdx.x * kPixPerThread, ba, bb, row, col);
+        const int64_t t0 = im.tile0, t1 = k + 1 < a.n_images ? a.images[k + 1].tile0 : n;
+        const int64_t* const pa = a.tile_pre;
+        const int64_t* const pb = a.tile_pre + n;
+        // the image's ALPHA count: the prefix at its last tile plus that tile's count
+        const int64_t a_img = pa[t1 - 1] + a.tile_count[t1 - 1] - pa[t0];
+        const int64_t base = pa[t0] + pb[t0];
+        int32_t tot;
+        __syncthreads();
+        const int32_t ra = block_excl_scan32(__popc(ba), s_w, tot);
+        __syncthreads();
+        const int32_t rb = block_excl_scan32(__popc(bb), s_w, tot);
+        int64_t pos_a = base + (pa[tile] - pa[t0]) + ra;
+        int64_t pos_b = base + a_img + (pb[tile] - pb[t0]) + rb;
+        int32_t id_a = (int32_t)((pa[tile] - pa[t0]) + (pb[tile] - pb[t0]));   // rank among the image's edges
+        int32_t r = row, c = col;
+        int32_t seen = 0;
+        // the lane's edges before pixel j, of both sets, come before it in the image
+        int32_t id0 = 0;
+        {
+            __syncthreads();
+            id0 = block_excl_scan32(__popc(ba | bb), s_w, tot);
+        }
+        for (int j = 0; j < kPixPerThread; ++j) {
+            const uint32_t bit = 1u << j;
+            if ((ba | bb) & bit) {
+                const int32_t id = id_a + id0 + seen;
+                if (ba & bit) {
+                    a.xy[pos_a] = pack_xy(c, r);
+                    a.ids[pos_a] = id;
+                    ++pos_a;
+                } else {
+                    a.xy[pos_b] = pack_xy(c, r);
+                    a.ids[pos_b] = id;
+                    ++pos_b;
+                }
+                ++seen;
+            }
             if (++c == im.width) {
                 c = 0;
                 ++r;
@@ -1434,7 +1595,8 @@ __global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc
 }
 
 template <typename Entry>
-__global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc* trees, const uint32_t* xy)
+__global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc* trees, const uint32_t* xy,
+                                                        const int32_t* ids)
 {
     __shared__ int64_t s_start[kMaxTrees];
     const uint32_t err = *G(ar.error);
@@ -1469,7 +1631,10 @@ __global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc*
             base = T.xy_base;
             swap = T.pass != 0;
         }
-        list[e] = EntryOps<Entry>::root(xy + base, e - lo, swap);
+        Entry v = EntryOps<Entry>::root(xy + base, e - lo, swap);
+        if constexpr (sizeof(Entry) == 8)
+            if (ids) v = (v & 0xFFFFFFFFull) | ((uint64_t)(uint32_t)ids[base + (e - lo)] << 32);
+        list[e] = v;
     }
 }
 
@@ -1561,6 +1726,16 @@ hipError_t launch_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t 
     return hipGetLastError();
 }
 
+hipError_t launch_sobel(const SobelArgs& a, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(a.n_tiles, 2048);
+    k_sobel_count<<<grid, kBlock, 0, s>>>(a);
+    k_sobel_scan<<<1, kScanThreads, 0, s>>>(a);
+    k_sobel_write<<<grid, kBlock, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_extract(const ExtractArgs& a, hipStream_t s)
 {
     if (a.n_tiles <= 0) return hipSuccess;
@@ -1571,13 +1746,13 @@ hipError_t launch_extract(const ExtractArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy, int grid,
-                        hipStream_t s)
+hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy,
+                        const int32_t* ids, int grid, hipStream_t s)
 {
     if (n_trees > kMaxTrees) return hipErrorInvalidValue;
     k_roots<<<1, kRootThreads, 0, s>>>(ar, trees, n_trees);
-    if (ar.entry_bytes == 8) k_root_lists<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, xy);
-    else k_root_lists<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, xy);
+    if (ar.entry_bytes == 8) k_root_lists<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, xy, ids);
+    else k_root_lists<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, xy, nullptr);
     return hipGetLastError();
 }
 

@@ -31,6 +31,23 @@ struct ExtractArgs {
     int32_t n_trees;
 };
 
+// Edge front end of a batch of gray images (Sec. 3: Sobel's operator sorts
+// the edge points into ALPHA and BETA).  Image k's ALPHA points, row-major,
+// then its BETA points become xy[image base ...], with ids[] holding each
+// point's rank among all edge points of its image; the tree of pass 0 gets
+// the ALPHA range and the tree of pass 1 the BETA range.
+struct SobelArgs {
+    const ImageDesc* images;
+    int32_t n_images;
+    int64_t n_tiles;
+    uint32_t* xy;
+    int32_t* ids;
+    int32_t* tile_count;       // [2][n_tiles] ALPHA, BETA edge pixels per tile
+    int64_t* tile_pre;         // [2][n_tiles] their exclusive prefixes
+    TreeDesc* trees;
+    int32_t n_trees;
+};
+
 // Zero the fixed part of an arena (level records, error word, scratch) and
 // mark every tree record as absent.
 hipError_t launch_clear(const Arena& ar, int64_t n_rec, hipStream_t s);
@@ -42,11 +59,16 @@ hipError_t launch_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t 
 // prefix (which also fills the trees' point ranges), then the row-major
 // compaction.
 hipError_t launch_extract(const ExtractArgs& a, hipStream_t s);
+// Gray images: Sobel gradients, the two point sets and the trees' ranges, in
+// three launches like launch_extract.
+hipError_t launch_sobel(const SobelArgs& a, hipStream_t s);
 // Root setup: level-0 sizes and root regions of every tree whose root splits
 // (more than T points and depth > 0), from the trees' point ranges; then the
 // root lists (the trees' points in input order) and the level-0 tile map.
-hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy, int grid,
-                        hipStream_t s);
+// With ids != nullptr (8-byte entries) a root entry takes its point id from
+// ids[] instead of its position in the tree's range.
+hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy,
+                        const int32_t* ids, int grid, hipStream_t s);
 // One level: child-vote counts per tile, per-region totals and decisions,
 // the next level's tables, then the compaction of the voters of the kept
 // children (skipped by the host at the finest level without members).

@@ -185,11 +185,11 @@ hh_status serve_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket)
 {
     Server* sv = ctx->server.get();
     if (!sv) throw Error{HH_EINVAL, "the context is not serving (hough_hier_serve_start)"};
-    if (in->kind != 0 && in->kind != 1) throw Error{HH_EINVAL, "input kind must be 0 (points) or 1 (image)"};
+    if (in->kind < 0 || in->kind > 2) throw Error{HH_EINVAL, "input kind must be 0 (points), 1 or 2 (images)"};
     if (in->width < 1 || in->height < 1) throw Error{HH_EINVAL, "width and height must be >= 1"};
     auto r = std::make_shared<Request>();
     r->in = *in;
-    r->cost = in->kind == 1 ? (int64_t)in->width * in->height : std::max<int64_t>(in->n_points, 1);
+    r->cost = in->kind != 0 ? (int64_t)in->width * in->height : std::max<int64_t>(in->n_points, 1);
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(sv->mu);

@@ -43,7 +43,7 @@ struct TreeDesc {
     int32_t threshold;  // a region splits (or is detected) iff votes > threshold
     int32_t pass;       // 0: (u, v) = (x, y); 1: (u, v) = (y, x)
     int32_t image;      // index of the image in its batch
-    int32_t pad;
+    int32_t image_points;   // edge points of the whole image (both sets of a gray image)
 };
 
 // One point list of a batch: n points (x[k], y[k]) in [0, W) x [0, H), packed
@@ -64,6 +64,8 @@ struct ImageDesc {
     int32_t width, height;
     int64_t tile0;
     int64_t n_pix;
+    int32_t edge_threshold;   // gray images: Sobel magnitude threshold
+    int32_t pad;
 };
 
 // Region.meta bits

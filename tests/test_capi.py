@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import paper_1007_0547_amd as hh
     assert C.sizeof(hh._Config) == 48
-    assert C.sizeof(hh._Input) == 64
+    assert C.sizeof(hh._Input) == 72
     assert hh.CELL_DTYPE.itemsize == 32
     assert hh.STATS_DTYPE.itemsize == 48
 
