@@ -297,6 +297,48 @@ def bench_sweep(seed, reps=20):
                              "integer arithmetic, so C_t reflects only the extra votes"}
 
 
+def bench_gray(seed, reps=20):
+    """The Sobel front end: a 1024x1024 gray image (32 bright segments of
+    length U[200, 1000] on a noisy background, seed-fixed), edge threshold
+    200, T = 120, depth 10, both passes on their own point sets."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    lines = synth.segment_image(rng, 1024, 1024, 32, 200.0, 1000.0, 0.0)
+    g = (rng.integers(0, 40, (1024, 1024)) + lines.astype(np.int64) * 170).astype(np.uint8)
+    d = torch.from_numpy(g).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = HoughHier(threshold=120, max_depth=10, membership=True, device=0, stream=stream)
+    for _ in range(3):
+        ctx.detect(gray=d, edge_threshold=200, width=1024, height=1024).free()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.detect(gray=d, edge_threshold=200, width=1024, height=1024).free()
+    torch.cuda.synchronize(dev)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    r = ctx.detect(gray=d, edge_threshold=200, width=1024, height=1024)
+    info = r.info
+    n_alpha = int(r.stats(0)["votes"][0])
+    r.free()
+    ctx.close()
+    ctx_t = HoughHier(threshold=120, max_depth=10, membership=True, device=0, stream=stream, timing=True)
+    ctx_t.detect(gray=d, edge_threshold=200, width=1024, height=1024).free()
+    r = ctx_t.detect(gray=d, edge_threshold=200, width=1024, height=1024)
+    kt = r.timing()
+    r.free()
+    ctx_t.close()
+    return {"workload": f"gray 1024x1024, seed {seed}, 32 segments, edge threshold 200, T=120, depth 10",
+            "edge_points": info["n_points"], "alpha_points": n_alpha, "beta_points": info["n_points"] - n_alpha,
+            "cells": sum(info["n_cells"]), "ms_per_image": ms, "front_end_ms": kt["extract_ms"],
+            "code_tests_per_s": info["code_tests"] / (ms / 1e3)}
+
+
 def bench_serving(seed, seconds, pool_size=128):
     """Serving: Poisson arrivals of images (sides log-uniform 256..4096,
     Poisson(48) segments, 1% noise, T = floor(side / 10), default depth),
@@ -422,6 +464,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 image")
     ap.add_argument("--no-sweep", action="store_true", help="skip the code/circle size sweep")
+    ap.add_argument("--no-gray", action="store_true", help="skip the Sobel front-end image")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -549,6 +592,8 @@ def main():
         out["seg4096"] = bench_large(args.seed)
     if not args.no_sweep:
         out["size_sweep"] = bench_sweep(args.seed)
+    if not args.no_gray:
+        out["gray1024"] = bench_gray(args.seed)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(args.seed, args.serve_seconds)
     if not args.no_cpu_baseline:
