@@ -187,6 +187,77 @@ def bench_batched(seed, reps=3):
     }
 
 
+def solution_bytes(r):
+    """Algorithmic bytes of the removal walk over one result: every voter id
+    read once (4 B), each cell's voter range read (12 B) and its keep flag
+    written (1 B), one plotted flag per point and pass (1 B)."""
+    cells = sum(r.info["n_cells"])
+    passes = bin(r.info["passes"]).count("1")
+    return 4 * r.info["member_slots"] + 13 * cells + passes * r.info["n_points"]
+
+
+def bench_solution(seed, reps=5):
+    """solution() with point removal (hough_hier_solution) on the benchmark
+    image and on the 512-image batch: the walk's kernel time from HIP events
+    in the library, and its algorithmic bandwidth.  The walk is sequential
+    per pass (one workgroup per tree)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1007_0547_amd as hh
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    w = synth.workload("seg1024", seed)
+    img = torch.from_numpy(w.image).to(dev)
+    ctx = hh.HoughHier(threshold=w.threshold, max_depth=w.max_depth, device=0, stream=stream)
+    ms, call = [], []
+    for k in range(reps + 1):
+        r = ctx.detect(image=img, width=w.width, height=w.height)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        m = hh.solution(r)
+        t1 = time.perf_counter()
+        if k > 0:
+            ms.append(m)
+            call.append((t1 - t0) * 1e3)
+        sol = [r.solution(p) for p in (0, 1)]
+        nbytes = solution_bytes(r)
+        members = r.info["member_slots"]
+        r.free()
+    ctx.close()
+    walk = float(np.median(ms))
+    one = {"workload": f"seg1024: 1024x1024, seed {seed}, T={w.threshold}, depth {w.max_depth}, both passes",
+           "walk_ms": walk, "call_ms": float(np.median(call)), "member_entries": members,
+           "kept": [s["kept"] for s in sol], "plotted": [s["plotted_points"] for s in sol],
+           "alg_bytes": nbytes, "GB/s": nbytes / (walk / 1e3) / 1e9,
+           "frac": nbytes / (walk / 1e3) / 1e9 / HBM_PEAK_GBS, "workgroups": 2}
+
+    ws = synth.batch_images(seed=seed, n=512)
+    imgs = [torch.from_numpy(x.image).to(dev) for x in ws]
+    inputs = [dict(image=d, width=x.width, height=x.height, threshold=x.threshold) for d, x in zip(imgs, ws)]
+    ctx = hh.HoughHier(threshold=0, device=0, stream=stream)
+    for r in ctx.detect_batch(inputs):   # learns the arena sizes
+        r.free()
+    rs = ctx.detect_batch(inputs)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    walk_b = hh.solution(rs)
+    call_b = (time.perf_counter() - t0) * 1e3
+    nbytes_b = sum(solution_bytes(r) for r in rs)
+    members_b = sum(r.info["member_slots"] for r in rs)
+    kept_b = sum(r.solution(p)["kept"] for r in rs for p in (0, 1))
+    for r in rs:
+        r.free()
+    ctx.close()
+    batch = {"workload": "the 512-image batch (seed %d), all 1024 passes in one launch" % seed,
+             "walk_ms": walk_b, "call_ms_with_id_conversion": call_b, "member_entries": members_b,
+             "kept": kept_b, "alg_bytes": nbytes_b, "GB/s": nbytes_b / (walk_b / 1e3) / 1e9,
+             "frac": nbytes_b / (walk_b / 1e3) / 1e9 / HBM_PEAK_GBS, "workgroups": 1024}
+    return {"seg1024": one, "batch512": batch}
+
+
 def bench_large(seed, reps=3):
     """The 4096x4096 image (128 segments of length U[500, 4000], 1% noise,
     T = 300, depth 12, both passes, voters kept): time per image and the
@@ -465,6 +536,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 image")
     ap.add_argument("--no-sweep", action="store_true", help="skip the code/circle size sweep")
     ap.add_argument("--no-gray", action="store_true", help="skip the Sobel front-end image")
+    ap.add_argument("--no-solution", action="store_true", help="skip solution() with point removal")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -594,6 +666,8 @@ def main():
         out["size_sweep"] = bench_sweep(args.seed)
     if not args.no_gray:
         out["gray1024"] = bench_gray(args.seed)
+    if not args.no_solution:
+        out["solution"] = bench_solution(args.seed)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(args.seed, args.serve_seconds)
     if not args.no_cpu_baseline:

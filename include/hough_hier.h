@@ -306,6 +306,37 @@ HH_API hh_status hough_hier_result_info(const hh_result* res, hh_result_info* in
 /* Kernel timings of the call that produced res (see hh_timing). */
 HH_API hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timing);
 
+/* solution() with point removal (Sec. 3, the procedure called at a detected
+ * finest region).  The depth-first search plots the voters of a detected cell
+ * and zeroes their codes at every level, so no region visited after it counts
+ * them.  Per pass this keeps a detected cell (in key order, the search's
+ * visiting order) iff more than T of its voters were not plotted by an earlier
+ * kept cell, and then plots its voters; the plotted points are the output
+ * image.  Passes are independent (each has its own plotted set).
+ * hough_hier_solution computes this on the device for n results (one launch
+ * for all their passes; results of a serving context are walked on the lane
+ * that made them); a result already solved is skipped.  *kernel_ms (may be
+ * NULL) receives the summed duration of the walk kernels.
+ * Errors: HH_EINVAL (null arguments, membership was not kept), HH_ENOMEM,
+ * HH_EDEVICE, HH_EINTERNAL (malformed result). */
+HH_API hh_status hough_hier_solution(hh_result* const* results, int32_t n, double* kernel_ms);
+
+/* The outcome of hough_hier_solution for one pass of a result. */
+typedef struct {
+    const uint8_t* keep;      /* [n_cells] 1 = the cell is kept, in the order of hough_hier_result_cells */
+    int64_t n_cells;
+    const uint8_t* plotted;   /* [n_points] 1 = point id k was plotted by this pass              */
+    int64_t n_points;
+    int64_t kept;             /* number of kept cells                                              */
+    int64_t plotted_points;   /* number of plotted points                                          */
+} hh_solution;
+
+/* on_device = 1 returns device arrays, on_device = 0 host copies owned by the
+ * result; both stay valid until hough_hier_result_free().  A pass that was not
+ * enabled has no cells and no plotted points.
+ * Errors: HH_EINVAL (bad pass, hough_hier_solution not run on res), HH_EDEVICE. */
+HH_API hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_device, hh_solution* out);
+
 /* Release a result (its device memory returns to the context, where the
  * context's next call may reuse it: finish any work that reads the result's
  * device arrays first).  Does not wait for calls running on the context.

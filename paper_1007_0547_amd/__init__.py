@@ -86,6 +86,11 @@ class _ServeConfig(C.Structure):
                 ("queue_capacity", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _Solution(C.Structure):
+    _fields_ = [("keep", C.c_void_p), ("n_cells", C.c_int64), ("plotted", C.c_void_p), ("n_points", C.c_int64),
+                ("kept", C.c_int64), ("plotted_points", C.c_int64)]
+
+
 CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),
                        ("key", np.int64), ("member_off", np.int64)])
 STATS_DTYPE = np.dtype([("evaluated", np.int64), ("votes", np.int64), ("split", np.int64),
@@ -122,6 +127,10 @@ _lib.hough_hier_result_info.restype = C.c_int
 _lib.hough_hier_result_info.argtypes = [_p, C.POINTER(_Info)]
 _lib.hough_hier_result_timing.restype = C.c_int
 _lib.hough_hier_result_timing.argtypes = [_p, C.POINTER(_Timing)]
+_lib.hough_hier_solution.restype = C.c_int
+_lib.hough_hier_solution.argtypes = [C.POINTER(_p), C.c_int32, C.POINTER(C.c_double)]
+_lib.hough_hier_result_solution.restype = C.c_int
+_lib.hough_hier_result_solution.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]
 _lib.hough_hier_result_free.restype = None
 _lib.hough_hier_result_free.argtypes = [_p]
 
@@ -213,6 +222,27 @@ class Result:
         """Statistics as an int64 array of shape (depth + 1, 6)."""
         s = self.stats(pass_)
         return s.view(np.int64).reshape(len(s), 6) if len(s) else np.zeros((0, 6), np.int64)
+
+    def solution(self, pass_: int) -> dict:
+        """Outcome of :func:`solution` for one pass, host copies: ``keep``
+        (bool per cell of :meth:`cells`), ``plotted`` (bool per point id),
+        ``kept`` and ``plotted_points``."""
+        out = _Solution()
+        self._check(_lib.hough_hier_result_solution(self._h, pass_, 0, C.byref(out)))
+        keep = np.zeros(out.n_cells, dtype=bool)
+        plotted = np.zeros(out.n_points, dtype=bool)
+        if out.n_cells:
+            keep = np.frombuffer((C.c_uint8 * out.n_cells).from_address(out.keep), dtype=np.uint8).astype(bool)
+        if out.n_points and out.plotted:
+            plotted = np.frombuffer((C.c_uint8 * out.n_points).from_address(out.plotted),
+                                    dtype=np.uint8).astype(bool)
+        return {"keep": keep, "plotted": plotted, "kept": out.kept, "plotted_points": out.plotted_points}
+
+    def device_solution(self, pass_: int) -> dict:
+        """Device pointers of one pass's keep and plotted flags and the counts."""
+        out = _Solution()
+        self._check(_lib.hough_hier_result_solution(self._h, pass_, 1, C.byref(out)))
+        return {k: (getattr(out, k) or 0) for k, _ in _Solution._fields_}
 
     def free(self):
         if self._h:
@@ -344,6 +374,12 @@ class HoughHier:
             raise HHError(s, self.last_error())
         return [Result(self, out[k]) for k in range(n)]
 
+    def solution(self, results) -> float:
+        """solution() with point removal (``hough_hier_solution``) on the
+        device for the given results; returns the walk's kernel time in ms.
+        Read the outcome with :meth:`Result.solution`."""
+        return solution(results)
+
     # ---- serving (continuous batching)
 
     def serve_start(self, lanes: int = 0, max_batch: int = 0, max_batch_pixels: int = 0,
@@ -399,3 +435,22 @@ class HoughHier:
             self.close()
         except Exception:
             pass
+
+
+def solution(results) -> float:
+    """solution() with point removal (Sec. 3) for a list of results (or one):
+    per pass, a detected cell is kept iff more than T of its voters were not
+    plotted by an earlier kept cell in key order; kept cells plot their
+    voters.  Returns the summed kernel time of the walk in ms."""
+    if isinstance(results, Result):
+        results = [results]
+    n = len(results)
+    arr = (C.c_void_p * max(n, 1))()
+    for k, r in enumerate(results):
+        arr[k] = r._h
+    ms = C.c_double()
+    s = _lib.hough_hier_solution(arr, n, C.byref(ms))
+    if s != 0:
+        msg = results[0]._ctx.last_error() if n else ""
+        raise HHError(s, msg)
+    return ms.value

@@ -5,6 +5,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "hh_engine.hpp"
 
@@ -208,6 +209,62 @@ hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timing)
 {
     if (!res || !timing) return HH_EINVAL;
     *timing = res->timing;
+    return HH_OK;
+}
+
+hh_status hough_hier_solution(hh_result* const* results, int32_t n, double* kernel_ms)
+{
+    if (kernel_ms) *kernel_ms = 0.0;
+    if (n < 0 || (n > 0 && !results)) return HH_EINVAL;
+    for (int32_t k = 0; k < n; ++k)
+        if (!results[k]) return HH_EINVAL;
+    // results of one context run in one launch; a serving context's results
+    // belong to the lane that made them
+    std::vector<bool> done((size_t)n, false);
+    for (int32_t k = 0; k < n; ++k) {
+        if (done[(size_t)k]) continue;
+        hh_ctx* ctx = results[k]->ctx;
+        std::vector<hh_result*> group;
+        for (int32_t q = k; q < n; ++q) {
+            if (!done[(size_t)q] && results[q]->ctx == ctx) {
+                group.push_back(results[q]);
+                done[(size_t)q] = true;
+            }
+        }
+        double ms = 0.0;
+        hh_status s;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            s = guarded(ctx, [&] { return hh::engine_solution(ctx, group.data(), (int32_t)group.size(), &ms); });
+        }
+        if (s != HH_OK) return s;
+        if (kernel_ms) *kernel_ms += ms;
+    }
+    return HH_OK;
+}
+
+hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_device, hh_solution* out)
+{
+    if (!res || !out || (pass != 0 && pass != 1)) return HH_EINVAL;
+    *out = hh_solution{};
+    if (!res->sol_ready) return fail(res->ctx, HH_EINVAL, "hough_hier_solution has not run on this result");
+    bool enabled = false;
+    for (int t = 0; t < res->n_trees; ++t) enabled = enabled || res->tree_pass[t] == pass;
+    if (!enabled) return HH_OK;
+    out->n_cells = res->info.n_cells[pass];
+    out->n_points = res->info.n_points;
+    out->kept = res->sol_kept[pass];
+    out->plotted_points = res->sol_plotted[pass];
+    if (on_device) {
+        out->keep = res->sol.as<const uint8_t>() + res->sol_keep_off[pass];
+        out->plotted = res->sol.as<const uint8_t>() + res->sol_plot_off[pass];
+        return HH_OK;
+    }
+    std::lock_guard<std::mutex> g(res->ctx->mu);
+    hh_status s = guarded(res->ctx, [&] { return hh::engine_host_solution(res, pass); });
+    if (s != HH_OK) return s;
+    out->keep = res->host_keep[pass].data();
+    out->plotted = res->host_plotted[pass].data();
     return HH_OK;
 }
 

@@ -18,6 +18,7 @@
 
 #include "hh_kernels.hpp"
 #include "hh_serve.hpp"
+#include "hh_solution.hpp"
 
 namespace hh {
 
@@ -1085,6 +1086,151 @@ hh_status engine_host_members(hh_result* res)
         }
     }
     res->host_members_ready = true;
+    return HH_OK;
+}
+
+// solution() with removal (Sec. 3): one walk per tree of every result, in
+// one launch per bitmap kind.  A result's pass p owns keep flags for its
+// cells and plotted flags for its n_points ids.
+hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double* kernel_ms)
+{
+    if (kernel_ms) *kernel_ms = 0.0;
+    check(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    std::vector<SolTree> lds, dev;
+    std::vector<hh_result*> todo;
+    int64_t max_lds_points = 0, dev_words = 0;
+    std::vector<int64_t> dev_word_off;
+    for (int32_t k = 0; k < n; ++k) {
+        hh_result* r = res[k];
+        if (!r) throw Error{HH_EINVAL, "null result"};
+        if (r->ctx != ctx) throw Error{HH_EINTERNAL, "result of another context"};
+        if (!r->have_members) throw Error{HH_EINVAL, "membership was not kept"};
+        if (r->sol_ready || std::find(todo.begin(), todo.end(), r) != todo.end()) continue;
+        todo.push_back(r);
+    }
+    for (hh_result* r : todo) {
+        engine_device_ids(r);
+        const Cell* cells = engine_device_cells(r);
+        const int32_t* ids = r->dev_ids.as<const int32_t>();
+        if (reinterpret_cast<uintptr_t>(ids) & 15u) throw Error{HH_EINTERNAL, "member ids not 16-byte aligned"};
+        const int64_t E = r->info.n_points;
+        int64_t bytes = 0, before = 0;
+        for (int q = 0; q < r->n_trees; ++q) {
+            const int32_t p = r->tree_pass[q];
+            r->sol_keep_off[p] = before;
+            before += r->info.n_cells[p];
+        }
+        bytes = align256(std::max<int64_t>(before, 1));
+        for (int q = 0; q < r->n_trees; ++q) {
+            const int32_t p = r->tree_pass[q];
+            r->sol_plot_off[p] = bytes;
+            bytes += align256(std::max<int64_t>(E, 1));
+        }
+        r->sol_counts_off = bytes;
+        bytes += 256;
+        r->sol = DevBuf(&ctx->pool, (size_t)bytes);
+        if (!r->sol) throw Error{HH_ENOMEM, "solution flags"};
+        uint8_t* base = r->sol.as<uint8_t>();
+        int64_t cbefore = 0;
+        for (int q = 0; q < r->n_trees; ++q) {
+            const int32_t p = r->tree_pass[q];
+            SolTree t{};
+            t.cells = cells ? cells + cbefore : nullptr;
+            t.ids = ids;
+            t.n_cells = r->info.n_cells[p];
+            t.n_points = E;
+            t.n_slots = r->info.member_slots;
+            t.keep = base + r->sol_keep_off[p];
+            t.plotted = base + r->sol_plot_off[p];
+            t.counts = reinterpret_cast<int64_t*>(base + r->sol_counts_off) + 2 * p;
+            t.threshold = r->info.threshold;
+            cbefore += t.n_cells;
+            if (t.n_cells > 0 && (!t.cells || !t.ids)) throw Error{HH_EINTERNAL, "solution inputs missing"};
+            if (E <= solution_lds_points()) {
+                max_lds_points = std::max(max_lds_points, E);
+                lds.push_back(t);
+            } else {
+                dev_word_off.push_back(dev_words);
+                dev_words += (((E + 31) >> 5) + 63) & ~(int64_t)63;
+                dev.push_back(t);
+            }
+        }
+    }
+    const int32_t n_lds = (int32_t)lds.size(), n_dev = (int32_t)dev.size();
+    if (n_lds + n_dev == 0) return HH_OK;
+    DevBuf bitmap;
+    if (n_dev > 0) {
+        bitmap = DevBuf(&ctx->pool, (size_t)dev_words * 4);
+        if (!bitmap) throw Error{HH_ENOMEM, "solution bitmaps"};
+        check(hipMemsetAsync(bitmap.get(), 0, (size_t)dev_words * 4, st), "clear bitmaps");
+        for (int32_t k = 0; k < n_dev; ++k) dev[(size_t)k].bitmap = bitmap.as<uint32_t>() + dev_word_off[(size_t)k];
+    }
+    std::vector<SolTree> all(lds);
+    all.insert(all.end(), dev.begin(), dev.end());
+    const size_t table = (size_t)align256((int64_t)(all.size() * sizeof(SolTree)));
+    DevBuf d(&ctx->pool, table + 256);
+    if (!d) throw Error{HH_ENOMEM, "solution table"};
+    uint32_t* d_err = reinterpret_cast<uint32_t*>(d.as<char>() + table);
+    check(hipMemcpyAsync(d.get(), all.data(), all.size() * sizeof(SolTree), hipMemcpyHostToDevice, st), "copy table");
+    check(hipMemsetAsync(d_err, 0, 4, st), "clear error");
+    hipEvent_t ev[2];
+    check(hipEventCreate(&ev[0]), "event");
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        throw Error{HH_EDEVICE, "event"};
+    }
+    struct Events {
+        hipEvent_t* e;
+        ~Events()
+        {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } guard{ev};
+    check(hipEventRecord(ev[0], st), "event");
+    check(launch_solution(d.as<SolTree>(), n_lds, max_lds_points, n_dev, d_err, st), "solution");
+    check(hipEventRecord(ev[1], st), "event");
+    uint32_t err = 0;
+    check(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, st), "copy error");
+    sync(ctx);
+    if (err) throw Error{HH_EINTERNAL, "solution: malformed cells or member ids"};
+    float ms = 0.f;
+    check(hipEventElapsedTime(&ms, ev[0], ev[1]), "event time");
+    if (kernel_ms) *kernel_ms = ms;
+    for (hh_result* r : todo) {   // counts: 32 bytes per result
+        int64_t counts[4] = {0, 0, 0, 0};
+        check(hipMemcpyAsync(counts, r->sol.as<char>() + r->sol_counts_off, sizeof(counts), hipMemcpyDeviceToHost,
+                             st),
+              "copy counts");
+        sync(ctx);
+        for (int p = 0; p < 2; ++p) {
+            r->sol_kept[p] = counts[2 * p];
+            r->sol_plotted[p] = counts[2 * p + 1];
+        }
+        r->sol_ready = true;
+    }
+    return HH_OK;
+}
+
+hh_status engine_host_solution(hh_result* res, int32_t pass)
+{
+    if (res->host_sol_ready[pass]) return HH_OK;
+    hh_ctx* ctx = res->ctx;
+    check(hipSetDevice(ctx->device), "hipSetDevice");
+    const int64_t nc = res->info.n_cells[pass], E = res->info.n_points;
+    res->host_keep[pass].assign((size_t)nc, 0);
+    res->host_plotted[pass].assign((size_t)E, 0);
+    if (nc > 0)
+        check(hipMemcpyAsync(res->host_keep[pass].data(), res->sol.as<char>() + res->sol_keep_off[pass], (size_t)nc,
+                             hipMemcpyDeviceToHost, ctx->stream),
+              "copy keep");
+    if (E > 0)
+        check(hipMemcpyAsync(res->host_plotted[pass].data(), res->sol.as<char>() + res->sol_plot_off[pass], (size_t)E,
+                             hipMemcpyDeviceToHost, ctx->stream),
+              "copy plotted");
+    sync(ctx);
+    res->host_sol_ready[pass] = true;
     return HH_OK;
 }
 

@@ -114,6 +114,18 @@ struct hh_result {
     hh::DevBuf depth0_cells;             // depth 0: the cells, made on the host
     hh::DevBuf dev_cells;                // cells with member_off relative to this image (made on request)
     hh::DevBuf dev_ids;                  // point ids in the layout of member_off (made on request)
+    // solution() with removal (hough_hier_solution): per pass, keep flags of
+    // its cells and plotted flags of the point ids, then the counts
+    bool sol_ready = false;
+    hh::DevBuf sol;
+    int64_t sol_keep_off[2] = {0, 0};
+    int64_t sol_plot_off[2] = {0, 0};
+    int64_t sol_counts_off = 0;
+    int64_t sol_kept[2] = {0, 0};
+    int64_t sol_plotted[2] = {0, 0};
+    bool host_sol_ready[2] = {false, false};
+    std::vector<uint8_t> host_keep[2];
+    std::vector<uint8_t> host_plotted[2];
     hh_timing timing{};
     // lazily filled host copies
     bool host_cells_ready = false;
@@ -179,6 +191,11 @@ hh_status engine_host_members(hh_result* res);
 hh_status engine_device_ids(hh_result* res);
 // The result's device cells with member_off counted from its own first voter.
 const Cell* engine_device_cells(hh_result* res);
+// solution() with removal over the detected cells of results of this context
+// (one launch for all their trees); *kernel_ms gets the walk's duration.
+hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double* kernel_ms);
+// Host copies of one pass's keep and plotted flags.
+hh_status engine_host_solution(hh_result* res, int32_t pass);
 
 // Serving (hh_serve.cpp).
 hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg);

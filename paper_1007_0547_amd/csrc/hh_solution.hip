@@ -1,0 +1,367 @@
+// solution() with point removal (Sec. 3) on gfx950.
+//
+// In the paper's depth-first search a detected finest cell calls solution():
+// its voters are plotted (they form the output image) and their codes are
+// zeroed at every level, so no region visited afterwards counts them.  The
+// search visits cells in key order, and it reaches a cell whenever the cell
+// itself has more than T unplotted voters (each ancestor, visited earlier with
+// fewer points plotted, has at least those voters).  So the kept cells are
+// those of a walk over the detected cells of the search without removal, in
+// key order, that keeps a cell iff more than T of its voters are not yet
+// plotted and then plots them.
+//
+// The walk is sequential by definition; one workgroup walks one tree.  It
+// streams the tree's voter ids in windows of kSolCh entries held in registers
+// (kSolR consecutive entries per lane).  For the cells of a window it counts
+// the unplotted voters with a block-wide prefix over per-entry live bits,
+// takes the first cell above T, plots it, and tests the window's entries again
+// from registers until no cell of the window is above T.  A cell that runs
+// past the window carries its count into the next one.  The plotted set is a
+// bitmap over the tree's point ids: in LDS when it fits, else in device memory
+// behind atomics at workgroup scope (performed in L2, one copy for all waves of
+// the workgroup).
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "hh_solution.hpp"
+
+namespace hh {
+namespace {
+
+constexpr int kSolThreads = 1024;
+constexpr int kSolWaves = kSolThreads / kWave;
+constexpr int kSolR = 8;                        // voter entries per lane in a window
+constexpr int kSolCh = kSolThreads * kSolR;     // entries per window
+constexpr int kSolMaxCells = 256;               // cells per window, one per lane of the first lanes
+constexpr int64_t kSolLdsBytes = 40 << 10;      // LDS for the plotted bitmap
+constexpr int64_t kSolLdsPoints = kSolLdsBytes * 8;
+using LiveMask = uint8_t;                       // one bit per entry of a lane
+static_assert(kSolR <= 8 * (int)sizeof(LiveMask), "a lane's live bits must fit its mask");
+static_assert(kSolMaxCells <= kSolThreads, "one lane per window cell");
+
+template <typename T>
+__device__ inline T* G(T* p)
+{
+    return (T*)(__attribute__((address_space(1))) T*)p;
+}
+
+// Loads and stores through global-address-space pointers: global (not flat)
+// instructions count only in vmcnt, so a wait for an LDS read never waits for
+// the next window's loads still in flight.
+template <typename T>
+__device__ inline T ldg(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T>
+__device__ inline void stg(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// A workgroup barrier for data exchanged through LDS only: it does not wait
+// for the wavefront's outstanding global loads (the next window's prefetch).
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// With the bitmap in device memory the waves also exchange global data.
+template <bool kLds>
+__device__ inline void sol_barrier()
+{
+    if constexpr (kLds) lds_barrier();
+    else __syncthreads();
+}
+
+template <bool kLds>
+__device__ inline uint32_t bit_word(uint32_t* bits, int64_t w)
+{
+    if constexpr (kLds) return bits[w];
+    else return __hip_atomic_fetch_or(G(bits) + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Sets bits m of word w; returns the word before.
+template <bool kLds>
+__device__ inline uint32_t bit_set(uint32_t* bits, int64_t w, uint32_t m)
+{
+    if constexpr (kLds) return atomicOr(bits + w, m);
+    else return __hip_atomic_fetch_or(G(bits) + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Live entries of the window before window position x (x in [0, kSolCh]).
+__device__ inline int32_t live_before(const int32_t* pre, const LiveMask* msk, int32_t x)
+{
+    const int32_t lane = x / kSolR, r = x % kSolR;
+    if (lane >= kSolThreads) return pre[kSolThreads];
+    return pre[lane] + __popc((uint32_t)msk[lane] & ((1u << r) - 1u));
+}
+
+// The ids of window base ab held by this lane: ab + kSolR * tid + j (-1 past
+// the buffer).
+__device__ inline void load_ids(const int32_t* ids, int64_t n_slots, int64_t ab, int tid, int32_t (&v)[kSolR])
+{
+    const int64_t q0 = ab + (int64_t)kSolR * tid;
+    const int64_t left = n_slots - q0;
+    const int32_t* src = ids + q0;
+    if (left >= kSolR) {
+        typedef int v4i __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int g = 0; g < kSolR; g += 4) {
+            const v4i x = ldg(reinterpret_cast<const v4i*>(src + g));
+            v[g] = x.x;
+            v[g + 1] = x.y;
+            v[g + 2] = x.z;
+            v[g + 3] = x.w;
+        }
+    } else {
+        const int n = left > 0 ? (int)left : 0;
+#pragma unroll
+        for (int j = 0; j < kSolR; ++j) v[j] = j < n ? ldg(src + j) : -1;
+    }
+}
+
+// Voter range of cell c (off, votes) and the start of the cell after it
+// (next; -1: c is the last cell).  Kept as loaded, so that a prefetch is not
+// waited for before the values are used.
+struct SolCell {
+    int64_t off, next;
+    int32_t votes;
+};
+
+__device__ inline SolCell load_cell(const SolTree& t, int64_t c)
+{
+    SolCell r{0, -1, 0};
+    if (c < t.n_cells) {
+        r.off = ldg(&t.cells[c].member_off);
+        r.votes = ldg(&t.cells[c].votes);
+        if (c + 1 < t.n_cells) r.next = ldg(&t.cells[c + 1].member_off);
+    }
+    return r;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, uint32_t* error)
+{
+    extern __shared__ uint32_t s_bits[];
+    __shared__ int32_t s_pre[kSolThreads + 1];   // exclusive prefix of live entries per lane
+    __shared__ LiveMask s_msk[kSolThreads];      // live entries of each lane
+    __shared__ int32_t s_cs[kSolMaxCells];       // window cells: first and end window position
+    __shared__ int32_t s_ce[kSolMaxCells];
+    __shared__ uint8_t s_keep[kSolMaxCells];
+    __shared__ int32_t s_sum[kSolWaves];
+    __shared__ int32_t s_first[kSolWaves];
+    __shared__ int64_t s_wend, s_off0;
+    __shared__ int32_t s_nw, s_carry, s_last_done, s_bad_cells, s_bad, s_plotted;
+
+    const SolTree t = trees[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t* bits = kLds ? s_bits : t.bitmap;
+    if constexpr (kLds) {
+        const int64_t words = (t.n_points + 31) >> 5;
+        for (int64_t w = tid; w < words; w += kSolThreads) s_bits[w] = 0;
+    }
+    if (tid == 0) {
+        s_bad_cells = 0;
+        s_bad = 0;
+        s_carry = 0;   // unplotted voters of the first undecided cell before pos
+        s_plotted = 0;
+    }
+    sol_barrier<kLds>();
+
+    const int32_t T = t.threshold;
+    int64_t c_cur = 0;                                            // first undecided cell
+    int64_t pos = t.n_cells > 0 ? ldg(&t.cells[0].member_off) : 0;   // its first untested voter
+    int64_t kept = 0;
+    int32_t plotted = 0;                                          // bits this lane set
+    bool bad = false;
+    // this window's and the next window's cells and ids, loaded one window ahead
+    SolCell cell = tid < kSolMaxCells ? load_cell(t, c_cur + tid) : SolCell{0, -1, 0};
+    int32_t id[kSolR], nid[kSolR];
+    if (t.n_cells > 0) load_ids(t.ids, t.n_slots, pos & ~(int64_t)3, tid, nid);
+    while (c_cur < t.n_cells) {
+        const int64_t ab = pos & ~(int64_t)3;   // window base, aligned for 16-byte loads
+        const int64_t limit = ab + kSolCh;
+        // The window's cells: c_cur and the cells that start before limit.
+        const int64_t c = c_cur + tid;
+        const int64_t off = cell.off, end = cell.off + cell.votes;
+        const int64_t next = cell.next < 0 ? end : cell.next;
+        // The last cell of the window knows it is last: the cell after it
+        // starts at or past limit (or there is none, or no lane for it).
+        if (tid < kSolMaxCells && c < t.n_cells) {
+            const bool in = tid == 0 || off < limit;
+            const bool ok = end > off && off >= 0 && end <= t.n_slots && next == end &&
+                            (tid > 0 || (pos >= off && pos < end));
+            if (in && !ok) s_bad_cells = 1;
+            if (in && (tid == kSolMaxCells - 1 || c + 1 >= t.n_cells || next >= limit)) {
+                s_nw = tid + 1;
+                s_wend = end < limit ? end : limit;
+                s_last_done = end <= limit;
+            }
+        }
+        if (tid == 0) s_off0 = off;
+        sol_barrier<kLds>();
+        if (s_bad_cells) {
+            bad = true;
+            break;
+        }
+        const int32_t n_w = s_nw;
+        const int32_t carry = s_carry;
+        const int64_t w_end = s_wend;
+        const bool last_done = s_last_done;
+        const bool complete = tid < n_w && end <= w_end;
+        if (tid < n_w) {
+            s_cs[tid] = (int32_t)((off > pos ? off : pos) - ab);
+            s_ce[tid] = (int32_t)((end < w_end ? end : w_end) - ab);
+            s_keep[tid] = 0;
+        }
+        // This lane's entries ab + kSolR * tid + j; those in [pos, w_end) take part.
+        const int64_t q0 = ab + (int64_t)kSolR * tid;
+        const int64_t lo64 = pos - q0, hi64 = w_end - q0;
+        const int lo = lo64 < 0 ? 0 : lo64 > kSolR ? kSolR : (int)lo64;
+        const int hi = hi64 < 0 ? 0 : hi64 > kSolR ? kSolR : (int)hi64;
+        uint32_t vmask = hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+#pragma unroll
+        for (int j = 0; j < kSolR; ++j) {
+            id[j] = nid[j];
+            if (((vmask >> j) & 1u) && (id[j] < 0 || (int64_t)id[j] >= t.n_points)) {
+                s_bad = 1;
+                vmask &= ~(1u << j);
+            }
+        }
+        // Prefetch the next window (its first cell and base are known now).
+        const int64_t c_next = last_done ? c_cur + n_w : c_cur + n_w - 1;
+        if (c_next < t.n_cells) {
+            if (tid < kSolMaxCells) cell = load_cell(t, c_next + tid);
+            load_ids(t.ids, t.n_slots, w_end & ~(int64_t)3, tid, nid);
+        }
+        // Take the first cell above T, plot it, test again; until none is left.
+        int32_t k_from = 0, cnt = 0;
+        for (;;) {
+            // live = taking part and not plotted (from LDS, entries not taking
+            // part read id 0; device words are read only for entries taking part)
+            uint32_t m = 0;
+#pragma unroll
+            for (int j = 0; j < kSolR; ++j) {
+                if constexpr (kLds) {
+                    const int32_t k = ((vmask >> j) & 1u) ? id[j] : 0;
+                    m |= (((bit_word<kLds>(bits, k >> 5) >> (k & 31)) & 1u) ^ 1u) << j;
+                } else if ((vmask >> j) & 1u) {
+                    m |= (((bit_word<kLds>(bits, id[j] >> 5) >> (id[j] & 31)) & 1u) ^ 1u) << j;
+                }
+            }
+            m &= vmask;
+            // the wavefront's exclusive prefix and total from one ballot per entry slot
+            int32_t excl = 0, wtot = 0;
+#pragma unroll
+            for (int j = 0; j < kSolR; ++j) {
+                const uint64_t b = __ballot((m >> j) & 1u);
+                excl += (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                wtot += __popcll(b);
+            }
+            if (lane == 0) s_sum[wave] = wtot;
+            s_msk[tid] = (LiveMask)m;
+            sol_barrier<kLds>();
+            if (s_bad) {
+                bad = true;
+                break;
+            }
+            int32_t base = 0;
+#pragma unroll
+            for (int w = 0; w < kSolWaves; ++w) base += w < wave ? s_sum[w] : 0;
+            s_pre[tid] = base + excl;
+            if (tid == kSolThreads - 1) s_pre[kSolThreads] = base + wtot;
+            sol_barrier<kLds>();
+            bool cand = false;
+            if (tid < n_w) {
+                cnt = live_before(s_pre, s_msk, s_ce[tid]) - live_before(s_pre, s_msk, s_cs[tid]) +
+                      (tid == 0 ? carry : 0);
+                cand = complete && tid >= k_from && cnt > T;
+            }
+            const uint64_t bc = __ballot(cand);
+            if (lane == 0) s_first[wave] = bc ? wave * kWave + __ffsll((unsigned long long)bc) - 1 : INT_MAX;
+            sol_barrier<kLds>();
+            int32_t f = INT_MAX;
+            for (int w = 0; w < kSolWaves; ++w) f = s_first[w] < f ? s_first[w] : f;
+            if (f == INT_MAX) break;
+            // Plot cell f: its live voters in this window, and for a cell that
+            // began in an earlier window, its voters before pos.
+            const int32_t fs = s_cs[f], fe = s_ce[f];
+#pragma unroll
+            for (int j = 0; j < kSolR; ++j) {
+                const int32_t x = kSolR * tid + j;
+                if (x >= fs && x < fe && ((m >> j) & 1u)) {
+                    const uint32_t b = 1u << (id[j] & 31);
+                    plotted += (bit_set<kLds>(bits, id[j] >> 5, b) & b) ? 0 : 1;
+                }
+            }
+            if (f == 0 && s_off0 < pos) {
+                for (int64_t q = s_off0 + tid; q < pos; q += kSolThreads) {
+                    const int32_t p = ldg(t.ids + q);
+                    if (p < 0 || (int64_t)p >= t.n_points) {
+                        s_bad = 1;
+                        continue;
+                    }
+                    const uint32_t b = 1u << (p & 31);
+                    plotted += (bit_set<kLds>(bits, p >> 5, b) & b) ? 0 : 1;
+                }
+            }
+            if (tid == f) s_keep[f] = 1;
+            ++kept;
+            k_from = f + 1;
+            // entries of cells up to f are decided: they take no further part
+            const int32_t x0 = kSolR * tid;
+            vmask &= fe <= x0 ? ~0u : fe >= x0 + kSolR ? 0u : ~((1u << (fe - x0)) - 1u);
+            sol_barrier<kLds>();
+        }
+        if (bad) break;
+        // The next window reads the carry after its first barrier; its tables
+        // are written only after that barrier too, when every lane is done
+        // with this window's.
+        if (tid == n_w - 1) s_carry = last_done ? 0 : cnt;
+        if (complete) stg(t.keep + c, s_keep[tid]);
+        c_cur = c_next;
+        pos = w_end;
+    }
+
+    // Output: plotted flags per point id, the kept cells and plotted points.
+    for (int d = kWave / 2; d > 0; d >>= 1) plotted += __shfl_xor(plotted, d, kWave);
+    if (lane == 0) atomicAdd(&s_plotted, plotted);
+    sol_barrier<kLds>();
+    const int64_t words = (t.n_points + 31) >> 5;
+    for (int64_t w = tid; w < words; w += kSolThreads) {
+        const uint32_t x = bit_word<kLds>(bits, w);
+        const int64_t k0 = w * 32;
+        const int nb = t.n_points - k0 < 32 ? (int)(t.n_points - k0) : 32;
+        for (int b = 0; b < nb; ++b) stg(t.plotted + k0 + b, (uint8_t)((x >> b) & 1u));
+    }
+    if (tid == 0) {
+        stg(t.counts, kept);
+        stg(t.counts + 1, (int64_t)s_plotted);
+        if (bad) __hip_atomic_fetch_or(G(error), kErrInternal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+}  // namespace
+
+int64_t solution_lds_points() { return kSolLdsPoints; }
+
+hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_points, int32_t n_dev,
+                           uint32_t* error, hipStream_t s)
+{
+    if (max_lds_points > kSolLdsPoints) return hipErrorInvalidValue;
+    if (n_lds > 0) {
+        const size_t lds = (size_t)((max_lds_points + 31) >> 5) * 4;
+        k_solution<true><<<n_lds, kSolThreads, lds, s>>>(trees, error);
+    }
+    if (n_dev > 0) k_solution<false><<<n_dev, kSolThreads, 0, s>>>(trees + n_lds, error);
+    return hipGetLastError();
+}
+
+}  // namespace hh

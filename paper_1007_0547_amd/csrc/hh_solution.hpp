@@ -1,0 +1,34 @@
+// Host-side launcher of the solution() walk (point removal, Sec. 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hh_types.hpp"
+
+namespace hh {
+
+// One tree (one pass of one image) for the walk.
+struct SolTree {
+    const Cell* cells;      // the pass's detected cells in key order, voters back to back
+    const int32_t* ids;     // voter point ids; cell c's are ids[cells[c].member_off ...]
+    int64_t n_cells;
+    int64_t n_points;       // ids lie in [0, n_points)
+    int64_t n_slots;        // length of ids
+    uint8_t* keep;          // [n_cells] 1 = the cell survives removal
+    uint8_t* plotted;       // [n_points] 1 = the point was plotted
+    uint32_t* bitmap;       // n_points bits of zeroed device memory, or null: the walk keeps them in LDS
+    int64_t* counts;        // [2] kept cells, plotted points
+    int32_t threshold;
+    int32_t pad;
+};
+
+// Point ids a walk keeps in LDS; trees with more points need a device bitmap.
+int64_t solution_lds_points();
+// The walk of n_lds trees with LDS bitmaps (trees[0 .. n_lds)) and n_dev
+// trees with device bitmaps (trees[n_lds ...]); max_lds_points is the
+// largest n_points among the first.  A malformed tree (cells not back to back,
+// an id out of range) raises kErrInternal in *error.
+hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_points, int32_t n_dev,
+                           uint32_t* error, hipStream_t s);
+
+}  // namespace hh

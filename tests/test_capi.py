@@ -21,7 +21,8 @@ def test_header_declares_the_entry_points():
     for n in ("hough_hier_create", "hough_hier_destroy", "hough_hier_detect", "hough_hier_detect_batch",
               "hough_hier_result_cells", "hough_hier_result_members", "hough_hier_result_stats",
               "hough_hier_result_info", "hough_hier_result_free", "hough_hier_last_error",
-              "hough_hier_serve_start", "hough_hier_submit", "hough_hier_poll"):
+              "hough_hier_serve_start", "hough_hier_submit", "hough_hier_poll", "hough_hier_solution",
+              "hough_hier_result_solution"):
         assert n in names
 
 
@@ -42,6 +43,7 @@ def test_struct_layouts_match_header():
     import paper_1007_0547_amd as hh
     assert C.sizeof(hh._Config) == 48
     assert C.sizeof(hh._Input) == 72
+    assert C.sizeof(hh._Solution) == 48
     assert hh.CELL_DTYPE.itemsize == 32
     assert hh.STATS_DTYPE.itemsize == 48
 
@@ -83,3 +85,19 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(hh.HHError) as e:
         hh.HoughHier(threshold=1)
     assert e.value.status == -4
+
+
+def test_solution_null_arguments():
+    """hough_hier_solution and its accessor reject null arguments and bad
+    passes without a device; an empty list is a no-op."""
+    import paper_1007_0547_amd as hh
+    lib = hh.library()
+    ms = C.c_double(-1.0)
+    assert lib.hough_hier_solution(None, 1, C.byref(ms)) == -1
+    assert lib.hough_hier_solution(None, -1, None) == -1
+    assert lib.hough_hier_solution(None, 0, C.byref(ms)) == 0 and ms.value == 0.0
+    arr = (C.c_void_p * 2)(None, None)
+    assert lib.hough_hier_solution(arr, 2, None) == -1
+    out = hh._Solution()
+    assert lib.hough_hier_result_solution(None, 0, 0, C.byref(out)) == -1
+    assert lib.hough_hier_result_solution(None, 0, 0, None) == -1
