@@ -37,8 +37,7 @@ constexpr int kSolCh = kSolThreads * kSolR;     // entries per window
 constexpr int kSolMaxCells = 256;               // cells per window, one per lane of the first lanes
 constexpr int64_t kSolLdsBytes = 40 << 10;      // LDS for the plotted bitmap
 constexpr int64_t kSolLdsPoints = kSolLdsBytes * 8;
-using LiveMask = uint8_t;                       // one bit per entry of a lane
-static_assert(kSolR <= 8 * (int)sizeof(LiveMask), "a lane's live bits must fit its mask");
+static_assert(kSolR == 8, "a lane's live bits are one byte of the window's live bitmap");
 static_assert(kSolMaxCells <= kSolThreads, "one lane per window cell");
 
 template <typename T>
@@ -94,14 +93,6 @@ __device__ inline uint32_t bit_set(uint32_t* bits, int64_t w, uint32_t m)
     else return __hip_atomic_fetch_or(G(bits) + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Live entries of the window before window position x (x in [0, kSolCh]).
-__device__ inline int32_t live_before(const int32_t* pre, const LiveMask* msk, int32_t x)
-{
-    const int32_t lane = x / kSolR, r = x % kSolR;
-    if (lane >= kSolThreads) return pre[kSolThreads];
-    return pre[lane] + __popc((uint32_t)msk[lane] & ((1u << r) - 1u));
-}
-
 // The ids of window base ab held by this lane: ab + kSolR * tid + j (-1 past
 // the buffer).
 __device__ inline void load_ids(const int32_t* ids, int64_t n_slots, int64_t ab, int tid, int32_t (&v)[kSolR])
@@ -145,19 +136,56 @@ __device__ inline SolCell load_cell(const SolTree& t, int64_t c)
     return r;
 }
 
+// Live bits of this lane's entries (bit j: entry j is an id of the tree and
+// not plotted); *valid gets the bits of entries that are ids of the tree.
+// Entries before window position skip_below are not read.
+template <bool kLds>
+__device__ inline uint32_t live_bits(uint32_t* bits, const int32_t (&id)[kSolR], uint32_t n_points, int x0,
+                                     int skip_below, uint32_t* valid)
+{
+    uint32_t m = 0, v = 0;
+#pragma unroll
+    for (int j = 0; j < kSolR; ++j) {
+        const bool ok = (uint32_t)id[j] < n_points;   // negative ids wrap above n_points
+        v |= (ok ? 1u : 0u) << j;
+        const bool take = ok && x0 + j >= skip_below;
+        if constexpr (kLds) {
+            const uint32_t k = take ? (uint32_t)id[j] : 0u;   // LDS: read unconditionally, mask after
+            m |= (take ? ((bits[k >> 5] >> (k & 31)) & 1u) ^ 1u : 0u) << j;
+        } else if (take) {
+            m |= (((bit_word<kLds>(bits, id[j] >> 5) >> (id[j] & 31)) & 1u) ^ 1u) << j;
+        }
+    }
+    *valid = v;
+    return m;
+}
+
+// Live entries of the window in positions [cs, ce), from the window's live
+// bitmap (entry e is bit e % 32 of word e / 32).
+__device__ inline int32_t live_in(const uint32_t* live, int32_t cs, int32_t ce)
+{
+    if (cs >= ce) return 0;
+    const int32_t w0 = cs >> 5, w1 = (ce - 1) >> 5;
+    int32_t n = 0;
+    for (int32_t w = w0; w <= w1; ++w) {
+        uint32_t v = live[w];
+        if (w == w0) v &= ~0u << (cs & 31);
+        if (w == w1 && (ce & 31)) v &= (1u << (ce & 31)) - 1u;
+        n += __popc(v);
+    }
+    return n;
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, uint32_t* error)
 {
     extern __shared__ uint32_t s_bits[];
-    __shared__ int32_t s_pre[kSolThreads + 1];   // exclusive prefix of live entries per lane
-    __shared__ LiveMask s_msk[kSolThreads];      // live entries of each lane
+    __shared__ uint32_t s_live[kSolCh / 32];     // the window's live bitmap: one byte per lane
     __shared__ int32_t s_cs[kSolMaxCells];       // window cells: first and end window position
     __shared__ int32_t s_ce[kSolMaxCells];
-    __shared__ uint8_t s_keep[kSolMaxCells];
-    __shared__ int32_t s_sum[kSolWaves];
     __shared__ int32_t s_first[kSolWaves];
     __shared__ int64_t s_wend, s_off0;
-    __shared__ int32_t s_nw, s_carry, s_last_done, s_bad_cells, s_bad, s_plotted;
+    __shared__ int32_t s_nw, s_carry, s_last_done, s_bad_cells, s_bad_ids, s_bad_mark, s_plotted;
 
     const SolTree t = trees[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -168,13 +196,17 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
     }
     if (tid == 0) {
         s_bad_cells = 0;
-        s_bad = 0;
-        s_carry = 0;   // unplotted voters of the first undecided cell before pos
+        s_bad_ids = 0;
+        s_bad_mark = 0;
         s_plotted = 0;
+        s_carry = 0;   // unplotted voters of the first undecided cell before pos
     }
     sol_barrier<kLds>();
 
     const int32_t T = t.threshold;
+    const uint32_t n_points = (uint32_t)t.n_points;              // ids are 32-bit
+    uint8_t* live_byte = reinterpret_cast<uint8_t*>(s_live) + tid;
+    const int x0 = kSolR * tid;                                   // this lane's first window position
     int64_t c_cur = 0;                                            // first undecided cell
     int64_t pos = t.n_cells > 0 ? ldg(&t.cells[0].member_off) : 0;   // its first untested voter
     int64_t kept = 0;
@@ -187,12 +219,12 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
     while (c_cur < t.n_cells) {
         const int64_t ab = pos & ~(int64_t)3;   // window base, aligned for 16-byte loads
         const int64_t limit = ab + kSolCh;
-        // The window's cells: c_cur and the cells that start before limit.
+        // The window's cells: c_cur and the cells that start before limit.  The
+        // last one knows it is last: the cell after it starts at or past limit
+        // (or there is none, or no lane for it).
         const int64_t c = c_cur + tid;
         const int64_t off = cell.off, end = cell.off + cell.votes;
         const int64_t next = cell.next < 0 ? end : cell.next;
-        // The last cell of the window knows it is last: the cell after it
-        // starts at or past limit (or there is none, or no lane for it).
         if (tid < kSolMaxCells && c < t.n_cells) {
             const bool in = tid == 0 || off < limit;
             const bool ok = end > off && off >= 0 && end <= t.n_slots && next == end &&
@@ -205,6 +237,13 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
             }
         }
         if (tid == 0) s_off0 = off;
+        // The window's entries and their live bits (every loaded entry; only
+        // those of the window's cells are counted).
+#pragma unroll
+        for (int j = 0; j < kSolR; ++j) id[j] = nid[j];
+        uint32_t valid = 0;
+        uint32_t m = live_bits<kLds>(bits, id, n_points, x0, 0, &valid);
+        *live_byte = (uint8_t)m;
         sol_barrier<kLds>();
         if (s_bad_cells) {
             bad = true;
@@ -215,24 +254,19 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         const int64_t w_end = s_wend;
         const bool last_done = s_last_done;
         const bool complete = tid < n_w && end <= w_end;
+        int32_t cs = 0, ce = 0;
         if (tid < n_w) {
-            s_cs[tid] = (int32_t)((off > pos ? off : pos) - ab);
-            s_ce[tid] = (int32_t)((end < w_end ? end : w_end) - ab);
-            s_keep[tid] = 0;
+            cs = (int32_t)((off > pos ? off : pos) - ab);
+            ce = (int32_t)((end < w_end ? end : w_end) - ab);
+            s_cs[tid] = cs;
+            s_ce[tid] = ce;
         }
-        // This lane's entries ab + kSolR * tid + j; those in [pos, w_end) take part.
-        const int64_t q0 = ab + (int64_t)kSolR * tid;
-        const int64_t lo64 = pos - q0, hi64 = w_end - q0;
-        const int lo = lo64 < 0 ? 0 : lo64 > kSolR ? kSolR : (int)lo64;
-        const int hi = hi64 < 0 ? 0 : hi64 > kSolR ? kSolR : (int)hi64;
-        uint32_t vmask = hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
-#pragma unroll
-        for (int j = 0; j < kSolR; ++j) {
-            id[j] = nid[j];
-            if (((vmask >> j) & 1u) && (id[j] < 0 || (int64_t)id[j] >= t.n_points)) {
-                s_bad = 1;
-                vmask &= ~(1u << j);
-            }
+        {   // every id of the window's cells must name a point of the tree
+            const int64_t lo64 = pos - (ab + x0), hi64 = w_end - (ab + x0);
+            const int lo = lo64 < 0 ? 0 : lo64 > kSolR ? kSolR : (int)lo64;
+            const int hi = hi64 < 0 ? 0 : hi64 > kSolR ? kSolR : (int)hi64;
+            const uint32_t in_cells = hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+            if (in_cells & ~valid) s_bad_ids = 1;
         }
         // Prefetch the next window (its first cell and base are known now).
         const int64_t c_next = last_done ? c_cur + n_w : c_cur + n_w - 1;
@@ -242,52 +276,22 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         }
         // Take the first cell above T, plot it, test again; until none is left.
         int32_t k_from = 0, cnt = 0;
+        bool my_keep = false;
         for (;;) {
-            // live = taking part and not plotted (from LDS, entries not taking
-            // part read id 0; device words are read only for entries taking part)
-            uint32_t m = 0;
-#pragma unroll
-            for (int j = 0; j < kSolR; ++j) {
-                if constexpr (kLds) {
-                    const int32_t k = ((vmask >> j) & 1u) ? id[j] : 0;
-                    m |= (((bit_word<kLds>(bits, k >> 5) >> (k & 31)) & 1u) ^ 1u) << j;
-                } else if ((vmask >> j) & 1u) {
-                    m |= (((bit_word<kLds>(bits, id[j] >> 5) >> (id[j] & 31)) & 1u) ^ 1u) << j;
-                }
-            }
-            m &= vmask;
-            // the wavefront's exclusive prefix and total from one ballot per entry slot
-            int32_t excl = 0, wtot = 0;
-#pragma unroll
-            for (int j = 0; j < kSolR; ++j) {
-                const uint64_t b = __ballot((m >> j) & 1u);
-                excl += (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-                wtot += __popcll(b);
-            }
-            if (lane == 0) s_sum[wave] = wtot;
-            s_msk[tid] = (LiveMask)m;
-            sol_barrier<kLds>();
-            if (s_bad) {
-                bad = true;
-                break;
-            }
-            int32_t base = 0;
-#pragma unroll
-            for (int w = 0; w < kSolWaves; ++w) base += w < wave ? s_sum[w] : 0;
-            s_pre[tid] = base + excl;
-            if (tid == kSolThreads - 1) s_pre[kSolThreads] = base + wtot;
-            sol_barrier<kLds>();
             bool cand = false;
             if (tid < n_w) {
-                cnt = live_before(s_pre, s_msk, s_ce[tid]) - live_before(s_pre, s_msk, s_cs[tid]) +
-                      (tid == 0 ? carry : 0);
+                cnt = live_in(s_live, cs, ce) + (tid == 0 ? carry : 0);
                 cand = complete && tid >= k_from && cnt > T;
             }
             const uint64_t bc = __ballot(cand);
             if (lane == 0) s_first[wave] = bc ? wave * kWave + __ffsll((unsigned long long)bc) - 1 : INT_MAX;
             sol_barrier<kLds>();
+            if (s_bad_ids) {
+                bad = true;
+                break;
+            }
             int32_t f = INT_MAX;
+#pragma unroll
             for (int w = 0; w < kSolWaves; ++w) f = s_first[w] < f ? s_first[w] : f;
             if (f == INT_MAX) break;
             // Plot cell f: its live voters in this window, and for a cell that
@@ -295,8 +299,7 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
             const int32_t fs = s_cs[f], fe = s_ce[f];
 #pragma unroll
             for (int j = 0; j < kSolR; ++j) {
-                const int32_t x = kSolR * tid + j;
-                if (x >= fs && x < fe && ((m >> j) & 1u)) {
+                if (x0 + j >= fs && x0 + j < fe && ((m >> j) & 1u)) {
                     const uint32_t b = 1u << (id[j] & 31);
                     plotted += (bit_set<kLds>(bits, id[j] >> 5, b) & b) ? 0 : 1;
                 }
@@ -305,27 +308,32 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
                 for (int64_t q = s_off0 + tid; q < pos; q += kSolThreads) {
                     const int32_t p = ldg(t.ids + q);
                     if (p < 0 || (int64_t)p >= t.n_points) {
-                        s_bad = 1;
+                        s_bad_mark = 1;
                         continue;
                     }
                     const uint32_t b = 1u << (p & 31);
                     plotted += (bit_set<kLds>(bits, p >> 5, b) & b) ? 0 : 1;
                 }
             }
-            if (tid == f) s_keep[f] = 1;
+            my_keep = my_keep || tid == f;
             ++kept;
             k_from = f + 1;
-            // entries of cells up to f are decided: they take no further part
-            const int32_t x0 = kSolR * tid;
-            vmask &= fe <= x0 ? ~0u : fe >= x0 + kSolR ? 0u : ~((1u << (fe - x0)) - 1u);
+            sol_barrier<kLds>();
+            if (s_bad_mark) {
+                bad = true;
+                break;
+            }
+            // entries up to cell f's end are decided; test the rest again
+            m = live_bits<kLds>(bits, id, n_points, x0, fe, &valid);
+            *live_byte = (uint8_t)m;
             sol_barrier<kLds>();
         }
         if (bad) break;
-        // The next window reads the carry after its first barrier; its tables
-        // are written only after that barrier too, when every lane is done
-        // with this window's.
+        // The next window reads the carry after its first barrier, and writes
+        // its tables only after that barrier, when every lane is done with
+        // this window's.
         if (tid == n_w - 1) s_carry = last_done ? 0 : cnt;
-        if (complete) stg(t.keep + c, s_keep[tid]);
+        if (complete) stg(t.keep + c, (uint8_t)(my_keep ? 1 : 0));
         c_cur = c_next;
         pos = w_end;
     }
