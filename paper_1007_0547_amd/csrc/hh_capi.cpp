@@ -256,8 +256,8 @@ hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_de
     out->kept = res->sol_kept[pass];
     out->plotted_points = res->sol_plotted[pass];
     if (on_device) {
-        out->keep = res->sol.as<const uint8_t>() + res->sol_keep_off[pass];
-        out->plotted = res->sol.as<const uint8_t>() + res->sol_plot_off[pass];
+        out->keep = res->sol + res->sol_keep_off[pass];
+        out->plotted = res->sol + res->sol_plot_off[pass];
         return HH_OK;
     }
     std::lock_guard<std::mutex> g(res->ctx->mu);

@@ -1021,6 +1021,14 @@ hh_status engine_device_ids(hh_result* res)
     res->dev_ids = DevBuf(&ctx->pool, (size_t)slots * 4);
     if (res->depth0) {
         check(launch_iota(res->dev_ids.as<int32_t>(), res->info.member_slots, ctx->stream), "iota");
+    } else if (res->entry_bytes == 4) {   // packed points: ids through a table of ranks per pixel
+        DevBuf table(&ctx->pool, (size_t)res->info.width * (size_t)res->info.height * 4);
+        if (!table) throw Error{HH_ENOMEM, "pixel rank table"};
+        check(launch_ids_by_pixel(res->xy, res->info.n_points, res->info.width, res->info.height,
+                                  table.as<int32_t>(), static_cast<const uint32_t*>(res->members),
+                                  res->info.member_slots, res->dev_ids.as<int32_t>(), ctx->stream),
+              "member ids");
+        sync(ctx);   // the table returns to the pool when this scope ends
     } else {
         check(launch_member_ids(res->cells, res->n_cells_total, nullptr, res->mem_base, res->members_base,
                                 res->entry_bytes, res->xy, res->info.n_points, res->dev_ids.as<int32_t>(),
@@ -1091,16 +1099,15 @@ hh_status engine_host_members(hh_result* res)
 
 // solution() with removal (Sec. 3): one walk per tree of every result, in
 // one launch per bitmap kind.  A result's pass p owns keep flags for its
-// cells and plotted flags for its n_points ids.
+// cells and plotted flags for its n_points ids.  The voter ids, rebased cells
+// and pixel rank table the walk reads live only for the call, in one buffer
+// each; the flags of all results share one buffer, held by every result.
 hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double* kernel_ms)
 {
     if (kernel_ms) *kernel_ms = 0.0;
     check(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = ctx->stream;
-    std::vector<SolTree> lds, dev;
     std::vector<hh_result*> todo;
-    int64_t max_lds_points = 0, dev_words = 0;
-    std::vector<int64_t> dev_word_off;
     for (int32_t k = 0; k < n; ++k) {
         hh_result* r = res[k];
         if (!r) throw Error{HH_EINVAL, "null result"};
@@ -1109,44 +1116,84 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
         if (r->sol_ready || std::find(todo.begin(), todo.end(), r) != todo.end()) continue;
         todo.push_back(r);
     }
-    for (hh_result* r : todo) {
-        engine_device_ids(r);
-        const Cell* cells = engine_device_cells(r);
-        const int32_t* ids = r->dev_ids.as<const int32_t>();
-        if (reinterpret_cast<uintptr_t>(ids) & 15u) throw Error{HH_EINTERNAL, "member ids not 16-byte aligned"};
-        const int64_t E = r->info.n_points;
-        int64_t bytes = 0, before = 0;
+    if (todo.empty()) return HH_OK;
+    // sizes: ids (4-aligned per result, for 16-byte loads), rebased cells, table, flags
+    const size_t nr = todo.size();
+    std::vector<int64_t> ids_off(nr), cells_off(nr, -1), flags_off(nr);
+    int64_t n_ids = 0, n_cells = 0, max_pix = 1, flag_bytes = 0;
+    for (size_t k = 0; k < nr; ++k) {
+        hh_result* r = todo[k];
+        ids_off[k] = n_ids;
+        n_ids += (std::max<int64_t>(r->info.member_slots, 1) + 3) & ~(int64_t)3;
+        if (!r->depth0 && r->mem_base != 0 && r->n_cells_total > 0) {
+            cells_off[k] = n_cells;
+            n_cells += r->n_cells_total;
+        }
+        if (!r->depth0 && r->entry_bytes == 4)
+            max_pix = std::max<int64_t>(max_pix, (int64_t)r->info.width * r->info.height);
+        // flags: keep per cell, plotted per point and pass, then 4 counts
+        flags_off[k] = flag_bytes;
+        int64_t before = 0;
         for (int q = 0; q < r->n_trees; ++q) {
             const int32_t p = r->tree_pass[q];
             r->sol_keep_off[p] = before;
             before += r->info.n_cells[p];
         }
-        bytes = align256(std::max<int64_t>(before, 1));
+        int64_t bytes = align256(std::max<int64_t>(before, 1));
         for (int q = 0; q < r->n_trees; ++q) {
-            const int32_t p = r->tree_pass[q];
-            r->sol_plot_off[p] = bytes;
-            bytes += align256(std::max<int64_t>(E, 1));
+            r->sol_plot_off[r->tree_pass[q]] = bytes;
+            bytes += align256(std::max<int64_t>(r->info.n_points, 1));
         }
         r->sol_counts_off = bytes;
-        bytes += 256;
-        r->sol = DevBuf(&ctx->pool, (size_t)bytes);
-        if (!r->sol) throw Error{HH_ENOMEM, "solution flags"};
-        uint8_t* base = r->sol.as<uint8_t>();
+        flag_bytes += bytes + 256;
+    }
+    DevBuf ids(&ctx->pool, (size_t)n_ids * 4);
+    DevBuf cells(&ctx->pool, (size_t)std::max<int64_t>(n_cells, 1) * sizeof(Cell));
+    DevBuf table(&ctx->pool, (size_t)max_pix * 4);
+    auto flags = std::make_shared<DevBuf>(&ctx->pool, (size_t)flag_bytes);
+    if (!ids || !cells || !table || !*flags) throw Error{HH_ENOMEM, "solution buffers"};
+    std::vector<SolTree> lds, dev;
+    int64_t max_lds_points = 0, dev_words = 0;
+    std::vector<int64_t> dev_word_off;
+    for (size_t k = 0; k < nr; ++k) {
+        hh_result* r = todo[k];
+        const int64_t E = r->info.n_points, slots = r->info.member_slots;
+        int32_t* dst = ids.as<int32_t>() + ids_off[k];
+        if (r->depth0) {
+            check(launch_iota(dst, slots, st), "iota");
+        } else if (r->entry_bytes == 4) {   // packed points: ids through the table of ranks per pixel
+            check(launch_ids_by_pixel(r->xy, E, r->info.width, r->info.height, table.as<int32_t>(),
+                                      static_cast<const uint32_t*>(r->members), slots, dst, st),
+                  "member ids");
+        } else {
+            check(launch_member_ids(r->cells, r->n_cells_total, nullptr, r->mem_base, r->members_base,
+                                    r->entry_bytes, r->xy, E, dst, st),
+                  "member ids");
+        }
+        const Cell* rc = r->cells;   // member_off counted from the result's first voter
+        if (cells_off[k] >= 0) {
+            Cell* d = cells.as<Cell>() + cells_off[k];
+            check(launch_rebase_cells(r->cells, r->n_cells_total, r->mem_base, d, st), "rebase cells");
+            rc = d;
+        }
+        r->sol_store = flags;
+        r->sol = flags->as<uint8_t>() + flags_off[k];
+        uint8_t* base = const_cast<uint8_t*>(r->sol);
         int64_t cbefore = 0;
         for (int q = 0; q < r->n_trees; ++q) {
             const int32_t p = r->tree_pass[q];
             SolTree t{};
-            t.cells = cells ? cells + cbefore : nullptr;
-            t.ids = ids;
+            t.cells = rc ? rc + cbefore : nullptr;
+            t.ids = dst;
             t.n_cells = r->info.n_cells[p];
             t.n_points = E;
-            t.n_slots = r->info.member_slots;
+            t.n_slots = slots;
             t.keep = base + r->sol_keep_off[p];
             t.plotted = base + r->sol_plot_off[p];
             t.counts = reinterpret_cast<int64_t*>(base + r->sol_counts_off) + 2 * p;
             t.threshold = r->info.threshold;
             cbefore += t.n_cells;
-            if (t.n_cells > 0 && (!t.cells || !t.ids)) throw Error{HH_EINTERNAL, "solution inputs missing"};
+            if (t.n_cells > 0 && !t.cells) throw Error{HH_EINTERNAL, "solution inputs missing"};
             if (E <= solution_lds_points()) {
                 max_lds_points = std::max(max_lds_points, E);
                 lds.push_back(t);
@@ -1158,7 +1205,6 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
         }
     }
     const int32_t n_lds = (int32_t)lds.size(), n_dev = (int32_t)dev.size();
-    if (n_lds + n_dev == 0) return HH_OK;
     DevBuf bitmap;
     if (n_dev > 0) {
         bitmap = DevBuf(&ctx->pool, (size_t)dev_words * 4);
@@ -1168,11 +1214,13 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
     }
     std::vector<SolTree> all(lds);
     all.insert(all.end(), dev.begin(), dev.end());
-    const size_t table = (size_t)align256((int64_t)(all.size() * sizeof(SolTree)));
-    DevBuf d(&ctx->pool, table + 256);
+    const size_t table_bytes = (size_t)align256((int64_t)(std::max<size_t>(all.size(), 1) * sizeof(SolTree)));
+    DevBuf d(&ctx->pool, table_bytes + 256);
     if (!d) throw Error{HH_ENOMEM, "solution table"};
-    uint32_t* d_err = reinterpret_cast<uint32_t*>(d.as<char>() + table);
-    check(hipMemcpyAsync(d.get(), all.data(), all.size() * sizeof(SolTree), hipMemcpyHostToDevice, st), "copy table");
+    uint32_t* d_err = reinterpret_cast<uint32_t*>(d.as<char>() + table_bytes);
+    if (!all.empty())
+        check(hipMemcpyAsync(d.get(), all.data(), all.size() * sizeof(SolTree), hipMemcpyHostToDevice, st),
+              "copy table");
     check(hipMemsetAsync(d_err, 0, 4, st), "clear error");
     hipEvent_t ev[2];
     check(hipEventCreate(&ev[0]), "event");
@@ -1191,6 +1239,9 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
     check(hipEventRecord(ev[0], st), "event");
     check(launch_solution(d.as<SolTree>(), n_lds, max_lds_points, n_dev, d_err, st), "solution");
     check(hipEventRecord(ev[1], st), "event");
+    // errors and counts of every result come back in two copies
+    std::vector<int64_t> counts(4 * nr, 0);
+    std::vector<char> hflags;
     uint32_t err = 0;
     check(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, st), "copy error");
     sync(ctx);
@@ -1198,15 +1249,17 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
     float ms = 0.f;
     check(hipEventElapsedTime(&ms, ev[0], ev[1]), "event time");
     if (kernel_ms) *kernel_ms = ms;
-    for (hh_result* r : todo) {   // counts: 32 bytes per result
-        int64_t counts[4] = {0, 0, 0, 0};
-        check(hipMemcpyAsync(counts, r->sol.as<char>() + r->sol_counts_off, sizeof(counts), hipMemcpyDeviceToHost,
-                             st),
+    for (size_t k = 0; k < nr; ++k) {
+        hh_result* r = todo[k];
+        check(hipMemcpyAsync(&counts[4 * k], r->sol + r->sol_counts_off, 32, hipMemcpyDeviceToHost, st),
               "copy counts");
-        sync(ctx);
+    }
+    sync(ctx);
+    for (size_t k = 0; k < nr; ++k) {
+        hh_result* r = todo[k];
         for (int p = 0; p < 2; ++p) {
-            r->sol_kept[p] = counts[2 * p];
-            r->sol_plotted[p] = counts[2 * p + 1];
+            r->sol_kept[p] = counts[4 * k + 2 * p];
+            r->sol_plotted[p] = counts[4 * k + 2 * p + 1];
         }
         r->sol_ready = true;
     }
@@ -1222,11 +1275,11 @@ hh_status engine_host_solution(hh_result* res, int32_t pass)
     res->host_keep[pass].assign((size_t)nc, 0);
     res->host_plotted[pass].assign((size_t)E, 0);
     if (nc > 0)
-        check(hipMemcpyAsync(res->host_keep[pass].data(), res->sol.as<char>() + res->sol_keep_off[pass], (size_t)nc,
+        check(hipMemcpyAsync(res->host_keep[pass].data(), res->sol + res->sol_keep_off[pass], (size_t)nc,
                              hipMemcpyDeviceToHost, ctx->stream),
               "copy keep");
     if (E > 0)
-        check(hipMemcpyAsync(res->host_plotted[pass].data(), res->sol.as<char>() + res->sol_plot_off[pass], (size_t)E,
+        check(hipMemcpyAsync(res->host_plotted[pass].data(), res->sol + res->sol_plot_off[pass], (size_t)E,
                              hipMemcpyDeviceToHost, ctx->stream),
               "copy plotted");
     sync(ctx);

@@ -117,7 +117,8 @@ struct hh_result {
     // solution() with removal (hough_hier_solution): per pass, keep flags of
     // its cells and plotted flags of the point ids, then the counts
     bool sol_ready = false;
-    hh::DevBuf sol;
+    std::shared_ptr<hh::DevBuf> sol_store;   // the flags of every result of one hough_hier_solution call
+    const uint8_t* sol = nullptr;            // this result's part
     int64_t sol_keep_off[2] = {0, 0};
     int64_t sol_plot_off[2] = {0, 0};
     int64_t sol_counts_off = 0;

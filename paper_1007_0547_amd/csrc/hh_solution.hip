@@ -12,18 +12,26 @@
 //
 // The walk is sequential by definition; one workgroup walks one tree.  It
 // streams the tree's voter ids in windows of kSolCh entries held in registers
-// (kSolR consecutive entries per lane).  For the cells of a window it counts
-// the unplotted voters with a block-wide prefix over per-entry live bits,
-// takes the first cell above T, plots it, and tests the window's entries again
-// from registers until no cell of the window is above T.  A cell that runs
-// past the window carries its count into the next one.  The plotted set is a
-// bitmap over the tree's point ids: in LDS when it fits, else in device memory
-// behind atomics at workgroup scope (performed in L2, one copy for all waves of
-// the workgroup).
+// (kSolR consecutive entries per lane, the next window's loaded while this one
+// is processed).  Each lane tests its entries against the plotted set and
+// stores its live bits into the window's live bitmap in LDS; the lane of each
+// cell of the window counts the cell's live entries there (popcounts over its
+// range), the first cell above T is plotted, and the window's remaining
+// entries are tested again from registers until no cell of the window is above
+// T.  A cell that runs past the window carries its count into the next one.
+// The plotted set is a bitmap over the tree's point ids: in LDS when it fits,
+// else in device memory behind atomics at workgroup scope (performed in L2,
+// one copy for all waves of the workgroup).
+//
+// The walk of one tree runs on one compute unit and is bound by its vector ALU
+// issue (the live test, the window setup) and by the latency of each window's
+// loads; many trees (a batch) fill the device.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "hh_solution.hpp"
 
@@ -37,7 +45,9 @@ constexpr int kSolCh = kSolThreads * kSolR;     // entries per window
 constexpr int kSolMaxCells = 256;               // cells per window, one per lane of the first lanes
 constexpr int64_t kSolLdsBytes = 40 << 10;      // LDS for the plotted bitmap
 constexpr int64_t kSolLdsPoints = kSolLdsBytes * 8;
-static_assert(kSolR == 8, "a lane's live bits are one byte of the window's live bitmap");
+// A lane's live bits are kSolR consecutive bits of the window's live bitmap.
+using LaneBits = std::conditional_t<kSolR == 8, uint8_t, uint16_t>;
+static_assert(kSolR == 8 || kSolR == 16, "a lane's live bits are one byte or one half-word");
 static_assert(kSolMaxCells <= kSolThreads, "one lane per window cell");
 
 template <typename T>
@@ -180,7 +190,7 @@ template <bool kLds>
 __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, uint32_t* error)
 {
     extern __shared__ uint32_t s_bits[];
-    __shared__ uint32_t s_live[kSolCh / 32];     // the window's live bitmap: one byte per lane
+    __shared__ uint32_t s_live[kSolCh / 32];     // the window's live bitmap, kSolR bits per lane
     __shared__ int32_t s_cs[kSolMaxCells];       // window cells: first and end window position
     __shared__ int32_t s_ce[kSolMaxCells];
     __shared__ int32_t s_first[kSolWaves];
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
 
     const int32_t T = t.threshold;
     const uint32_t n_points = (uint32_t)t.n_points;              // ids are 32-bit
-    uint8_t* live_byte = reinterpret_cast<uint8_t*>(s_live) + tid;
+    LaneBits* live_byte = reinterpret_cast<LaneBits*>(s_live) + tid;
     const int x0 = kSolR * tid;                                   // this lane's first window position
     int64_t c_cur = 0;                                            // first undecided cell
     int64_t pos = t.n_cells > 0 ? ldg(&t.cells[0].member_off) : 0;   // its first untested voter
@@ -243,7 +253,7 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         for (int j = 0; j < kSolR; ++j) id[j] = nid[j];
         uint32_t valid = 0;
         uint32_t m = live_bits<kLds>(bits, id, n_points, x0, 0, &valid);
-        *live_byte = (uint8_t)m;
+        *live_byte = (LaneBits)m;
         sol_barrier<kLds>();
         if (s_bad_cells) {
             bad = true;
@@ -325,7 +335,7 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
             }
             // entries up to cell f's end are decided; test the rest again
             m = live_bits<kLds>(bits, id, n_points, x0, fe, &valid);
-            *live_byte = (uint8_t)m;
+            *live_byte = (LaneBits)m;
             sol_barrier<kLds>();
         }
         if (bad) break;
@@ -356,7 +366,40 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
     }
 }
 
+// The rank table of an image's edge points: table[y * W + x] = k for
+// xy[k] = x | y << 16.
+__global__ void k_pixel_rank(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height, int32_t* table)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_points;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = ldg(xy + k);
+        const int32_t x = (int32_t)(p & 0xFFFFu), y = (int32_t)(p >> 16);
+        if (x < width && y < height) stg(table + (int64_t)y * width + x, (int32_t)k);
+    }
+}
+
+__global__ void k_ids_by_pixel(const int32_t* table, int32_t width, int32_t height, const uint32_t* src,
+                               int64_t n_slots, int32_t* dst)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_slots;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = ldg(src + e);
+        const int32_t x = (int32_t)(p & 0xFFFFu), y = (int32_t)(p >> 16);
+        stg(dst + e, x < width && y < height ? ldg(table + (int64_t)y * width + x) : -1);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_ids_by_pixel(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height,
+                               int32_t* table, const uint32_t* src, int64_t n_slots, int32_t* dst, hipStream_t s)
+{
+    constexpr int kThreads = 256;
+    auto grid = [](int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + kThreads - 1) / kThreads, 1), 8192); };
+    if (n_points > 0) k_pixel_rank<<<grid(n_points), kThreads, 0, s>>>(xy, n_points, width, height, table);
+    if (n_slots > 0) k_ids_by_pixel<<<grid(n_slots), kThreads, 0, s>>>(table, width, height, src, n_slots, dst);
+    return hipGetLastError();
+}
 
 int64_t solution_lds_points() { return kSolLdsPoints; }
 

@@ -31,4 +31,11 @@ int64_t solution_lds_points();
 hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_points, int32_t n_dev,
                            uint32_t* error, hipStream_t s);
 
+// Point ids of packed-point voter entries (binary-image inputs, whose ids are
+// the row-major ranks of their edge points xy[0 .. n_points)): a W x H table
+// of ranks (table, W * H int32) is filled from xy, then dst[e] is the rank of
+// the point in src[e] for e < n_slots (-1 for an entry outside the image).
+hipError_t launch_ids_by_pixel(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height,
+                               int32_t* table, const uint32_t* src, int64_t n_slots, int32_t* dst, hipStream_t s);
+
 }  // namespace hh
