@@ -131,6 +131,8 @@ _lib.hough_hier_solution.restype = C.c_int
 _lib.hough_hier_solution.argtypes = [C.POINTER(_p), C.c_int32, C.POINTER(C.c_double)]
 _lib.hough_hier_result_solution.restype = C.c_int
 _lib.hough_hier_result_solution.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]
+_lib.hough_hier_result_solution_image.restype = C.c_int
+_lib.hough_hier_result_solution_image.argtypes = [_p, C.c_void_p, C.c_int64, C.c_int32]
 _lib.hough_hier_result_free.restype = None
 _lib.hough_hier_result_free.argtypes = [_p]
 
@@ -237,6 +239,23 @@ class Result:
             plotted = np.frombuffer((C.c_uint8 * out.n_points).from_address(out.plotted),
                                     dtype=np.uint8).astype(bool)
         return {"keep": keep, "plotted": plotted, "kept": out.kept, "plotted_points": out.plotted_points}
+
+    def solution_image(self, out=None) -> np.ndarray:
+        """The output image of :func:`solution` (255 at plotted points of any
+        pass, else 0), ``height x width`` uint8.  ``out`` may be a torch
+        device tensor or a numpy array of that shape (rows may be strided);
+        by default a new numpy array is returned."""
+        H, W = self.info["height"], self.info["width"]
+        if out is None:
+            out = np.empty((H, W), dtype=np.uint8)
+        if _is_torch_cuda(out):
+            assert tuple(out.shape) == (H, W) and out.stride(1) == 1
+            self._check(_lib.hough_hier_result_solution_image(self._h, C.c_void_p(out.data_ptr()),
+                                                              out.stride(0), 1))
+        else:
+            assert out.shape == (H, W) and out.dtype == np.uint8 and out.strides[1] == 1
+            self._check(_lib.hough_hier_result_solution_image(self._h, out.ctypes.data, out.strides[0], 0))
+        return out
 
     def device_solution(self, pass_: int) -> dict:
         """Device pointers of one pass's keep and plotted flags and the counts."""

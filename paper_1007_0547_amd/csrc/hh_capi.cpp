@@ -268,6 +268,15 @@ hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_de
     return HH_OK;
 }
 
+hh_status hough_hier_result_solution_image(hh_result* res, uint8_t* image, int64_t row_stride, int32_t on_device)
+{
+    if (!res || !image) return HH_EINVAL;
+    if (!res->sol_ready) return fail(res->ctx, HH_EINVAL, "hough_hier_solution has not run on this result");
+    if (row_stride < res->info.width) return fail(res->ctx, HH_EINVAL, "row_stride is below the image width");
+    std::lock_guard<std::mutex> g(res->ctx->mu);
+    return guarded(res->ctx, [&] { return hh::engine_solution_image(res, image, row_stride, on_device); });
+}
+
 void hough_hier_result_free(hh_result* res)
 {
     if (!res) return;

@@ -1287,4 +1287,30 @@ hh_status engine_host_solution(hh_result* res, int32_t pass)
     return HH_OK;
 }
 
+hh_status engine_solution_image(hh_result* res, uint8_t* image, int64_t row_stride, int32_t on_device)
+{
+    hh_ctx* ctx = res->ctx;
+    check(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    const int32_t W = res->info.width, H = res->info.height;
+    DevBuf img(&ctx->pool, (size_t)W * (size_t)H);
+    if (!img) throw Error{HH_ENOMEM, "output image"};
+    check(hipMemsetAsync(img.get(), 0, (size_t)W * (size_t)H, st), "clear image");
+    const Cell* cells = engine_device_cells(res);   // member_off counted from res->members
+    int64_t before = 0;
+    for (int q = 0; q < res->n_trees; ++q) {
+        const int32_t p = res->tree_pass[q];
+        const int64_t nc = res->info.n_cells[p];
+        check(launch_paint(cells + before, nc, res->sol + res->sol_keep_off[p], res->members, res->entry_bytes, W, H,
+                           img.as<uint8_t>(), st),
+              "paint");
+        before += nc;
+    }
+    check(hipMemcpy2DAsync(image, (size_t)row_stride, img.get(), (size_t)W, (size_t)W, (size_t)H,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st),
+          "copy image");
+    sync(ctx);
+    return HH_OK;
+}
+
 }  // namespace hh

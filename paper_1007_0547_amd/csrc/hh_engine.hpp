@@ -197,6 +197,9 @@ const Cell* engine_device_cells(hh_result* res);
 hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double* kernel_ms);
 // Host copies of one pass's keep and plotted flags.
 hh_status engine_host_solution(hh_result* res, int32_t pass);
+// The output image of solution() (plotted points of every pass = 255, else 0)
+// into image (host or device memory, rows of row_stride bytes).
+hh_status engine_solution_image(hh_result* res, uint8_t* image, int64_t row_stride, int32_t on_device);
 
 // Serving (hh_serve.cpp).
 hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg);

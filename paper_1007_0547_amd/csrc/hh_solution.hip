@@ -389,7 +389,41 @@ __global__ void k_ids_by_pixel(const int32_t* table, int32_t width, int32_t heig
     }
 }
 
+// One wavefront per cell; kept cells paint their voters.
+template <typename Entry>
+__global__ void k_paint(const Cell* cells, int64_t n_cells, const uint8_t* keep, const Entry* members,
+                        int32_t width, int32_t height, uint8_t* image)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t c = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; c < n_cells; c += waves) {
+        if (!ldg(keep + c)) continue;
+        const int64_t off = ldg(&cells[c].member_off);
+        const int32_t votes = ldg(&cells[c].votes);
+        for (int32_t k = lane; k < votes; k += kWave) {
+            const uint32_t p = (uint32_t)ldg(members + off + k);
+            const int32_t x = (int32_t)(p & 0xFFFFu), y = (int32_t)(p >> 16);
+            if (x < width && y < height) stg(image + (int64_t)y * width + x, (uint8_t)255);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_paint(const Cell* cells, int64_t n_cells, const uint8_t* keep, const void* members,
+                        int entry_bytes, int32_t width, int32_t height, uint8_t* image, hipStream_t s)
+{
+    if (n_cells <= 0) return hipSuccess;
+    constexpr int kThreads = 256;
+    const int grid = (int)std::min<int64_t>((n_cells + kThreads / kWave - 1) / (kThreads / kWave), 4096);
+    if (entry_bytes == 8)
+        k_paint<uint64_t><<<grid, kThreads, 0, s>>>(cells, n_cells, keep, static_cast<const uint64_t*>(members),
+                                                     width, height, image);
+    else
+        k_paint<uint32_t><<<grid, kThreads, 0, s>>>(cells, n_cells, keep, static_cast<const uint32_t*>(members),
+                                                     width, height, image);
+    return hipGetLastError();
+}
 
 hipError_t launch_ids_by_pixel(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height,
                                int32_t* table, const uint32_t* src, int64_t n_slots, int32_t* dst, hipStream_t s)

@@ -38,4 +38,11 @@ hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_
 hipError_t launch_ids_by_pixel(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height,
                                int32_t* table, const uint32_t* src, int64_t n_slots, int32_t* dst, hipStream_t s);
 
+// The output image: image[y * width + x] = 255 for the voters of the kept
+// cells (keep[c] = 1) among n_cells cells whose voters are entries of
+// entry_bytes bytes at members[cells[c].member_off ...] (the packed point in
+// the low 32 bits); other pixels are left as they are.
+hipError_t launch_paint(const Cell* cells, int64_t n_cells, const uint8_t* keep, const void* members,
+                        int entry_bytes, int32_t width, int32_t height, uint8_t* image, hipStream_t s);
+
 }  // namespace hh

@@ -101,3 +101,4 @@ def test_solution_null_arguments():
     out = hh._Solution()
     assert lib.hough_hier_result_solution(None, 0, 0, C.byref(out)) == -1
     assert lib.hough_hier_result_solution(None, 0, 0, None) == -1
+    assert lib.hough_hier_result_solution_image(None, None, 0, 0) == -1

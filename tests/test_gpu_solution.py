@@ -56,6 +56,15 @@ def points(img):
     return oracle.edge_points(img)
 
 
+def check_image(r, want, x, y, what=""):
+    """The output image: 255 at the points plotted by any pass, else 0."""
+    H, W = r.info["height"], r.info["width"]
+    ref = np.zeros((H, W), np.uint8)
+    for p, (_, plotted) in want.items():
+        ref[np.asarray(y)[plotted], np.asarray(x)[plotted]] = 255
+    np.testing.assert_array_equal(r.solution_image(), ref, err_msg=f"{what} image")
+
+
 CASES = [
     # name, image maker, T, dmax, variant
     ("line256", lambda: synth.workload("line256", 0).image, 40, 0, "code"),
@@ -80,6 +89,7 @@ def test_solution_images(hh, case):
         ms = ctx.solution([r])
         assert ms > 0
         check(r, want, len(x), name)
+        check_image(r, want, x, y, name)
         assert ctx.solution([r]) == 0.0   # solved results are skipped
         r.free()
 
@@ -99,6 +109,7 @@ def test_solution_point_lists(hh):
             r = ctx.detect(x, y, width=W, height=H)
             ctx.solution(r)
             check(r, want, len(x), name)
+            check_image(r, want, x, y, name)
             r.free()
 
 
@@ -139,6 +150,14 @@ def test_solution_gray(hh):
         r = ctx.detect(gray=g, edge_threshold=180, width=W, height=H)
         ctx.solution(r)
         check(r, want, len(x), "gray")
+        check_image(r, want, x, y, "gray")
+        import torch
+        out = torch.full((H, W + 8), 7, dtype=torch.uint8, device="cuda")   # strided device rows
+        r.solution_image(out[:, :W])
+        torch.cuda.synchronize()
+        ref = r.solution_image()
+        np.testing.assert_array_equal(out[:, :W].cpu().numpy(), ref)
+        assert (out[:, W:] == 7).all()
         r.free()
 
 
@@ -164,6 +183,8 @@ def test_solution_batch_served_and_mixed(hh):
         hh.solution(served[:3] + plain + served[3:])
         for k, r in enumerate(served):
             check(r, *wants[k], what=f"served {k}")
+            x, y = points(imgs[k])
+            check_image(r, wants[k][0], x, y, f"served {k}")
             r.free()
         for k, r in enumerate(plain):
             check(r, *wants[k], what=f"plain {k}")
@@ -190,6 +211,7 @@ def test_solution_edge_cases(hh):
         r = ctx.detect(xs, xs, width=1, height=1)
         ctx.solution(r)
         check(r, expect(xs, xs, 1, 1, 3), 7, "depth 0")
+        assert r.solution_image().tolist() == [[255]]
         r.free()
     with hh.HoughHier(threshold=5, membership=False) as ctx:
         r = ctx.detect(image=img, width=40, height=40)
