@@ -316,7 +316,10 @@ HH_API hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timin
  * hough_hier_solution computes this on the device for n results (one launch
  * for all their passes; results of a serving context are walked on the lane
  * that made them); a result already solved is skipped.  *kernel_ms (may be
- * NULL) receives the summed duration of the walk kernels.
+ * NULL) receives the summed duration of the walk kernels.  While it runs the
+ * call holds device memory for the voter ids of all its results (4 bytes per
+ * voter, kept in the context's pool for later calls); the flags (a byte per
+ * cell, and per point and pass) stay with the results until they are freed.
  * Errors: HH_EINVAL (null arguments, membership was not kept), HH_ENOMEM,
  * HH_EDEVICE, HH_EINTERNAL (malformed result). */
 HH_API hh_status hough_hier_solution(hh_result* const* results, int32_t n, double* kernel_ms);
