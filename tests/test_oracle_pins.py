@@ -393,3 +393,22 @@ def test_golden_line256(orc):
         assert res.stats[p].tolist() == g["stats"][str(p)]
     assert len(res.cells) == g["n_cells"]
     assert int(res.members.astype(np.int64).sum()) == g["members_sum"]
+
+
+def test_solution_removal_closed_forms(orc):
+    """One row of W collinear points (optionally each point twice): every
+    point's parameter line passes through (m, b) = (0, row), and with T one
+    below the number of points only cells crossed by every line are detected.
+    The first of them in key order is kept and plots every point, so no later
+    cell has a live voter: exactly one kept cell, every point plotted (Sec. 3,
+    solution()).  Rows inside a cell and on a b grid line, both passes."""
+    for W, H, row, dup in ((32, 32, 7, 1), (32, 32, 5, 1), (64, 16, 9, 1), (20, 40, 13, 2)):
+        x = np.tile(np.arange(W), dup).astype(np.int32)
+        y = np.full(W * dup, row, dtype=np.int32)
+        n = W * dup
+        cells, keep, plotted = orc.solution(x, y, W, H, n - 1, 0, 0)
+        assert len(cells) >= 3 and (cells["votes"] == n).all(), (W, row)   # removal must skip cells 2..n
+        assert keep.sum() == 1 and keep[0] and plotted.all(), (W, row)
+        # the same row read as a column goes to pass 1
+        cells, keep, plotted = orc.solution(y, x, H, W, n - 1, 0, 1)
+        assert keep.sum() == 1 and keep[0] and plotted.all(), (W, row, "pass 1")
