@@ -1204,6 +1204,9 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
             }
         }
     }
+    // longest walks first: workgroups start in launch order, so a long walk
+    // started last would run on alone
+    std::stable_sort(lds.begin(), lds.end(), [](const SolTree& a, const SolTree& b) { return a.n_slots > b.n_slots; });
     const int32_t n_lds = (int32_t)lds.size(), n_dev = (int32_t)dev.size();
     DevBuf bitmap;
     if (n_dev > 0) {
