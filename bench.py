@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def survey_alg_bytes(stats_by_pass, detected_votes_by_pass, E):
+def id_list_alg_bytes(stats_by_pass, detected_votes_by_pass, E):
     """Algorithmic bytes of an id-list design that gathers coordinates: per
     pass 8 E + sum_{1<=l<D} 12 L_l + sum_{1<=l<=D} 4 L_l, with L_l the summed
     votes of the regions split at level l and L_D those of the detected
@@ -661,7 +661,7 @@ def main():
                      "other": {f"k_{k}": {"alg_bytes_per_step": kb[k], "ms_per_step": kms[k],
                                           "GB/s": kb[k] / (kms[k] / 1e3) / 1e9 if kms[k] > 0 else 0.0}
                                for k in kms},
-                     "id_list_design_alg_bytes_per_step": survey_alg_bytes(stats, det_votes, E)},
+                     "id_list_design_alg_bytes_per_step": id_list_alg_bytes(stats, det_votes, E)},
     }
     ctx.close()
     if not args.no_batched:
