@@ -205,6 +205,14 @@ def test_solution_edge_cases(hh):
             s = r.solution(p)
             assert s["kept"] == 0 and s["plotted_points"] == 0 and len(s["plotted"]) == len(x)
         r.free()
+    with hh.HoughHier(threshold=0) as ctx:   # no edge points at all
+        r = ctx.detect(image=np.zeros((16, 24), np.uint8), width=24, height=16)
+        ctx.solution(r)
+        for p in (0, 1):
+            s = r.solution(p)
+            assert s["kept"] == 0 and s["plotted_points"] == 0 and len(s["keep"]) == 0 and len(s["plotted"]) == 0
+        assert (r.solution_image() == 0).all() and r.solution_image().shape == (16, 24)
+        r.free()
     # a 1x1 image: depth 0, the root is the finest region and every point votes
     xs = np.zeros(7, np.int32)
     with hh.HoughHier(threshold=3) as ctx:
