@@ -340,8 +340,8 @@ typedef struct {
  * Errors: HH_EINVAL (bad pass, hough_hier_solution not run on res), HH_EDEVICE. */
 HH_API hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_device, hh_solution* out);
 
-/* The output image of solution() (Sec. 3: the plotted points are reflected in
- * the output image): height rows of width bytes, row r at image + r *
+/* The output image of solution() (Sec. 3: the plotted points make up the
+ * output image): height rows of width bytes, row r at image + r *
  * row_stride, set to 255 where a point plotted by any enabled pass lies and 0
  * elsewhere.  image is caller-owned host memory (on_device = 0) or device
  * memory (on_device = 1); the call waits until it is written.
