@@ -12,8 +12,12 @@ never does, and the two share no code.
   circle test of the comparison method (``variant='circle'``), both passes
   (ALPHA as given, BETA with the axes swapped), implemented in plain C
   (``hough_oracle.c``) with exact integer arithmetic.
+* :func:`detect_subtree` -- the same search restricted to one region and
+  everything below it (a part of a large search, run or timed on its own).
 * :func:`region_voters` -- the voters of one region found by testing every
   line against it directly, with no hierarchy.
+* :func:`member_digest` -- the checksum ``detect(..., keep_members="digest")``
+  folds a pass's voters into, computed from a voter list.
 * :func:`solution` -- solution() of Sec. 3 with the removal of plotted edge
   points, as a greedy walk over the detected cells in depth-first order.
 * :func:`sobel_partition` -- the edge front end of Sec. 3: Sobel's gradient
@@ -35,6 +39,9 @@ _lib = None
 
 STAT_NAMES = ("evaluated", "votes", "split", "detected", "code_tests", "entries")
 VARIANTS = {"code": 0, "circle": 1}
+MEMBERS = {False: 0, True: 1, "digest": 2}
+DIGEST_A = 0x9E3779B97F4A7C15
+DIGEST_B = 0x632BE59BD9B4E019
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
@@ -67,6 +74,15 @@ def _load():
     lib.hough_oracle_stats.argtypes = [C.c_void_p, C.c_int32, _i64p]
     lib.hough_oracle_free.restype = None
     lib.hough_oracle_free.argtypes = [C.c_void_p]
+    lib.hough_oracle_member_digest.restype = C.c_uint64
+    lib.hough_oracle_member_digest.argtypes = [C.c_void_p, C.c_int32]
+    lib.hough_oracle_pass_members.restype = C.c_int64
+    lib.hough_oracle_pass_members.argtypes = [C.c_void_p, C.c_int32]
+    lib.hough_oracle_detect_subtree.restype = C.c_void_p
+    lib.hough_oracle_detect_subtree.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                                C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                                C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                                                C.c_int32]
     lib.hough_oracle_region_voters.restype = C.c_int64
     lib.hough_oracle_region_voters.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                                C.c_int32, C.c_int32, C.c_int32, C.c_int64,
@@ -155,12 +171,16 @@ class OracleResult:
     ``cells`` is a structured array with fields pass, i, j, key, votes,
     member_off; ``members`` holds each cell's voters (ascending ids) at
     ``member_off`` (empty when membership was not kept); ``stats[pass]`` is
-    an int64 array of shape (Dmax + 1, 6) with columns ``STAT_NAMES``."""
+    an int64 array of shape (Dmax + 1, 6) with columns ``STAT_NAMES``.
+    ``member_digest[pass]`` is the pass's voter checksum (``keep_members=
+    "digest"``, else 0) and ``pass_members[pass]`` its number of voters."""
     S: int
     dmax: int
     cells: np.ndarray
     members: np.ndarray
     stats: Dict[int, np.ndarray]
+    member_digest: Dict[int, int] = None
+    pass_members: Dict[int, int] = None
 
     def cell_members(self, c: int) -> np.ndarray:
         off = int(self.cells["member_off"][c])
@@ -182,11 +202,12 @@ def _as_i32(a) -> np.ndarray:
 
 
 def detect(x, y, W: int, H: int, threshold: int, max_depth: int = 0,
-           variant: str = "code", passes: int = 3, keep_members: bool = True) -> OracleResult:
+           variant: str = "code", passes: int = 3, keep_members=True) -> OracleResult:
     """Hierarchical vote (Sec. 3) of the edge points ``(x, y)`` of a W x H
     image.  ``max_depth=0`` selects ceil(log2(max(W, H))), ``-1`` depth 0.
     ``passes`` bit 0 = pass 0 (|m| <= 1 as given), bit 1 = pass 1 (x, y
-    swapped)."""
+    swapped).  ``keep_members``: True stores every cell's voters, False
+    none, ``"digest"`` folds them into ``member_digest`` instead."""
     lib = _load()
     x, y = _as_i32(x), _as_i32(y)
     if x.shape != y.shape:
@@ -194,7 +215,41 @@ def detect(x, y, W: int, H: int, threshold: int, max_depth: int = 0,
     E = int(x.size)
     h = lib.hough_oracle_detect(x.ctypes.data if E else None, y.ctypes.data if E else None,
                                 E, int(W), int(H), int(threshold), int(max_depth),
-                                VARIANTS[variant], int(passes), int(bool(keep_members)))
+                                VARIANTS[variant], int(passes), MEMBERS[keep_members])
+    return _collect(lib, h, passes)
+
+
+def detect_subtree(x, y, W: int, H: int, threshold: int, max_depth: int, pass_: int,
+                   level: int, i: int, j: int, key: int, cand, variant: str = "code",
+                   keep_members=False) -> OracleResult:
+    """The search of :func:`detect` for one pass restricted to region
+    ``(level, i, j)`` and the regions below it, the region evaluated against
+    the lines ``cand`` (the voters of its parent; all lines for the root).
+    ``key`` is the region's quad-digit key.  Statistics cover levels >=
+    ``level``."""
+    lib = _load()
+    x, y = _as_i32(x), _as_i32(y)
+    cand = _as_i32(cand)
+    E = int(x.size)
+    h = lib.hough_oracle_detect_subtree(x.ctypes.data if E else None, y.ctypes.data if E else None,
+                                        E, int(W), int(H), int(threshold), int(max_depth),
+                                        VARIANTS[variant], int(pass_), int(level), int(i), int(j),
+                                        int(key), cand.ctypes.data if cand.size else None,
+                                        int(cand.size), MEMBERS[keep_members])
+    return _collect(lib, h, 1 << int(pass_))
+
+
+def member_digest(ids) -> int:
+    """The checksum of ``keep_members="digest"`` over one pass's voter list
+    (cells in key order, voters ascending): sum over positions t of
+    (t * A + B) * (id + 1) modulo 2^64."""
+    ids = np.asarray(ids, dtype=np.uint64)
+    t = np.arange(ids.size, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return int(((t * np.uint64(DIGEST_A) + np.uint64(DIGEST_B)) * (ids + np.uint64(1))).sum(dtype=np.uint64))
+
+
+def _collect(lib, h, passes) -> OracleResult:
     if not h:
         raise MemoryError("oracle out of memory")
     try:
@@ -218,7 +273,9 @@ def detect(x, y, W: int, H: int, threshold: int, max_depth: int = 0,
                 s = np.zeros(nl * 6, dtype=np.int64)
                 lib.hough_oracle_stats(h, p, s)
                 stats[p] = s.reshape(nl, 6)
-        return OracleResult(int(lib.hough_oracle_S(h)), nl - 1, cells, members, stats)
+        return OracleResult(int(lib.hough_oracle_S(h)), nl - 1, cells, members, stats,
+                            {p: int(lib.hough_oracle_member_digest(h, p)) for p in (0, 1)},
+                            {p: int(lib.hough_oracle_pass_members(h, p)) for p in (0, 1)})
     finally:
         lib.hough_oracle_free(h)
 

@@ -59,6 +59,11 @@ typedef struct {
     int64_t key, member_off;
 } or_cell;
 
+/* keep_members: 0 = counts only, 1 = every cell's voters stored,
+ * 2 = voters folded into a per-pass checksum instead of stored (see
+ * push_cell), for searches whose voter lists do not fit in host memory. */
+#define OR_MEMBERS_DIGEST 2
+
 typedef struct {
     int32_t status;
     int32_t n_levels;                               /* Dmax + 1 */
@@ -69,6 +74,8 @@ typedef struct {
     int32_t* members;
     int64_t n_members, cap_members;
     int32_t keep_members;
+    uint64_t member_digest[2];                      /* keep_members = 2 */
+    int64_t pass_members[2];                        /* voters reported per pass */
 } or_result;
 
 typedef struct {
@@ -133,8 +140,24 @@ static int votes_for_region(const or_walk* w, int l, int64_t i, int64_t j, int32
 
 /* ---- result storage ----------------------------------------------------- */
 
+/* Checksum of a pass's voters in the order a stored member list holds them
+ * (cells in visiting order, each cell's voters ascending): the sum over
+ * positions t of (t * A + B) * (id + 1), modulo 2^64.  It is a record of the
+ * output, not part of the method. */
+#define OR_DIGEST_A 0x9E3779B97F4A7C15ull
+#define OR_DIGEST_B 0x632BE59BD9B4E019ull
+
 static int push_cell(or_result* r, const or_cell* c, const int32_t* mem, int64_t n)
 {
+    const int p = c->pass & 1;
+    if (r->keep_members == OR_MEMBERS_DIGEST) {
+        uint64_t d = r->member_digest[p];
+        const uint64_t t0 = (uint64_t)r->pass_members[p];
+        for (int64_t t = 0; t < n; ++t)
+            d += ((t0 + (uint64_t)t) * OR_DIGEST_A + OR_DIGEST_B) * ((uint64_t)(uint32_t)mem[t] + 1u);
+        r->member_digest[p] = d;
+    }
+    r->pass_members[p] += n;
     if (r->n_cells == r->cap_cells) {
         int64_t cap = r->cap_cells ? 2 * r->cap_cells : 1024;
         or_cell* p = (or_cell*)realloc(r->cells, (size_t)cap * sizeof(or_cell));
@@ -143,9 +166,9 @@ static int push_cell(or_result* r, const or_cell* c, const int32_t* mem, int64_t
         r->cap_cells = cap;
     }
     r->cells[r->n_cells] = *c;
-    r->cells[r->n_cells].member_off = r->keep_members ? r->n_members : -1;
+    r->cells[r->n_cells].member_off = r->keep_members == 1 ? r->n_members : -1;
     r->n_cells++;
-    if (r->keep_members) {
+    if (r->keep_members == 1) {
         if (r->n_members + n > r->cap_members) {
             int64_t cap = r->cap_members ? r->cap_members : 4096;
             while (cap < r->n_members + n) cap *= 2;
@@ -281,6 +304,72 @@ or_result* hough_oracle_detect(const int32_t* x, const int32_t* y, int64_t E, in
     return r;
 }
 
+/* One subtree of one pass: region (level, i, j), evaluated against the lines
+ * cand[0..n_cand) -- in the search, the lines that voted for its parent (all
+ * lines for the root) -- and everything the search visits below it, in the
+ * same order and with the same arithmetic as hough_oracle_detect.  key is
+ * the region's quad-digit key; its cells' keys extend it.  Statistics cover
+ * levels >= level only.  A part of a large search can so be run (or timed)
+ * on its own. */
+or_result* hough_oracle_detect_subtree(const int32_t* x, const int32_t* y, int64_t E, int32_t W,
+                                       int32_t H, int32_t threshold, int32_t dmax, int32_t variant,
+                                       int32_t pass, int32_t level, int64_t i, int64_t j, int64_t key,
+                                       const int32_t* cand, int64_t n_cand, int32_t keep_members)
+{
+    or_result* r = (or_result*)calloc(1, sizeof(or_result));
+    if (!r) return NULL;
+    r->keep_members = keep_members;
+    if (W < 1 || H < 1 || E < 0 || threshold < 0 || (variant != 0 && variant != 1) ||
+        (pass != 0 && pass != 1) || (E > 0 && (!x || !y)) || E > INT32_MAX || n_cand < 0 ||
+        n_cand > E || (n_cand > 0 && !cand)) {
+        r->status = OR_EINVAL;
+        return r;
+    }
+    r->S = pow2_ceil(W > H ? W : H);
+    if (dmax == 0) dmax = log2_exact(r->S);
+    if (dmax < 0) dmax = 0;
+    if (dmax > OR_MAX_DEPTH || level < 0 || level > dmax || i < 0 || j < 0 ||
+        i >= ((int64_t)1 << level) || j >= ((int64_t)1 << level)) {
+        r->status = OR_EINVAL;
+        return r;
+    }
+    r->n_levels = dmax + 1;
+    for (int64_t k = 0; k < E; ++k)
+        if (x[k] < 0 || x[k] >= W || y[k] < 0 || y[k] >= H) {
+            r->status = OR_EINVAL;
+            return r;
+        }
+    for (int64_t t = 0; t < n_cand; ++t)
+        if (cand[t] < 0 || cand[t] >= E) {
+            r->status = OR_EINVAL;
+            return r;
+        }
+    int32_t** lists = (int32_t**)calloc((size_t)dmax + 1, sizeof(int32_t*));
+    int rc = lists ? OR_OK : OR_ENOMEM;
+    for (int l = level; rc == OR_OK && l <= dmax; ++l) {
+        lists[l] = (int32_t*)malloc((size_t)(n_cand > 0 ? n_cand : 1) * sizeof(int32_t));
+        if (!lists[l]) rc = OR_ENOMEM;
+    }
+    if (rc == OR_OK) {
+        or_walk w;
+        w.u = pass == 0 ? x : y;
+        w.v = pass == 0 ? y : x;
+        w.S = r->S;
+        w.dmax = dmax;
+        w.threshold = threshold;
+        w.variant = variant;
+        w.pass = pass;
+        w.level_list = lists;
+        w.res = r;
+        rc = evaluate(&w, level, i, j, cand, n_cand, key);
+    }
+    if (lists)
+        for (int l = 0; l <= dmax; ++l) free(lists[l]);
+    free(lists);
+    r->status = rc;
+    return r;
+}
+
 /* ---- accessors ---------------------------------------------------------- */
 
 int32_t hough_oracle_status(const or_result* r) { return r->status; }
@@ -288,6 +377,8 @@ int32_t hough_oracle_n_levels(const or_result* r) { return r->n_levels; }
 int64_t hough_oracle_S(const or_result* r) { return r->S; }
 int64_t hough_oracle_n_cells(const or_result* r) { return r->n_cells; }
 int64_t hough_oracle_n_members(const or_result* r) { return r->n_members; }
+uint64_t hough_oracle_member_digest(const or_result* r, int32_t pass) { return r->member_digest[pass & 1]; }
+int64_t hough_oracle_pass_members(const or_result* r, int32_t pass) { return r->pass_members[pass & 1]; }
 
 void hough_oracle_cells(const or_result* r, int32_t* pass, int32_t* i, int32_t* j,
                         int64_t* key, int32_t* votes, int64_t* member_off)
@@ -370,7 +461,7 @@ int32_t hough_oracle_circle(int64_t S, int32_t l, int64_t i, int64_t j, int64_t 
 int64_t hough_oracle_solution(const or_result* r, int32_t pass, int32_t threshold, int64_t E,
                               uint8_t* keep, uint8_t* plotted)
 {
-    if (!r->keep_members) return -1;
+    if (r->keep_members != 1) return -1;
     memset(plotted, 0, (size_t)E);
     int64_t kept = 0, c_out = 0;
     for (int64_t c = 0; c < r->n_cells; ++c) {
