@@ -174,12 +174,17 @@ def key_of(i: int, j: int, depth: int) -> int:
     return key
 
 
-def paper_dfs(x, y, W, H, T, dmax=0, pass_=0):
-    """The pseudo-code of Sec. 3 run literally: one linecode array per level
-    over all edge points, every visited region scanning every edge point and
-    skipping those whose parent code is 0000 or 1111, quads in the order NE,
-    NW, SW, SE, and solution() at the finest level (no removal).  Returns the
-    detected (i, j, votes, members) in visiting order and the total votes."""
+def recursive_search(x, y, W, H, T, dmax=0, pass_=0):
+    """The hierarchical search of Sec. 3 written as a recursion over sets,
+    from the method's definition rather than from its printed listing: a
+    region's voters are the lines of its candidate set (its parent's
+    voters; every line at the root) whose 4-bit code is neither 0000 nor
+    1111; a region with more than T voters recurses into its children in
+    quad order NE, NW, SW, SE, or, at the finest level, is reported with its
+    voters.  Sets are boolean masks over all lines; codes come from
+    ``codes`` (float64 corner geometry), not from the oracle.  Returns the
+    detected (i, j, votes, members) in visiting order and the total votes
+    of all evaluated regions."""
     S = side_pow2(W, H)
     if dmax == 0:
         dmax = S.bit_length() - 1
@@ -187,50 +192,22 @@ def paper_dfs(x, y, W, H, T, dmax=0, pass_=0):
     x = np.asarray(x, dtype=np.int64)
     y = np.asarray(y, dtype=np.int64)
     u, v = (x, y) if pass_ == 0 else (y, x)
-    E = x.size
-    code_at = {l: codes(u, v, S, l) for l in range(dmax + 1)}
-    linecode = np.zeros((dmax + 1, E), dtype=np.int64)
-    out, total = [], 0
-    # level 0
-    linecode[0] = code_at[0][0, 0]
-    vote0 = int(np.sum((linecode[0] != 0) & (linecode[0] != 15)))
-    total += vote0
-    if dmax == 0:
-        if vote0 > T:
-            mem = np.nonzero((linecode[0] != 0) & (linecode[0] != 15))[0]
-            out.append((0, 0, vote0, mem.astype(np.int32)))
-        return out, total
-    quad_e = [1, 0, 0, 1]
-    quad_n = [1, 1, 0, 0]
-    level = 1
-    quad = [0] * (dmax + 2)
-    pos = [(0, 0)] * (dmax + 2)      # (i, j) of the region open at each level
-    while level > 0:
-        quad[level] += 1
-        if quad[level] <= 4:
-            pi, pj = pos[level - 1]
-            q = quad[level] - 1
-            i, j = 2 * pi + quad_e[q], 2 * pj + quad_n[q]
-            pos[level] = (i, j)
-            vote = 0
-            for k in range(E):
-                pc = linecode[level - 1, k]
-                if pc != 0 and pc != 15:
-                    c = code_at[level][i, j, k]
-                    linecode[level, k] = c
-                    if c != 0 and c != 15:
-                        vote += 1
-                else:
-                    linecode[level, k] = 0
-            total += vote
-            if vote > T:
-                if level == dmax:
-                    lc = linecode[level]
-                    mem = np.nonzero((lc != 0) & (lc != 15))[0]
-                    out.append((i, j, vote, mem.astype(np.int32)))
-                else:
-                    level += 1
-                    quad[level] = 0
-        else:
-            level -= 1
-    return out, total
+    cross = {l: crosses_code(u, v, S, l) for l in range(dmax + 1)}
+    found = []
+    total = 0
+
+    def visit(level, i, j, cand):
+        nonlocal total
+        voters = cand & cross[level][i, j]
+        n = int(voters.sum())
+        total += n
+        if n <= T:
+            return
+        if level == dmax:
+            found.append((i, j, n, np.nonzero(voters)[0].astype(np.int32)))
+            return
+        for e, nn in ((1, 1), (0, 1), (0, 0), (1, 0)):   # NE, NW, SW, SE
+            visit(level + 1, 2 * i + e, 2 * j + nn, voters)
+
+    visit(0, 0, 0, np.ones(x.size, dtype=bool))
+    return found, total

@@ -13,8 +13,9 @@
   variants, square and non-square tiny images and depth overrides.
 * Hand closed form: a horizontal image line y = c (pass 0) in the two
   columns next to m = 0.
-* The pseudo-code of Sec. 3 run literally (per-level linecode arrays over
-  all edge points) visits and detects the same cells.
+* The search of Sec. 3 written as a recursion over candidate sets (float64
+  geometry, no oracle code) visits and detects the same cells in the same
+  order, with the same total votes.
 * Invariants and metamorphic relations: child voters within parent voters;
   a crossing line crosses 1..3 children (code variant); circle voters contain code voters;
   point permutation, duplication with T' = 2T + 1, and the x <-> y swap.
@@ -238,16 +239,16 @@ def test_horizontal_line_closed_form(orc, c):
 
 
 # --------------------------------------------------------------------------
-# the paper's pseudo-code, literally
+# the search as a recursion over candidate sets
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_paper_pseudocode_same_cells(orc, seed):
+def test_recursive_search_same_cells(orc, seed):
     W, H = (16, 16) if seed % 2 == 0 else (11, 14)
     x, y = points(tiny_image(700 + seed, W, H, 0.12))
     for T in (0, 2, 4, 7):
         for p in (0, 1):
-            out, total = brute.paper_dfs(x, y, W, H, T, 0, p)
+            out, total = brute.recursive_search(x, y, W, H, T, 0, p)
             res = orc.detect(x, y, W, H, T, 0, "code", 1 << p)
             assert len(out) == len(res.cells)
             for c, (i, j, vv, mem) in enumerate(out):
