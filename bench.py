@@ -29,12 +29,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def id_list_alg_bytes(stats_by_pass, detected_votes_by_pass, E):
-    """Algorithmic bytes of an id-list design that gathers coordinates: per
-    pass 8 E + sum_{1<=l<D} 12 L_l + sum_{1<=l<=D} 4 L_l, with L_l the summed
-    votes of the regions split at level l and L_D those of the detected
-    cells.  Reported for comparison only; this library's lists carry the
-    packed point, see ``kernel_bytes``."""
+def algorithmic_bytes(stats_by_pass, detected_votes_by_pass, E):
+    """What the method must move per step, independent of this design: per
+    pass 8 E (the points) + sum_{1<=l<D} 12 L_l (a 4-byte id and two 4-byte
+    coordinates per candidate test) + sum_{1<=l<=D} 4 L_l (a 4-byte id per
+    kept vote), with L_l the summed votes of the regions split at level l and
+    L_D those of the detected cells.  The points are cache resident, so the
+    HBM traffic measured can sit below it."""
     total = 0
     for p, st in stats_by_pass.items():
         D = len(st) - 1
@@ -65,11 +66,12 @@ def kernel_source_digest():
     return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per step of `kernel` from the committed rocprofv3 summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
-    kernel code has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_write_seg1024_hbm_traffic.md")
+def measured_traffic(workload):
+    """HBM bytes per step of the two list kernels (FETCH_SIZE and WRITE_SIZE
+    from rocprofv3, scaled by a plain copy) from the committed summary for
+    this workload, or None when the kernel code has changed since the
+    counters were taken (or there is no summary)."""
+    path = os.path.join(ROOT, "profiles", f"list_kernels_{workload}_hbm_traffic.md")
     try:
         text = open(path).read()
         sha = kernel_source_digest()
@@ -82,26 +84,97 @@ def measured_traffic(kernel):
             fields[k.strip()] = v.strip()
     if fields.get("kernel_source_sha256") != sha:
         return None
-    v = fields.get(f"{kernel}_traffic_bytes_per_step")
+    v = fields.get("traffic_bytes_per_step")
     return float(v) if v else None
 
 
-def cpu_baseline(image, W, H, T, depth, budget_s=12.0):
+def _quad_key(i, j, level):
+    """Quad-digit key of region (level, i, j): NE=0, NW=1, SW=2, SE=3 from level 1 down."""
+    k = 0
+    for b in range(level - 1, -1, -1):
+        e, n = (i >> b) & 1, (j >> b) & 1
+        k = k * 4 + ((n ^ 1) << 1 | (e ^ n))
+    return k
+
+
+_CPU = {}
+
+
+def _cpu_init(x, y, W, H, T, D, k, deadline):
+    _CPU.update(x=x, y=y, W=W, H=H, T=T, D=D, k=k, deadline=deadline)
+
+
+def _cpu_subtree(task):
     import oracle
-    x, y = oracle.edge_points(image)
-    runs, t_total, tests = 0, 0.0, 0
-    while t_total < budget_s or runs == 0:
+    g = _CPU
+    if time.time() > g["deadline"]:
+        return 0
+    p, i, j, key, cand = task
+    r = oracle.detect_subtree(g["x"], g["y"], g["W"], g["H"], g["T"], g["D"], p, g["k"], i, j, key, cand,
+                              keep_members=False)
+    return int(r.stats[p][:, 4].sum())
+
+
+def cpu_baseline(w, budget_s=10.0, split=4):
+    """The CPU oracle (plain C, depth-first search) on a bounded sample of
+    the benchmark image: the subtrees of level `split` of both passes, each
+    searched from its parent's voters, in a seeded random order, as many as
+    finish in `budget_s` -- once on one thread and once over the host's
+    cores (a process pool, one subtree per task).  Rates are code tests per
+    second over the subtrees that finished.  Runs before the GPU is touched
+    (the pool forks)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    x, y = oracle.edge_points(w.image)
+    W, H, T, D = w.width, w.height, w.threshold, w.max_depth
+    tasks = []
+    for p in (0, 1):
+        level = {(0, 0): np.arange(len(x), dtype=np.int32)}
+        for lev in range(1, split + 1):
+            kids = {}
+            for (i, j), v in sorted(level.items()):
+                if len(v) > T:
+                    for e in (0, 1):
+                        for n in (0, 1):
+                            kids[(2 * i + e, 2 * j + n)] = v
+            if lev == split:
+                tasks += [(p, i, j, _quad_key(i, j, split), v) for (i, j), v in sorted(kids.items())]
+            else:
+                level = {c: oracle.region_voters(x, y, W, H, p, lev, c[0], c[1]) for c in kids}
+    order = np.random.default_rng(0).permutation(len(tasks))
+    tasks = [tasks[k] for k in order]
+
+    _cpu_init(x, y, W, H, T, D, split, float("inf"))
+    t0 = time.perf_counter()
+    tests1, n1 = 0, 0
+    while n1 < len(tasks) and (n1 == 0 or time.perf_counter() - t0 < budget_s):
+        tests1 += _cpu_subtree(tasks[n1])
+        n1 += 1
+    t1 = time.perf_counter() - t0
+
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(cores, initializer=_cpu_init,
+                                     initargs=(x, y, W, H, T, D, split, time.time() + budget_s)) as pool:
         t0 = time.perf_counter()
-        r = oracle.detect(x, y, W, H, T, depth)
-        t_total += time.perf_counter() - t0
-        tests += r.code_tests()
-        runs += 1
-        if runs >= 50:
-            break
-    return {"value": tests / t_total, "unit": "code tests/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full benchmark image (both passes), {runs} run(s), "
-                      f"{t_total:.1f} s single-threaded C oracle",
-            "seconds_per_image": t_total / runs}
+        done = [v for v in pool.imap_unordered(_cpu_subtree, tasks, chunksize=1)]
+        tn = time.perf_counter() - t0
+    testsn = sum(done)
+    nn = sum(1 for v in done if v)
+    model = ""
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": testsn / tn, "unit": "code tests/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nn} of the {len(tasks)} level-{split} subtrees of the benchmark image (both passes), "
+                      f"each searched from its parent's voters by the C oracle, {cores} processes for "
+                      f"{tn:.1f} s; the same sample order on one thread: {n1} subtrees in {t1:.1f} s",
+            "single_thread": {"value": tests1 / t1, "unit": "code tests/s", "cores": 1, "subtrees": n1,
+                              "seconds": t1},
+            "host_cpu": model, "host_threads": os.cpu_count()}
 
 
 def bench_batched(seed, reps=3):
@@ -264,61 +337,18 @@ def bench_solution(seed, reps=5):
     return {"seg1024": one, "batch512": batch}
 
 
-def bench_large(seed, reps=3):
-    """The 4096x4096 image (128 segments of length U[500, 4000], 1% noise,
-    T = 300, depth 12, both passes, voters kept): time per image and the
-    per-level footprint of its level lists."""
-    import numpy as np
-    import torch
-
-    import synth
-    from paper_1007_0547_amd import HoughHier
-
-    dev = torch.device("cuda:0")
-    w = synth.workload("seg4096", seed)
-    img = torch.from_numpy(w.image).to(dev)
-    ctx = HoughHier(threshold=w.threshold, max_depth=w.max_depth, membership=True, device=0,
-                    stream=torch.cuda.current_stream(dev))
-    ctx.detect(image=img, width=w.width, height=w.height).free()   # learns the arena sizes
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ctx.detect(image=img, width=w.width, height=w.height).free()
-    torch.cuda.synchronize(dev)
-    dt = (time.perf_counter() - t0) / reps
-    ctx_t = HoughHier(threshold=w.threshold, max_depth=w.max_depth, membership=True, device=0,
-                      stream=torch.cuda.current_stream(dev), timing=True)
-    ctx_t.detect(image=img, width=w.width, height=w.height).free()
-    rt = ctx_t.detect(image=img, width=w.width, height=w.height)
-    kt = rt.timing()
-    rt.free()
-    ctx_t.close()
-    kb = kernel_bytes(kt, 4)
-    r = ctx.detect(image=img, width=w.width, height=w.height)
-    st = [r.stats(p) for p in (0, 1)]
-    info = r.info
+def level_footprint(stats, depth, entry_bytes=4):
+    """Bytes of each level's lists and tables (both passes): the level's half
+    of the arena holds the region table (24 B), task table (8 B per task of
+    1024 entries) and child votes (16 B) per region, and the list."""
     levels = []
-    for l in range(info["depth"]):
-        regions = int(st[0]["split"][l] + st[1]["split"][l])
-        entries = int(st[0]["entries"][l] + st[1]["entries"][l])
-        # a level's half: region table (24 B), code constants (16 B) and child
-        # votes (16 B) per region, the tile map, and the list (4 B per entry)
+    for l in range(depth):
+        regions = int(stats[0]["split"][l] + stats[1]["split"][l])
+        entries = int(stats[0]["entries"][l] + stats[1]["entries"][l])
+        tasks = entries // 1024 + regions
         levels.append({"level": l, "regions": regions, "list_entries": entries,
-                       "bytes": regions * 56 + (entries // 2048 + 1) * 4 + entries * 4})
-    out = {"workload": f"seg4096: 4096x4096 binary image, seed {seed}, 128 segments, 1% noise, T={w.threshold}, "
-                       f"depth {info['depth']}, both passes, voters kept on device",
-           "edge_points": info["n_points"], "cells": sum(info["n_cells"]), "code_tests": info["code_tests"],
-           "ms_per_image": dt * 1e3, "code_tests_per_s": info["code_tests"] / dt,
-           "member_entries": info["member_slots"],
-           "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"], "decide": kt["decide_ms"],
-                         "extract": kt["extract_ms"]},
-           "roofline": {k: {"alg_bytes": kb[k], "GB/s": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9,
-                            "frac": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
-                        for k in ("count", "write")},
-           "level_footprint": levels}
-    r.free()
-    ctx.close()
-    return out
+                       "bytes": regions * 40 + tasks * 8 + entries * entry_bytes})
+    return levels
 
 
 def bench_sweep(seed, reps=20):
@@ -528,22 +558,103 @@ def bench_serving(seed, seconds, pool_size=128):
     return out
 
 
+def bench_single(name, seed, steps, warmup, variant="code", wide=False, kernel_steps=10):
+    """One image of workload `name` per step (edge staging from the binary
+    image resident in HBM, both passes to the finest level, voters kept on
+    the device): wall time per step over `steps` steps with no per-launch
+    events, then the count and compaction kernels' durations from HIP events
+    on the library's stream over `kernel_steps` more steps, and the sizes the
+    byte models need."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(name, seed)
+    img = torch.from_numpy(w.image).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def make(timing):
+        return HoughHier(threshold=w.threshold, max_depth=w.max_depth, variant=variant, membership=True,
+                         device=0, stream=stream, wide_compare=wide, timing=timing)
+
+    def step(c):
+        return c.detect(image=img, width=w.width, height=w.height)
+
+    ctx = make(False)
+    for _ in range(warmup):
+        step(ctx).free()
+    torch.cuda.synchronize(dev)
+    lat = []
+    info = None
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = step(ctx)
+        lat.append(time.perf_counter() - t0)
+        info = r.info
+        r.free()
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t_start
+    ctx.close()
+
+    ctx_t = make(True)
+    for _ in range(2):
+        step(ctx_t).free()
+    acc = {}
+    for _ in range(kernel_steps):
+        r = step(ctx_t)
+        for k, v in r.timing().items():
+            acc[k] = acc.get(k, 0) + v
+        r.free()
+    kt = {k: v / kernel_steps for k, v in acc.items()}
+    r = step(ctx_t)
+    stats = {p: r.stats(p) for p in (0, 1)}
+    det_votes = {p: int(r.cells(p)["votes"].astype(np.int64).sum()) for p in (0, 1)}
+    r.free()
+    ctx_t.close()
+    E = int(info["n_points"])
+    return {"w": w, "info": info, "steps": steps, "elapsed": elapsed, "ms_per_step": elapsed / steps * 1e3,
+            "lat": lat, "kt": kt, "stats": stats, "det_votes": det_votes, "E": E,
+            "code_tests": int(info["code_tests"]),
+            "alg_bytes": algorithmic_bytes(stats, det_votes, E)}
+
+
+def single_summary(b):
+    """The extra-block form of a bench_single run."""
+    kt = b["kt"]
+    pass_ms = kt["count_ms"] + kt["write_ms"]
+    return {"workload": f"{b['w'].name}: {b['w'].width}x{b['w'].height}, T={b['w'].threshold}, "
+                        f"depth {b['info']['depth']}, both passes, voters kept on device",
+            "edge_points": b["E"], "cells": sum(b["info"]["n_cells"]), "code_tests": b["code_tests"],
+            "ms_per_image": b["ms_per_step"], "images_per_s": 1e3 / b["ms_per_step"],
+            "code_tests_per_s": b["code_tests"] / (b["ms_per_step"] / 1e3),
+            "compare_bits": b["info"]["compare_bits"],
+            "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"], "decide": kt["decide_ms"],
+                          "extract": kt["extract_ms"]},
+            "vote_pass": {"alg_bytes": b["alg_bytes"], "ms": pass_ms,
+                          "GB/s": b["alg_bytes"] / (pass_ms / 1e3) / 1e9,
+                          "frac": b["alg_bytes"] / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="seg1024")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="seg4096", choices=["seg4096", "seg1024", "line256"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", default="code", choices=["code", "circle"])
     ap.add_argument("--wide", action="store_true", help="64-bit corner compares")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-image batch comparison")
-    ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 image")
     ap.add_argument("--no-sweep", action="store_true", help="skip the code/circle size sweep")
     ap.add_argument("--no-gray", action="store_true", help="skip the Sobel front-end image")
     ap.add_argument("--no-solution", action="store_true", help="skip solution() with point removal")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window per rate of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
@@ -555,7 +666,13 @@ def main():
               "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import synth
+
+    # the CPU baseline forks a process pool, so it runs before the GPU is touched
+    cpu = None
+    if not args.no_cpu_baseline and not args.calibrate_copy:
+        cpu = cpu_baseline(synth.workload(args.workload, args.seed))
+
     import torch
 
     if args.calibrate_copy:
@@ -568,116 +685,71 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
         return
 
-    import synth
-    from paper_1007_0547_amd import HoughHier
-
-    dev = torch.device("cuda:0")
-    w = synth.workload(args.workload, args.seed)
-    img = torch.from_numpy(w.image).to(dev)
-    stream = torch.cuda.current_stream(dev)
-
-    def make(timing):
-        return HoughHier(threshold=w.threshold, max_depth=w.max_depth, variant=args.variant,
-                         membership=True, device=0, stream=stream, wide_compare=args.wide,
-                         timing=timing)
-
-    ctx = make(False)
-
-    def step(c):
-        return c.detect(image=img, width=w.width, height=w.height)
-
-    for _ in range(args.warmup):
-        step(ctx).free()
-    torch.cuda.synchronize(dev)
-
-    lat = []
-    info = None
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        r = step(ctx)
-        lat.append(time.perf_counter() - t0)
-        info = r.info
-        r.free()
-    torch.cuda.synchronize(dev)
-    elapsed = time.perf_counter() - t_start
-
-    # kernel durations: the same steps again with HIP events around the launches
-    ctx_t = make(True)
-    for _ in range(2):
-        step(ctx_t).free()
-    kt_steps = max(1, min(args.steps, 10))
-    acc = {}
-    for _ in range(kt_steps):
-        r = step(ctx_t)
-        for k, v in r.timing().items():
-            acc[k] = acc.get(k, 0) + v
-        r.free()
-    kt = {k: v / kt_steps for k, v in acc.items()}
-    r = step(ctx_t)
-    stats = {p: r.stats(p) for p in (0, 1)}
-    det_votes = {p: int(r.cells(p)["votes"].astype(np.int64).sum()) for p in (0, 1)}
-    entry_bytes = 4
-    r.free()
-    ctx_t.close()
-
-    E = int(info["n_points"])
-    code_tests = int(info["code_tests"])
-    kb = kernel_bytes(kt, entry_bytes)
-    kms = {"count": kt["count_ms"], "write": kt["write_ms"]}
-    dom = max(kms, key=kms.get)
-    achieved = kb[dom] / (kms[dom] / 1e3) / 1e9 if kms[dom] > 0 else 0.0
-
-    ms_per_step = elapsed / args.steps * 1e3
+    b = bench_single(args.workload, args.seed, args.steps, args.warmup, args.variant, args.wide)
+    info, kt, w = b["info"], b["kt"], b["w"]
+    pass_ms = kt["count_ms"] + kt["write_ms"]
+    achieved = b["alg_bytes"] / (pass_ms / 1e3) / 1e9
+    kb = kernel_bytes(kt, 4)
+    import numpy as np
+    bits = info["compare_bits"]
+    exact = (f"int32 corner compares, exact because S*2^depth = 2^{info['depth'] + int(info['side_pow2']).bit_length() - 1}"
+             f" <= 2^28 keeps every scaled corner value below 2^31" if bits == 32 else
+             "int64 corner compares")
     out = {
         "metric": "line-region code tests/s (plain, one image per call)",
-        "value": code_tests * args.steps / elapsed,
+        "value": b["code_tests"] * b["steps"] / b["elapsed"],
         "unit": "code tests/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": b["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"int{info['compare_bits']}",
+        "dtype": f"int{bits}",
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.width}x{w.height} binary image, seed {args.seed}, "
-                        f"T={w.threshold}, depth {info['depth']}, both passes, "
-                        f"{args.variant} variant, voters kept on device",
-            "E": E, "cells": sum(info["n_cells"]), "code_tests_per_image": code_tests,
+                        f"T={w.threshold}, depth {info['depth']}, both passes, {args.variant} variant, "
+                        f"voters kept on device",
+            "E": b["E"], "cells": sum(info["n_cells"]), "code_tests_per_image": b["code_tests"],
+            "compares": exact,
         },
-        "images_per_s": args.steps / elapsed,
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "images_per_s": b["steps"] / b["elapsed"],
+        "latency_ms": {"p50": float(np.percentile(b["lat"], 50) * 1e3),
+                       "p99": float(np.percentile(b["lat"], 99) * 1e3)},
+        "level_footprint": level_footprint(b["stats"], info["depth"]),
         "kernel_ms_per_step": {"count": kt["count_ms"], "write": kt["write_ms"],
                                "decide": kt["decide_ms"], "extract": kt["extract_ms"],
                                "device_total_with_events": kt["total_ms"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_{dom}"),
-                     "alg_bytes_per_step": kb[dom],
-                     "other": {f"k_{k}": {"alg_bytes_per_step": kb[k], "ms_per_step": kms[k],
-                                          "GB/s": kb[k] / (kms[k] / 1e3) / 1e9 if kms[k] > 0 else 0.0}
-                               for k in kms},
-                     "id_list_design_alg_bytes_per_step": id_list_alg_bytes(stats, det_votes, E)},
+        "roofline": {"bound": "hbm", "kernel": "k_count+k_write (the vote and compaction pass, every level)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload),
+                     "alg_bytes_per_step": b["alg_bytes"], "ms_per_step": pass_ms,
+                     "other": {"entry_bytes_model": {
+                         f"k_{k}": {"bytes_per_step": kb[k], "ms_per_step": kt[f"{k}_ms"],
+                                    "GB/s": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9 if kt[f"{k}_ms"] > 0 else 0.0}
+                         for k in ("count", "write")}}},
     }
-    ctx.close()
-    if not args.no_batched:
-        out["batch512"] = bench_batched(args.seed)
-    if not args.no_large:
-        out["seg4096"] = bench_large(args.seed)
-    if not args.no_sweep:
-        out["size_sweep"] = bench_sweep(args.seed)
-    if not args.no_gray:
-        out["gray1024"] = bench_gray(args.seed)
-    if not args.no_solution:
-        out["solution"] = bench_solution(args.seed)
-    if args.serve_seconds > 0:
-        out["serving"] = bench_serving(args.seed, args.serve_seconds)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w.image, w.width, w.height, w.threshold, w.max_depth)
+    if not args.no_extras:
+        if args.workload != "seg1024":
+            out["seg1024"] = single_summary(bench_single("seg1024", args.seed, 30, 3))
+        out["line256"] = single_summary(bench_single("line256", args.seed, 100, 10))
+        if bits == 32:
+            out["wide_compares"] = single_summary(bench_single(args.workload, args.seed, 5, 2, wide=True))
+        if not args.no_batched:
+            out["batch512"] = bench_batched(args.seed)
+        if not args.no_sweep:
+            out["size_sweep"] = bench_sweep(args.seed)
+        if not args.no_gray:
+            out["gray1024"] = bench_gray(args.seed)
+        if not args.no_solution:
+            out["solution"] = bench_solution(args.seed)
+        if args.serve_seconds > 0:
+            out["serving"] = bench_serving(args.seed, args.serve_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

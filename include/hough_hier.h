@@ -86,6 +86,15 @@ typedef enum {
                                     compares are provably exact                         */
 #define HH_FLAG_TIMING 2         /* record HIP events around every kernel launch; read them
                                     with hough_hier_result_timing()                    */
+#define HH_FLAG_GRAPH 4          /* with a caller arena (hh_config.arena), a stream (not
+                                    the null stream) and device-resident
+                                    inputs: capture a call's level launches (arena
+                                    clear, root setup, every level's four launches and
+                                    the copy of the level records) into a HIP graph, and
+                                    replay it for the next call whose sizes, parameters
+                                    and memory are the same (its addresses are then the
+                                    same too); otherwise the launches run one by one.
+                                    Results do not depend on it.  Not with TIMING.     */
 
 /* Limits: max(W, H) <= 16384, depth <= 15 and S * 2^depth <= 2^28 (keeps every
  * scaled corner value inside 31 bits and the circle test inside 63 bits);
@@ -110,6 +119,27 @@ typedef struct {
                                  (0: 64 MiB); the other parts start in proportion.  A
                                  call whose levels outgrow the arena continues in a
                                  larger one, and later calls keep the larger sizes.   */
+    void* arena;              /* caller-owned device memory (e.g. a torch tensor's) for
+                                 every detection call on this context, or NULL (the
+                                 library allocates from its own pool).  A call carves
+                                 its staged inputs, descriptors and level arena from it
+                                 front to back and allocates no device memory; the
+                                 level arena's parts are split in the proportions the
+                                 context has learnt.  When a level does not fit, the
+                                 call reruns once with the parts re-split by the sizes
+                                 it measured, then fails with HH_ECAPACITY (nothing is
+                                 grouped or resumed in a larger arena).  The results of
+                                 a call point into the arena: free them before the
+                                 next call (that call fails with HH_EBUSY otherwise).
+                                 The memory stays the caller's; it must stay valid
+                                 while results of the context live.  A context with an
+                                 arena cannot serve.  256-byte aligned.                */
+    uint64_t arena_bytes;     /* size of arena in bytes                                 */
+    uint64_t hbm_budget_bytes;/* device-memory budget of one call's level arena (a
+                                 batch beyond it runs in groups) and the admission
+                                 budget of serving (sum of the predicted footprints of
+                                 the requests in flight); 0: arena_limit_mib if set,
+                                 else 35% of the device memory                         */
 } hh_config;
 
 typedef struct {
@@ -190,7 +220,47 @@ typedef struct {
     double queue_ms;          /* served requests: submission to the start of its batch */
     double service_ms;        /* served requests: batch start to cells and statistics
                                  on the host                                           */
+    int32_t graph_replayed;   /* HH_FLAG_GRAPH: 1 if the call replayed the graph captured
+                                 by an earlier call, 0 if it captured or ran launches  */
+    int32_t reserved;
 } hh_timing;
+
+/* Launch shape of the two list kernels of every level (the count pass and
+ * the compaction pass).  A level's list is cut into tasks, each a run of at
+ * most task_steps * 512 entries of one region's list; the kernels run a
+ * resident grid (wg_per_cu workgroups of 256 threads per compute unit) whose
+ * wavefronts take tasks until the level's are all taken: from a fixed share
+ * (queue_batch = 0: wavefront w takes tasks w, w + W, w + 2W, ... of the W
+ * wavefronts), or from the level's device work queue, an atomic head that
+ * hands out queue_batch consecutive tasks at a time.  Results do not depend
+ * on the launch shape; only the time does. */
+typedef struct {
+    int32_t task_steps;       /* 512-entry steps per task, 1..64 (0: default 4)       */
+    int32_t queue_batch;      /* 0: fixed share; 1..1024: tasks per take from the queue */
+    int32_t wg_per_cu;        /* resident workgroups per compute unit, 0: as many as fit */
+    int32_t reserved;
+} hh_launch;
+
+/* Set or read the launch shape of the list kernels on ctx (applies to the
+ * calls that start afterwards; serving lanes take it when they start).
+ * Errors: HH_EINVAL (NULL arguments, a field out of range). */
+HH_API hh_status hough_hier_set_launch(hh_ctx* ctx, const hh_launch* launch);
+HH_API hh_status hough_hier_get_launch(const hh_ctx* ctx, hh_launch* launch);
+
+/* Pick the launch shape for calls like inputs[0 .. n) (the same kind, count,
+ * sizes, depth and context settings) and set it on ctx.  The choice is read
+ * from a cache file keyed by the device (architecture, compute units, HIP
+ * runtime version) and the shape of the call, or, for a new key, made by
+ * running the call once per candidate shape (task_steps 1, 2, 4, 8, 16 with
+ * wg_per_cu 0 or 4, fixed shares) -- once to warm up, then twice timed, the
+ * fastest kept -- and written to the cache.  The cache file is
+ * $HH_TUNE_CACHE, else $HOME/.cache/hough_hier_tune.json (a JSON object of
+ * key -> shape and milliseconds).  Inputs are borrowed for the call; the
+ * results of the timed runs are freed.  *from_cache (may be NULL) is 1 when
+ * the cache had the key.
+ * Errors: as hough_hier_detect_batch. */
+HH_API hh_status hough_hier_autotune(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_launch* chosen,
+                                     int32_t* from_cache);
 
 /* Create a context on cfg->device.  Checks the device is a gfx950.
  * Errors: HH_EINVAL (cfg or out NULL, bad defaults), HH_EDEVICE. */
@@ -230,24 +300,31 @@ HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, in
 
 /* ---- Serving: continuous batching of requests on one context.
  *
- * hough_hier_serve_start starts `lanes` worker lanes, each with its own HIP
- * stream and arena (default-priority streams).  A free lane takes the
- * pending requests in arrival order, as many as fit its admission budget
- * (at most max_batch requests and max_batch_pixels image pixels, or points
- * for point lists; the first request is always admitted), runs them as one
- * batch (hough_hier_detect_batch), copies each result's cells and
- * statistics to the host and completes the tickets.  Requests that arrive
- * while batches run are admitted by the next free lane, so batches of
+ * hough_hier_serve_start starts `lanes` worker lanes (slots), each with its
+ * own HIP stream and arena (default-priority streams).  A free lane takes the
+ * pending requests in arrival order, as many as fit (at most max_batch
+ * requests, at most max_batch_pixels image pixels if that is not 0, and --
+ * the admission by device memory -- while the predicted footprints of the
+ * batches running on all lanes plus this one stay within the context's
+ * budget: hbm_budget_bytes, else arena_limit_mib, else 35% of the device
+ * memory; a batch alone on the device always runs), runs them as one batch
+ * (hough_hier_detect_batch), copies each result's cells and statistics to
+ * the host and completes the tickets.  A request's footprint is predicted as
+ * beta * E * 2^depth bytes, E its edge points (counted at submission for a
+ * host binary image or a point list, else its pixels times the edge density
+ * seen so far), beta a running average over completed batches of their
+ * measured footprint per unit.  Requests that arrive while batches run are
+ * admitted by the next lane that is free once memory allows, so batches of
  * different lanes overlap on the device.  A request's result is identical to
- * what hough_hier_detect returns for the same input.  The lanes share the
- * context's arena limit equally, and a served result holds exact copies of
- * its cells and voters only (the arena goes to the lane's next batch).  The
- * context stays usable for plain calls.  Served results carry queue_ms and service_ms in
- * hh_timing. */
+ * what hough_hier_detect returns for the same input.  A served result holds
+ * exact copies of its cells and voters only (the arena goes to the lane's
+ * next batch).  The context stays usable for plain calls.  Served results
+ * carry queue_ms and service_ms in hh_timing. */
 typedef struct {
     int32_t lanes;            /* concurrent batches, 1..8 (0: 2)                       */
     int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 32)           */
-    int64_t max_batch_pixels; /* admission budget of one batch (0: 2^24)               */
+    int64_t max_batch_pixels; /* most image pixels (points of lists) in a batch, 0: no
+                                 limit besides the memory budget                        */
     int32_t queue_capacity;   /* most tickets not yet claimed by poll (0: 4096)        */
     int32_t reserved;
 } hh_serve_config;
@@ -349,6 +426,12 @@ HH_API hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_
  * run on res), HH_ENOMEM, HH_EDEVICE. */
 HH_API hh_status hough_hier_result_solution_image(hh_result* res, uint8_t* image, int64_t row_stride,
                                                   int32_t on_device);
+
+/* Text of the last error recorded by a call on res (its accessors, solution
+ * and image calls).  Results of a serving context record their errors on the
+ * serving lane that made them, not on the context passed to poll, so read
+ * them here (never NULL; empty if none). */
+HH_API const char* hough_hier_result_last_error(const hh_result* res);
 
 /* Release a result (its device memory returns to the context, where the
  * context's next call may reuse it: finish any work that reads the result's

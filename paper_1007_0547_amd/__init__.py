@@ -55,7 +55,8 @@ class _Config(C.Structure):
     _fields_ = [("threshold", C.c_int32), ("max_depth", C.c_int32), ("passes", C.c_uint32),
                 ("variant", C.c_int32), ("membership", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("flags", C.c_int32), ("arena_limit_mib", C.c_int32),
-                ("arena_hint", C.c_uint64)]
+                ("arena_hint", C.c_uint64), ("arena", C.c_void_p), ("arena_bytes", C.c_uint64),
+                ("hbm_budget_bytes", C.c_uint64)]
 
 
 class _Input(C.Structure):
@@ -78,12 +79,18 @@ class _Timing(C.Structure):
                 ("vote_ms", C.c_double), ("decide_ms", C.c_double), ("extract_ms", C.c_double),
                 ("total_ms", C.c_double), ("vote_entries", C.c_int64), ("vote_written", C.c_int64),
                 ("count_ms", C.c_double), ("write_ms", C.c_double), ("groups", C.c_int32),
-                ("resumes", C.c_int32), ("queue_ms", C.c_double), ("service_ms", C.c_double)]
+                ("resumes", C.c_int32), ("queue_ms", C.c_double), ("service_ms", C.c_double),
+                ("graph_replayed", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _ServeConfig(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("max_batch_pixels", C.c_int64),
                 ("queue_capacity", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Launch(C.Structure):
+    _fields_ = [("task_steps", C.c_int32), ("queue_batch", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class _Solution(C.Structure):
@@ -97,6 +104,7 @@ STATS_DTYPE = np.dtype([("evaluated", np.int64), ("votes", np.int64), ("split", 
                         ("detected", np.int64), ("code_tests", np.int64), ("entries", np.int64)])
 assert CELL_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 48
 
+MAX_DEPTH = 15          # HH_MAX_DEPTH
 _p = C.c_void_p
 _lib.hough_hier_create.restype = C.c_int
 _lib.hough_hier_create.argtypes = [C.POINTER(_Config), C.POINTER(_p)]
@@ -133,6 +141,14 @@ _lib.hough_hier_result_solution.restype = C.c_int
 _lib.hough_hier_result_solution.argtypes = [_p, C.c_int32, C.c_int32, C.POINTER(_Solution)]
 _lib.hough_hier_result_solution_image.restype = C.c_int
 _lib.hough_hier_result_solution_image.argtypes = [_p, C.c_void_p, C.c_int64, C.c_int32]
+_lib.hough_hier_set_launch.restype = C.c_int
+_lib.hough_hier_set_launch.argtypes = [_p, C.POINTER(_Launch)]
+_lib.hough_hier_autotune.restype = C.c_int
+_lib.hough_hier_autotune.argtypes = [_p, C.POINTER(_Input), C.c_int32, C.POINTER(_Launch), C.POINTER(C.c_int32)]
+_lib.hough_hier_get_launch.restype = C.c_int
+_lib.hough_hier_get_launch.argtypes = [_p, C.POINTER(_Launch)]
+_lib.hough_hier_result_last_error.restype = C.c_char_p
+_lib.hough_hier_result_last_error.argtypes = [_p]
 _lib.hough_hier_result_free.restype = None
 _lib.hough_hier_result_free.argtypes = [_p]
 
@@ -165,7 +181,7 @@ class Result:
 
     def _check(self, s):
         if s != 0:
-            raise HHError(s, self._ctx.last_error())
+            raise HHError(s, (_lib.hough_hier_result_last_error(self._h) or b"").decode())
 
     def timing(self) -> dict:
         """Kernel timings of the call (contexts created with ``timing=True``)."""
@@ -282,7 +298,8 @@ class HoughHier:
     def __init__(self, threshold: int = 0, max_depth: int = 0, passes: int = 3,
                  variant: str = "code", membership: bool = True, device: int = 0,
                  stream=None, wide_compare: bool = False, timing: bool = False,
-                 arena_hint: int = 0, arena_limit_mib: int = 0):
+                 arena_hint: int = 0, arena_limit_mib: int = 0, arena=None, hbm_budget_bytes: int = 0,
+                 graph: bool = False):
         cfg = _Config()
         cfg.threshold = int(threshold)
         cfg.max_depth = int(max_depth)
@@ -291,9 +308,15 @@ class HoughHier:
         cfg.membership = 1 if membership else 0
         cfg.device = int(device)
         cfg.stream = self._stream_handle(stream)
-        cfg.flags = (1 if wide_compare else 0) | (2 if timing else 0)
+        cfg.flags = (1 if wide_compare else 0) | (2 if timing else 0) | (4 if graph else 0)
         cfg.arena_hint = int(arena_hint)
         cfg.arena_limit_mib = int(arena_limit_mib)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        if arena is not None:   # a torch device tensor: its memory backs every call
+            assert _is_torch_cuda(arena) and arena.is_contiguous()
+            cfg.arena = arena.data_ptr()
+            cfg.arena_bytes = arena.numel() * arena.element_size()
+            self._arena = arena   # kept alive with the context
         h = C.c_void_p()
         s = _lib.hough_hier_create(C.byref(cfg), C.byref(h))
         if s != 0:
@@ -307,6 +330,41 @@ class HoughHier:
         if isinstance(stream, int):
             return stream
         return int(stream.cuda_stream)   # torch.cuda.Stream
+
+    def set_launch(self, task_steps: int = 0, queue_batch: int = 0, wg_per_cu: int = 0):
+        """Launch shape of the list kernels (``hough_hier_set_launch``)."""
+        ln = _Launch(int(task_steps), int(queue_batch), int(wg_per_cu), 0)
+        s = _lib.hough_hier_set_launch(self._h, C.byref(ln))
+        if s != 0:
+            raise HHError(s, self.last_error())
+
+    def autotune(self, inputs) -> dict:
+        """``hough_hier_autotune`` for calls like ``inputs`` (a list of
+        ``detect`` keyword dicts): the launch shape chosen (and set on the
+        context), and whether it came from the cache."""
+        arr = (_Input * len(inputs))()
+        keep = []
+        for k, kw in enumerate(inputs):
+            inp, kp = self._input(**kw)
+            arr[k] = inp
+            keep.append(kp)
+        ln = _Launch()
+        cached = C.c_int32()
+        s = _lib.hough_hier_autotune(self._h, arr, len(inputs), C.byref(ln), C.byref(cached))
+        del keep
+        if s != 0:
+            raise HHError(s, self.last_error())
+        out = {k: getattr(ln, k) for k, _ in _Launch._fields_ if k != "reserved"}
+        out["from_cache"] = bool(cached.value)
+        return out
+
+    def launch(self) -> dict:
+        """The current launch shape (``hough_hier_get_launch``)."""
+        ln = _Launch()
+        s = _lib.hough_hier_get_launch(self._h, C.byref(ln))
+        if s != 0:
+            raise HHError(s, self.last_error())
+        return {k: getattr(ln, k) for k, _ in _Launch._fields_ if k != "reserved"}
 
     def last_error(self) -> str:
         if not self._h:

@@ -53,7 +53,8 @@ hh_status hough_hier_create(const hh_config* cfg, hh_ctx** out)
     if (cfg->threshold < 0 || cfg->max_depth < -1 || cfg->max_depth > HH_MAX_DEPTH ||
         (cfg->variant != HH_VARIANT_CODE && cfg->variant != HH_VARIANT_CIRCLE) ||
         (cfg->passes & ~(HH_PASS_0 | HH_PASS_1)) != 0 || (cfg->membership != 0 && cfg->membership != 1) ||
-        cfg->arena_limit_mib < 0)
+        cfg->arena_limit_mib < 0 || (cfg->arena && (cfg->arena_bytes == 0 || (uintptr_t)cfg->arena % 256)) ||
+        (!cfg->arena && cfg->arena_bytes))
         return HH_EINVAL;
     try {
         return hh::engine_create(cfg, out);
@@ -68,6 +69,43 @@ void hough_hier_destroy(hh_ctx* ctx)
         hh::engine_destroy(ctx);
     } catch (...) {
     }
+}
+
+hh_status hough_hier_set_launch(hh_ctx* ctx, const hh_launch* launch)
+{
+    if (!ctx || !launch) return HH_EINVAL;
+    const int32_t steps = launch->task_steps ? launch->task_steps : 4;
+    if (steps < 1 || steps > hh::kMaxTaskSteps || launch->queue_batch < 0 || launch->queue_batch > 1024 ||
+        launch->wg_per_cu < 0 || launch->wg_per_cu > 64)
+        return fail(ctx, HH_EINVAL, "launch shape out of range");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->task_steps = steps;
+    ctx->queue_batch = launch->queue_batch;
+    ctx->wg_per_cu = launch->wg_per_cu;
+    return HH_OK;
+}
+
+hh_status hough_hier_autotune(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_launch* chosen,
+                              int32_t* from_cache)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!inputs || !chosen || n < 1) return fail(ctx, HH_EINVAL, "inputs and chosen must not be NULL, n >= 1");
+    clear_error(ctx);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    int32_t cached = 0;
+    const hh_status s = guarded(ctx, [&] { return hh::engine_autotune(ctx, inputs, n, chosen, &cached); });
+    if (from_cache) *from_cache = cached;
+    return s;
+}
+
+hh_status hough_hier_get_launch(const hh_ctx* ctx, hh_launch* launch)
+{
+    if (!ctx || !launch) return HH_EINVAL;
+    launch->task_steps = ctx->task_steps;
+    launch->queue_batch = ctx->queue_batch;
+    launch->wg_per_cu = ctx->wg_per_cu;
+    launch->reserved = 0;
+    return HH_OK;
 }
 
 const char* hough_hier_last_error(const hh_ctx* ctx)
@@ -277,6 +315,13 @@ hh_status hough_hier_result_solution_image(hh_result* res, uint8_t* image, int64
     return guarded(res->ctx, [&] { return hh::engine_solution_image(res, image, row_stride, on_device); });
 }
 
+const char* hough_hier_result_last_error(const hh_result* res)
+{
+    if (!res || !res->ctx) return "";
+    std::lock_guard<std::mutex> g(res->ctx->err_mu);
+    return res->ctx->last_error.c_str();
+}
+
 void hough_hier_result_free(hh_result* res)
 {
     if (!res) return;
@@ -285,6 +330,7 @@ void hough_hier_result_free(hh_result* res)
         {
             std::lock_guard<std::mutex> g(res->ctx->results_mu);
             res->ctx->live_results.erase(res);
+            if (res->in_arena) --res->ctx->arena_results;
         }
         delete res;
     } catch (...) {

@@ -146,6 +146,19 @@ void DevBuf::reset()
     bytes_ = 0;
 }
 
+DevBuf CallMem::get(size_t bytes, const char* what)
+{
+    taken += (int64_t)bytes;
+    if (!base) return DevBuf(pool, bytes);
+    const int64_t n = align256(std::max<int64_t>((int64_t)bytes, 1));
+    if (used + n > cap)
+        throw Error{HH_ECAPACITY, std::string("the caller's arena (") + std::to_string(cap) +
+                                      " bytes) cannot hold the call's " + what};
+    DevBuf b = DevBuf::view(base + used, bytes);
+    used += n;
+    return b;
+}
+
 // ---------------------------------------------------------------- helpers
 
 namespace {
@@ -321,6 +334,8 @@ void engine_destroy(hh_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     ctx->events.clear();
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
     {
         std::lock_guard<std::mutex> g(ctx->results_mu);
         for (hh_result* r : ctx->live_results) delete r;
@@ -379,7 +394,7 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
 int failing_stage(const LevelInfo* info, int32_t dmax, const Caps& c, bool members, int32_t eb)
 {
     auto fits = [&](const LevelInfo& x) {
-        return half_layout(nullptr, x.P, x.L, eb).end <= c.half && work_layout(nullptr, x.P, x.L).end <= c.work;
+        return half_layout(nullptr, x.P, x.L, x.NT, eb).end <= c.half && work_layout(nullptr, x.P, x.NT).end <= c.work;
     };
     if (!fits(info[0])) return -1;
     for (int l = 0; l < dmax; ++l) {
@@ -399,8 +414,8 @@ Caps grown_caps(const Caps& c, const LevelInfo& x, bool members, int32_t eb, dou
         return need <= cur ? cur : align256((int64_t)((double)need * factor));
     };
     Caps g = c;
-    g.half = grow(c.half, half_layout(nullptr, x.P, x.L, eb).end);
-    g.work = grow(c.work, work_layout(nullptr, x.P, x.L).end);
+    g.half = grow(c.half, half_layout(nullptr, x.P, x.L, x.NT, eb).end);
+    g.work = grow(c.work, work_layout(nullptr, x.P, x.NT).end);
     g.cells = grow(c.cells, x.cells_base + x.cells);
     if (members) g.mem = grow(c.mem, x.mem_base + x.mem);
     return g;
@@ -504,32 +519,195 @@ struct GroupRun {
     uint32_t err = 0;
 };
 
-void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees, int32_t n_trees, int32_t dmax,
-               const uint32_t* xy, const int32_t* ids, TreeDesc* h_trees, int64_t back_bytes, hh_timing& tm,
-               GroupRun& g)
+// The part sizes of a level arena of `avail` bytes in the proportions of c
+// (every part scaled by one factor).
+Caps fit_caps(const Caps& c, int64_t avail, int32_t n_trees, int32_t eb, bool members)
+{
+    const double need = (double)arena_bytes(fixed_layout(n_trees, c.cells), c, eb);
+    double f = (double)avail / need;
+    for (int k = 0; k < 64; ++k, f *= 0.97) {
+        Caps s{};
+        s.cells = std::max<int64_t>(256, (int64_t)((double)c.cells * f));
+        s.mem = members ? std::max<int64_t>(1024, (int64_t)((double)c.mem * f)) : 0;
+        s.half = std::max<int64_t>(4096, (int64_t)((double)c.half * f) & ~(int64_t)255);
+        s.work = std::max<int64_t>(4096, (int64_t)((double)c.work * f) & ~(int64_t)255);
+        if (arena_bytes(fixed_layout(n_trees, s.cells), s, eb) <= avail) return s;
+    }
+    throw Error{HH_ECAPACITY, "the caller's arena (" + std::to_string(avail) +
+                                  " bytes left after the call's inputs) is too small for a level arena"};
+}
+
+void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, TreeDesc* trees, int32_t n_trees,
+               int32_t dmax, const uint32_t* xy, const int32_t* ids, TreeDesc* h_trees, int64_t back_bytes,
+               hh_timing& tm, GroupRun& g)
 {
     hipStream_t st = ctx->stream;
     DevicePool* pool = &ctx->pool;
     const bool members = p0.membership;
     const bool timing = !ctx->events.empty();
     const int64_t n_rec = (int64_t)n_trees * kMaxLevels * kRecCh;
+    const int32_t task_steps = ctx->task_steps;   // fixed for the whole run: a resume reuses built tasks
+    int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
+    if (ctx->wg_per_cu > 0) {
+        count_grid = std::min(count_grid, ctx->wg_per_cu * ctx->cu_count);
+        write_grid = std::min(write_grid, ctx->wg_per_cu * ctx->cu_count);
+    }
+    // the launches from stage `from` (-1: the root setup; l: level l's split
+    // decision) to the finest level, then the copies of the level records
+    // back to the host (enqueued only)
+    auto enqueue_levels = [&](int from) {
+        if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ids, task_steps, ctx->grid, st), "roots");
+        LevelArgs la{};
+        la.ar = g.ar;
+        la.trees = trees;
+        la.xy = xy;
+        la.keep_members = members ? 1 : 0;
+        la.task_steps = task_steps;
+        la.queue_batch = ctx->queue_batch;
+        for (int l = std::max(from, 0); l < dmax; ++l) {
+            la.level = l;
+            mark(ctx, 3 + 4 * l);
+            if (l != from) check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
+            mark(ctx, 4 + 4 * l);
+            if (l != from) check(launch_decide(la, kRangeGrid, st), "decide");
+            check(launch_emit(la, kRangeGrid, st), "emit");
+            mark(ctx, 5 + 4 * l);
+            if (l + 1 < dmax || members) check(launch_write(la, p0.variant, p0.wide, write_grid, st), "write");
+            mark(ctx, 6 + 4 * l);
+        }
+        mark(ctx, 2);
+        check(hipMemcpyAsync(ctx->h_fixed, g.ar.info, (size_t)g.fl.head_bytes, hipMemcpyDeviceToHost, st),
+              "copy level records");
+        check(hipMemcpyAsync(h_trees, trees, (size_t)back_bytes, hipMemcpyDeviceToHost, st), "copy trees back");
+    };
+    // wait for them; false if a level outgrew the arena
+    auto collect = [&]() {
+        sync(ctx);
+        g.err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + g.fl.error);
+        return !(g.err & kErrArena) || (g.err & (kErrPointRange | kErrInternal));
+    };
+    auto launch_levels = [&](int from) {
+        enqueue_levels(from);
+        return collect();
+    };
+    auto account = [&](int first) {
+        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
+        if (timing) {
+            for (int l = first; l < dmax; ++l) {
+                const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
+                tm.count_ms += c;
+                tm.write_ms += w;
+                tm.vote_ms += c + w;
+                tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
+            }
+            tm.vote_launches += dmax + (members ? dmax : dmax - 1);
+            tm.decide_launches += 2 * dmax;
+        }
+        for (int l = 0; l < dmax; ++l) {
+            tm.vote_entries += info[l].L;
+            if (l + 1 < dmax) tm.vote_written += info[l + 1].L;
+            if (members) tm.vote_written += info[l + 1].mem;
+        }
+    };
+    // part sizes that hold the needs of the stage that overflowed (factor x need)
+    auto learn = [&](const Caps& caps, double factor, Caps& grown) {
+        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
+        const int f = failing_stage(info, dmax, caps, members, entry_bytes);
+        if (f == -2) throw Error{HH_EINTERNAL, "arena overflow reported but every level fits"};
+        grown = grown_caps(caps, info[f + 1], members, entry_bytes, factor);   // f = -1: the root level
+        return f;
+    };
+
+    if (mem.base) {
+        // the caller's arena: the rest of it is the level arena; one rerun
+        // with the parts re-split by the sizes the first run measured.  With
+        // HH_FLAG_GRAPH the first run's launches are a captured graph,
+        // replayed when the next call bakes in the same addresses and sizes.
+        const bool graph = (ctx->cfg.flags & HH_FLAG_GRAPH) && !timing && mem.graph_ok && st != nullptr;
+        const int64_t avail = mem.left() & ~(int64_t)255;
+        DevBuf whole = mem.get((size_t)std::max<int64_t>(avail, 256), "level arena");
+        mem.taken -= (int64_t)whole.bytes();
+        mem.arena_peak = std::max<int64_t>(mem.arena_peak, avail);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const Caps want{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+            const Caps caps = fit_caps(want, avail, n_trees, entry_bytes, members);
+            g.fl = fixed_layout(n_trees, caps.cells);
+            g.ar = carve(whole.as<char>(), g.fl, n_trees, caps, entry_bytes);
+            g.arena = DevBuf::view(whole.get(), whole.bytes());
+            bool ok;
+            if (graph && attempt == 0) {
+                // every address and size the launches bake in
+                std::string key;
+                auto put = [&](const auto& v) { key.append(reinterpret_cast<const char*>(&v), sizeof(v)); };
+                for (const auto& v : {(int64_t)(intptr_t)whole.get(), caps.cells, caps.mem, caps.half, caps.work,
+                                      (int64_t)(intptr_t)trees, (int64_t)(intptr_t)xy, (int64_t)(intptr_t)ids,
+                                      (int64_t)(intptr_t)h_trees, back_bytes, (int64_t)n_trees, (int64_t)dmax,
+                                      (int64_t)entry_bytes, (int64_t)p0.variant, (int64_t)p0.wide,
+                                      (int64_t)members, (int64_t)task_steps, (int64_t)ctx->queue_batch,
+                                      (int64_t)count_grid, (int64_t)write_grid})
+                    put(v);
+                if (!ctx->graph_exec || ctx->graph_key != key) {
+                    if (ctx->graph_exec) check(hipGraphExecDestroy(ctx->graph_exec), "hipGraphExecDestroy");
+                    ctx->graph_exec = nullptr;
+                    check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                    hipGraph_t gr = nullptr;
+                    try {
+                        check(launch_clear(g.ar, n_rec, st), "clear");
+                        enqueue_levels(-1);
+                    } catch (...) {
+                        (void)hipStreamEndCapture(st, &gr);
+                        if (gr) (void)hipGraphDestroy(gr);
+                        throw;
+                    }
+                    check(hipStreamEndCapture(st, &gr), "hipStreamEndCapture");
+                    const hipError_t e = hipGraphInstantiate(&ctx->graph_exec, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    check(e, "hipGraphInstantiate");
+                    ctx->graph_key = key;
+                } else {
+                    ++ctx->graph_replays;
+                    tm.graph_replayed = 1;
+                }
+                check(hipGraphLaunch(ctx->graph_exec, st), "hipGraphLaunch");
+                ok = collect();
+            } else {
+                check(launch_clear(g.ar, n_rec, st), "clear");
+                ok = launch_levels(-1);
+            }
+            if (ok) {
+                account(0);
+                return;
+            }
+            Caps grown{};
+            learn(caps, 1.25, grown);
+            ++tm.resumes;
+            ctx->half_cap = std::max(ctx->half_cap, grown.half);
+            ctx->work_cap = std::max(ctx->work_cap, grown.work);
+            ctx->cells_cap = std::max(ctx->cells_cap, grown.cells);
+            if (members) ctx->mem_cap = std::max(ctx->mem_cap, grown.mem);
+        }
+        throw Error{HH_ECAPACITY, "the caller's arena (" + std::to_string(mem.cap) +
+                                      " bytes) cannot hold the call's level lists"};
+    }
+
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
         (void)hipGetLastError();
         total_b = (size_t)64 << 30;
     }
     // one arena; a resume holds two for a moment
-    const double budget =
-        ctx->cfg.arena_limit_mib > 0 ? (double)ctx->cfg.arena_limit_mib * (1 << 20) : 0.35 * (double)total_b;
+    const double budget = ctx->cfg.hbm_budget_bytes > 0 ? (double)ctx->cfg.hbm_budget_bytes
+                          : ctx->cfg.arena_limit_mib > 0 ? (double)ctx->cfg.arena_limit_mib * (1 << 20)
+                                                         : 0.35 * (double)total_b;
     int from = -1;   // -1: from the root setup; l: from level l's split decision
-    const int count_grid = level_grid(0, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
-    const int write_grid = level_grid(1, p0.variant, p0.wide, entry_bytes, ctx->cu_count);
     for (int run = 0;; ++run) {
         if (run >= 64) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
         const Caps caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
         const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
         if (run == 0 && (double)arena_bytes(nfl, caps, entry_bytes) > budget) throw BudgetExceeded{budget};
         DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
+        mem.arena_peak = std::max<int64_t>(mem.arena_peak, arena_bytes(nfl, caps, entry_bytes));
         const Arena nar = carve(narena.as<char>(), nfl, n_trees, caps, entry_bytes);
         if (from < 0) {
             check(launch_clear(nar, n_rec, st), "clear");
@@ -545,67 +723,25 @@ void run_group(hh_ctx* ctx, const Plan& p0, int32_t entry_bytes, TreeDesc* trees
             check(hipMemsetAsync(nar.error, 0, sizeof(uint32_t), st), "resume clear");
             copy(nar.cells, g.ar.cells, nx.cells_base * (int64_t)sizeof(Cell));
             if (members) copy(nar.members, g.ar.members, nx.mem_base * entry_bytes);
-            copy(nar.half[from & 1], g.ar.half[from & 1], half_layout(nullptr, lv.P, lv.L, entry_bytes).end);
-            copy(nar.work, g.ar.work, work_layout(nullptr, lv.P, lv.L).end);
+            copy(nar.half[from & 1], g.ar.half[from & 1], half_layout(nullptr, lv.P, lv.L, lv.NT, entry_bytes).end);
+            copy(nar.work, g.ar.work, work_layout(nullptr, lv.P, lv.NT).end);
             sync(ctx);   // the old arena goes back to the pool only once it is read
         }
         if (run > 0) g.arena.discard();   // a smaller arena is of no further use
         g.arena = std::move(narena);
         g.ar = nar;
         g.fl = nfl;
-        if (from < 0) check(launch_roots(g.ar, trees, n_trees, xy, ids, ctx->grid, st), "roots");
-        LevelArgs la{};
-        la.ar = g.ar;
-        la.trees = trees;
-        la.xy = xy;
-        la.keep_members = members ? 1 : 0;
-        const int first = std::max(from, 0);
-        for (int l = first; l < dmax; ++l) {
-            la.level = l;
-            mark(ctx, 3 + 4 * l);
-            if (l != from) check(launch_count(la, p0.variant, p0.wide, count_grid, st), "count");
-            mark(ctx, 4 + 4 * l);
-            if (l != from) check(launch_decide(la, kRangeGrid, st), "decide");
-            check(launch_emit(la, kRangeGrid, st), "emit");
-            mark(ctx, 5 + 4 * l);
-            if (l + 1 < dmax || members) check(launch_write(la, write_grid, st), "write");
-            mark(ctx, 6 + 4 * l);
-        }
-        mark(ctx, 2);
-        check(hipMemcpyAsync(ctx->h_fixed, g.arena.get(), (size_t)g.fl.head_bytes, hipMemcpyDeviceToHost, st),
-              "copy level records");
-        check(hipMemcpyAsync(h_trees, trees, (size_t)back_bytes, hipMemcpyDeviceToHost, st), "copy trees back");
-        sync(ctx);
-        g.err = *reinterpret_cast<const uint32_t*>(ctx->h_fixed + g.fl.error);
-        const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
-        if (!(g.err & kErrArena) || (g.err & (kErrPointRange | kErrInternal))) {
-            if (timing) {
-                for (int l = first; l < dmax; ++l) {
-                    const double c = elapsed(ctx, 3 + 4 * l, 4 + 4 * l), w = elapsed(ctx, 5 + 4 * l, 6 + 4 * l);
-                    tm.count_ms += c;
-                    tm.write_ms += w;
-                    tm.vote_ms += c + w;
-                    tm.decide_ms += elapsed(ctx, 4 + 4 * l, 5 + 4 * l);
-                }
-                tm.vote_launches += dmax + (members ? dmax : dmax - 1);
-                tm.decide_launches += 2 * dmax;
-            }
-            for (int l = 0; l < dmax; ++l) {
-                tm.vote_entries += info[l].L;
-                if (l + 1 < dmax) tm.vote_written += info[l + 1].L;
-                if (members) tm.vote_written += info[l + 1].mem;
-            }
+        if (launch_levels(from)) {
+            account(std::max(from, 0));
             return;
         }
-        const int f = failing_stage(info, dmax, caps, members, entry_bytes);
-        if (f == -2) throw Error{HH_EINTERNAL, "arena overflow reported but every level fits"};
-        const LevelInfo& need = info[f + 1];   // f = -1: the root level
         // lists about double per level while most regions split: twice the
         // need, less if that exceeds the budget
         Caps grown{};
         bool ok = false;
+        int f = -2;
         for (double factor : {2.0, 1.25, 1.0}) {
-            grown = grown_caps(caps, need, members, entry_bytes, factor);
+            f = learn(caps, factor, grown);
             if ((double)arena_bytes(fixed_layout(n_trees, grown.cells), grown, entry_bytes) <= budget) {
                 ok = true;
                 break;
@@ -628,7 +764,7 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     return engine_detect_batch(ctx, in, 1, out);
 }
 
-hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out)
+hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out, CallMem* ext)
 {
     hipStream_t st = ctx->stream;
     DevicePool* pool = &ctx->pool;
@@ -639,6 +775,18 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     if (n < 1) throw Error{HH_EINVAL, "a call needs at least one input"};
     if ((int64_t)n * n_pass > kMaxTrees) throw Error{HH_ECAPACITY, "too many images in one call"};
     const int32_t n_trees = n * n_pass;
+    // device memory of the call: the pool, or the caller's arena front to back
+    CallMem mem;
+    mem.pool = pool;
+    if (ext) {
+        mem = *ext;
+    } else if (ctx->cfg.arena) {
+        std::lock_guard<std::mutex> g(ctx->results_mu);
+        if (ctx->arena_results > 0)
+            throw Error{HH_EBUSY, "results of an earlier call still live in the caller's arena: free them first"};
+        mem.base = static_cast<char*>(ctx->cfg.arena);
+        mem.cap = (int64_t)ctx->cfg.arena_bytes;
+    }
 
     // ---- plans; every input of a call is of one kind
     std::vector<ImagePlan> ip((size_t)n);
@@ -655,6 +803,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         if (in->kind != inputs[0].kind) throw Error{HH_EINVAL, "all inputs of a call must be of one kind"};
         dmax_all = std::max(dmax_all, ip[(size_t)k].plan.dmax);
     }
+    mem.graph_ok = true;
+    for (int32_t k = 0; k < n; ++k) mem.graph_ok = mem.graph_ok && inputs[k].on_device;
     const Plan& p0 = ip[0].plan;   // variant, compares and membership are the context's
     const int32_t kind = inputs[0].kind;
     // point lists and gray images keep their point ids in the entries
@@ -695,8 +845,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
                 std::copy(in->y, in->y + in->n_points, hyv.begin() + at);
                 at += in->n_points;
             }
-            hx = DevBuf(pool, (size_t)host_points * 4);
-            hy = DevBuf(pool, (size_t)host_points * 4);
+            hx = mem.get((size_t)host_points * 4, "staged x");
+            hy = mem.get((size_t)host_points * 4, "staged y");
             check(hipMemcpyAsync(hx.get(), hxv.data(), (size_t)host_points * 4, hipMemcpyHostToDevice, st), "copy x");
             check(hipMemcpyAsync(hy.get(), hyv.data(), (size_t)host_points * 4, hipMemcpyHostToDevice, st), "copy y");
             check(hipStreamSynchronize(st), "copy points");   // the host vectors end here
@@ -713,7 +863,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             d.width = in->width;
             d.height = in->height;
         }
-        store->points = DevBuf(pool, (size_t)std::max<int64_t>(total_points, 1) * 4);
+        store->points = mem.get((size_t)std::max<int64_t>(total_points, 1) * 4, "packed points");
     } else {
         // binary or gray images: host images are packed into one upload
         int64_t host_bytes = 0, pix_all = 0;
@@ -725,7 +875,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             if (!in->on_device) host_bytes += (int64_t)in->width * in->height;
             pix_all += (int64_t)in->width * in->height;
         }
-        if (host_bytes > 0) himg = DevBuf(pool, (size_t)host_bytes);
+        if (host_bytes > 0) himg = mem.get((size_t)host_bytes, "staged images");
         int64_t at = 0;
         for (int32_t k = 0; k < n; ++k) {
             const hh_input* in = &inputs[k];
@@ -751,11 +901,11 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             }
             ip[(size_t)k].n_points = -1;
         }
-        store->points = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
+        store->points = mem.get((size_t)std::max<int64_t>(pix_all, 1) * 4, "packed points");
         const int64_t sets = kind == 2 ? 2 : 1;   // gray images count ALPHA and BETA apart
-        tcount = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles * sets, 1) * 4);
-        tpre = DevBuf(pool, (size_t)std::max<int64_t>(n_tiles * sets, 1) * 8);
-        if (kind == 2) d_ids = DevBuf(pool, (size_t)std::max<int64_t>(pix_all, 1) * 4);
+        tcount = mem.get((size_t)std::max<int64_t>(n_tiles * sets, 1) * 4, "tile counts");
+        tpre = mem.get((size_t)std::max<int64_t>(n_tiles * sets, 1) * 8, "tile prefixes");
+        if (kind == 2) d_ids = mem.get((size_t)std::max<int64_t>(pix_all, 1) * 4, "point ids");
     }
     uint32_t* xy = store->points.as<uint32_t>();
 
@@ -784,7 +934,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     // trees, a cleared staging error word and the input table in one upload
     *h_err = 0;
     const int64_t call_bytes = cl.desc + (int64_t)n * (kind == 0 ? sizeof(PointsDesc) : sizeof(ImageDesc));
-    DevBuf d_call(pool, (size_t)call_bytes);
+    DevBuf d_call = mem.get((size_t)call_bytes, "descriptors");
     check(hipMemcpyAsync(d_call.get(), ctx->h_call, (size_t)call_bytes, hipMemcpyHostToDevice, st), "copy descriptors");
     TreeDesc* const d_trees = d_call.as<TreeDesc>();
     uint32_t* const d_err = reinterpret_cast<uint32_t*>(d_call.as<char>() + cl.err);
@@ -838,7 +988,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     int32_t n_groups = 0;
     for (int32_t k0 = 0; k0 < n;) {
         int32_t k1 = n;
-        if (ctx->group_points > 0 && n > 1) {
+        if (ctx->group_points > 0 && n > 1 && !mem.base) {
             ensure_counts();
             int64_t sum = points_of(k0);
             for (k1 = k0 + 1; k1 < n && sum + points_of(k1) <= ctx->group_points; ++k1) sum += points_of(k1);
@@ -850,8 +1000,8 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         try {
             // the first group also brings back the staging error word
             const int64_t back = k0 == 0 ? cl.err + 4 : (int64_t)ntg * (int64_t)sizeof(TreeDesc);
-            run_group(ctx, p0, entry_bytes, d_trees + t0g, ntg, dmax, xy, kind == 2 ? d_ids.as<int32_t>() : nullptr,
-                      ctx->h_trees + t0g, back, tm, g);
+            run_group(ctx, mem, p0, entry_bytes, d_trees + t0g, ntg, dmax, xy,
+                      kind == 2 ? d_ids.as<int32_t>() : nullptr, ctx->h_trees + t0g, back, tm, g);
         } catch (const BudgetExceeded& b) {
             if (k1 - k0 <= 1)
                 throw Error{HH_ECAPACITY, "input " + std::to_string(k0) + " needs more than " +
@@ -946,7 +1096,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             } else if (r->n_cells_total > 0) {
                 // depth 0: the root is the finest region; every line votes for it
                 r->depth0 = true;
-                r->depth0_cells = DevBuf(pool, sizeof(Cell) * (size_t)n_pass);
+                r->depth0_cells = mem.get(sizeof(Cell) * (size_t)n_pass, "cells");
                 std::vector<Cell> hc;
                 for (int32_t q = 0; q < n_pass; ++q) {
                     if (r->info.n_cells[tree_pass[q]] == 0) continue;
@@ -981,6 +1131,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         k0 = k1;
     }
     sync(ctx);   // the copies of the last group
+    ctx->last_call_bytes = mem.taken + mem.arena_peak;
     if (timing) {
         tm.total_ms = elapsed(ctx, 0, 2);
         tm.extract_ms = elapsed(ctx, 0, 1);
@@ -989,8 +1140,10 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     for (int32_t k = 0; k < n; ++k) {
         res[(size_t)k]->timing = tm;
         res[(size_t)k]->timing.groups = n_groups;
+        res[(size_t)k]->in_arena = mem.base != nullptr && !ext;
         out[k] = res[(size_t)k].release();
         ctx->live_results.insert(out[k]);
+        if (out[k]->in_arena) ++ctx->arena_results;
     }
     return HH_OK;
 }

@@ -48,6 +48,14 @@ class DevBuf {
 public:
     DevBuf() = default;
     DevBuf(DevicePool* pool, size_t bytes);
+    // a view of memory the DevBuf does not own (nothing is released)
+    static DevBuf view(void* p, size_t bytes)
+    {
+        DevBuf b;
+        b.ptr_ = p;
+        b.bytes_ = bytes;
+        return b;
+    }
     ~DevBuf() { reset(); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -69,6 +77,19 @@ private:
 struct Error {
     hh_status status;
     std::string what;
+};
+
+// Device memory of one call: blocks of the context's pool, or views carved
+// front to back (256-byte aligned) from a caller's arena.
+struct CallMem {
+    DevicePool* pool = nullptr;
+    char* base = nullptr;   // the caller's arena, or nullptr
+    int64_t cap = 0, used = 0;
+    bool graph_ok = false;  // every input is device resident (HH_FLAG_GRAPH may capture)
+    int64_t taken = 0;      // bytes handed out (both kinds), for the footprint of the call
+    int64_t arena_peak = 0; // largest level arena the call held
+    DevBuf get(size_t bytes, const char* what);
+    int64_t left() const { return cap - used; }
 };
 
 }  // namespace hh
@@ -110,6 +131,7 @@ struct hh_result {
     const uint32_t* xy = nullptr;        // this image's packed edge points
     int32_t entry_bytes = 4;             // 4: packed point; 8: id << 32 | packed point
     bool have_members = false;
+    bool in_arena = false;               // made in the caller's arena (counted in ctx->arena_results)
     bool depth0 = false;                 // the root is the only level: every point votes
     hh::DevBuf depth0_cells;             // depth 0: the cells, made on the host
     hh::DevBuf dev_cells;                // cells with member_off relative to this image (made on request)
@@ -172,12 +194,28 @@ struct hh_ctx {
     // most edge points one group of a batch may hold (0: no limit), learnt
     // when a group's level lists exceeded the memory budget
     int64_t group_points = 0;
-    int32_t grid = 0;          // workgroups of the level kernels (fixed grid, tiles strided)
+    int32_t grid = 0;          // workgroups of the root-list kernel
+    // launch shape of the list kernels: steps (512 entries) per task, tasks a
+    // wavefront takes from the level's queue at once (0: a fixed share), and
+    // resident workgroups per compute unit (0: as many as fit)
+    int32_t task_steps = 4;
+    int32_t queue_batch = 0;
+    int32_t wg_per_cu = 0;
     // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
     // then four per level: before count, after count, after emit, after the compaction
     std::vector<hipEvent_t> events;
     // results not yet freed; destroyed with the context
     std::unordered_set<hh_result*> live_results;
+    // results made in the caller's arena (hh_config.arena) and not yet freed
+    int64_t arena_results = 0;
+    // device bytes the last detection call held at most (inputs, staging,
+    // level arena), for serving admission
+    int64_t last_call_bytes = 0;
+    // HH_FLAG_GRAPH: the captured level launches of the last call and what
+    // they were captured for (sizes, parameters, addresses)
+    hipGraphExec_t graph_exec = nullptr;
+    std::string graph_key;
+    int64_t graph_replays = 0;
 };
 
 namespace hh {
@@ -185,8 +223,14 @@ namespace hh {
 hh_status engine_create(const hh_config* cfg, hh_ctx** out);
 void engine_destroy(hh_ctx* ctx);
 hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
-// n inputs in one call; out[k] is the result of in[k] (all or none are made)
-hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* in, int32_t n, hh_result** out);
+// n inputs in one call; out[k] is the result of in[k] (all or none are made).
+// With ext, the call's device memory is carved from ext's region (no
+// allocation) and its results are not counted as the caller arena's.
+hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* in, int32_t n, hh_result** out,
+                              CallMem* ext = nullptr);
+// Autotuner (hh_tune.cpp): the launch shape for calls like in[0 .. n), from
+// the cache or by timing candidates on this call; set on ctx and returned.
+hh_status engine_autotune(hh_ctx* ctx, const hh_input* in, int32_t n, hh_launch* chosen, int32_t* from_cache);
 hh_status engine_host_cells(hh_result* res);
 hh_status engine_host_members(hh_result* res);
 hh_status engine_device_ids(hh_result* res);

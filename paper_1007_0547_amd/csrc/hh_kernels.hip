@@ -12,21 +12,23 @@
 // Per level, four launches:
 //   k_count   one read of every entry: the 4-bit corner codes of the line for
 //             the four children (Sec. 2, getcode()) and the vote rule (code
-//             not 0000 / 1111, Sec. 3) as wavefront lane masks, and
-//             per tile of kTile entries the child-vote counts of every
-//             region piece in it.
-//   k_decide  per region: its child votes (its pieces summed), the split
-//             decisions (votes > T, Sec. 3) and their sums per range of regions.
+//             not 0000 / 1111, Sec. 3) as wavefront lane masks, counted per
+//             task (a run of one region's list) and summed per region.
+//   k_decide  per region: the split decisions (votes > T, Sec. 3) and their
+//             sums per range of regions.
 //   k_emit    per region: offsets from those sums; the next level's region
-//             table in quad order (so key order is kept) and tile map, or the
-//             detected cells at the finest level.
-//   k_write   a second read of every entry: each vote for a kept child is
-//             written, in list order, to that child's list in the next
-//             level (or to the member buffer at the finest level).
+//             table in quad order (so key order is kept) and its tasks, or
+//             the detected cells at the finest level.
+//   k_write   a second read of every entry of a region with a kept child:
+//             each vote for a kept child is written, in list order, to that
+//             child's list in the next level (or to the member buffer at the
+//             finest level).
 //
 // Level sizes never travel to the host: each launch reads them from the
-// arena's LevelInfo records written by the launches before it, and walks its
-// work with a fixed grid.  No launch waits on another workgroup.
+// arena's LevelInfo records written by the launches before it.  The list
+// launches run a resident grid whose wavefronts draw tasks until the
+// level's are all taken; the others walk their work with a fixed grid.  No
+// launch waits on another workgroup.
 
 #include <hip/hip_runtime.h>
 
@@ -49,6 +51,19 @@ __device__ inline T* G(T* p)
     return (T*)(__attribute__((address_space(1))) T*)p;
 }
 
+// Element k of an array no launch writes while the caller runs, read through
+// the constant address space: with a wavefront-uniform index the compiler
+// emits a scalar load into scalar registers.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p, int64_t k)
+{
+#if __HIP_DEVICE_COMPILE__
+    return ((const __attribute__((address_space(4))) T*)p)[k];
+#else
+    return p[k];   // the host pass only parses device code
+#endif
+}
+
 // Whether an earlier launch stopped the call.  A plain load: errors of earlier
 // launches are visible at the kernel boundary, and an error raised by a
 // concurrent workgroup of this launch need not stop the others.  Kernels load
@@ -58,17 +73,6 @@ __device__ inline bool stopped(uint32_t err) { return (err & kErrStop) != 0; }
 __device__ inline void raise_error(uint32_t* error, uint32_t bits)
 {
     __hip_atomic_fetch_or(G(error), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Workgroup barrier that orders LDS only.  The level kernels share nothing
-// but LDS inside a workgroup, so their barriers need not wait for the
-// wavefront's outstanding global stores (a full __syncthreads would drain
-// them at every tile).
-__device__ inline void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // set bits of b at lanes below this lane
@@ -197,16 +201,13 @@ __device__ inline void child_masks(uint64_t vm, uint32_t point, uint32_t meta, u
         circle_masks(vm, u, v, pi, pj, lc, s_log2, cm);
 }
 
-// The open region's part of the vote test, computed once per region and kept
-// in scalar registers; masks() evaluates a whole row of lines against it as
-// lane masks, votes() (code variant) as per-lane bits without any scalar
-// work.  With d_cr = t_c - B_r - 1, corner (c, r) is below the line iff
-// d_cr >= 0, so a child votes iff the sign bit of ~d_SW & d_NE is set.
+// A region's part of the vote test, computed once per task and kept in
+// scalar registers; masks() evaluates a whole row of lines against it as lane
+// masks, one per child (see code_masks and circle_masks).
 template <int kVariant, typename CT>
-struct OpenMasks {
+struct RegionTest {
     uint32_t ij, meta;
     CT M0, B0, B1, B2;      // code variant: scaled corner values of the children's grid
-    CT nB0, nB1, nB2;       //   -B_r - 1
     __device__ void set(uint32_t ij_, uint32_t meta_, int lc)
     {
         ij = ij_;
@@ -218,9 +219,6 @@ struct OpenMasks {
         B0 = (CT)6 * S * (CT)pj - (S << lc);
         B1 = B0 + (CT)3 * S;
         B2 = B1 + (CT)3 * S;
-        nB0 = -B0 - 1;
-        nB1 = -B1 - 1;
-        nB2 = -B2 - 1;
     }
     __device__ void masks(uint64_t vm, uint32_t point, int lc, uint64_t (&cm)[4]) const
     {
@@ -241,32 +239,37 @@ struct OpenMasks {
             child_masks<kVariant, CT>(vm, point, meta, ij, lc, cm);
         }
     }
-    // code variant: vote bits of one lane (NE, NW, SW, SE in bits 0..3)
+    // The same test as per-lane flags (vote of this lane's line for child q in
+    // bit q): used as store predicates, so no lane has to pick its bit out of
+    // a mask.  vm as in masks().
+    __device__ __forceinline__ uint32_t lane_votes(bool valid, uint32_t point, int lc) const
+    {
+        if constexpr (kVariant == 0) {
+            const CT u = (CT)(point & 0xFFFFu), v = (CT)(point >> 16);
+            const CT t0 = (v << lc) - mul(u, M0);
+            const CT du = 2 * u;
+            const CT t1 = t0 - du;
+            const CT t2 = t1 - du;
+            const bool ne = (B1 < t1) && !(B2 < t2);
+            const bool nw = (B1 < t0) && !(B2 < t1);
+            const bool sw = (B0 < t0) && !(B1 < t1);
+            const bool se = (B0 < t1) && !(B1 < t2);
+            return (uint32_t)ne | ((uint32_t)nw << 1) | ((uint32_t)sw << 2) | ((uint32_t)se << 3);
+        } else {
+            uint64_t cm[4];
+            child_masks<kVariant, CT>(valid ? ~0ull : 0ull, point, meta, ij, lc, cm);
+            const int lane = threadIdx.x & (kWave - 1);
+            uint32_t b = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b |= (uint32_t)((cm[q] >> lane) & 1u) << q;
+            return valid ? b : 0u;
+        }
+    }
     // |u| < 2^14 and |M0| <= 2^15: a 24-bit multiply is exact for 32-bit compares
     __device__ static CT mul(CT u, CT m)
     {
         if constexpr (sizeof(CT) == 4) return __mul24(u, m);
         else return u * m;
-    }
-    template <bool kAllValid>
-    __device__ uint32_t votes(bool valid, uint32_t point, int lc) const
-    {
-        const CT u = (CT)(point & 0xFFFFu), v = (CT)(point >> 16);
-        CT t0 = (v << lc) - mul(u, M0);
-        const CT du = 2 * u;
-        CT t1 = t0 - du;
-        CT t2 = t1 - du;
-        if (!kAllValid && !valid) t0 = t1 = t2 = -((CT)1 << 30);   // below every corner: no vote
-        const CT d00 = t0 + nB0, d01 = t0 + nB1;
-        const CT d10 = t1 + nB0, d11 = t1 + nB1, d12 = t1 + nB2;
-        const CT d21 = t2 + nB1, d22 = t2 + nB2;
-        constexpr int kSign = 8 * (int)sizeof(CT) - 1;
-        using U = typename std::conditional<sizeof(CT) == 8, uint64_t, uint32_t>::type;
-        const uint32_t ne = (uint32_t)((U)(~d11 & d22) >> kSign);
-        const uint32_t nw = (uint32_t)((U)(~d01 & d12) >> kSign);
-        const uint32_t sw = (uint32_t)((U)(~d00 & d11) >> kSign);
-        const uint32_t se = (uint32_t)((U)(~d10 & d21) >> kSign);
-        return ne | (nw << 1) | (sw << 2) | (se << 3);
     }
 };
 
@@ -297,366 +300,452 @@ __device__ inline int64_t wave_sum64(int64_t x)
     return x;
 }
 
-__device__ inline int32_t wave_sum32(int32_t x)
-{
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
-    return x;
-}
-
-// ------------------------------------------------------------------ tiles
+// ------------------------------------------------------------------ tasks
 //
-// A tile is kTile consecutive entries of a level's list: 32 rows of 64,
-// wavefront w taking rows 8w .. 8w+7.  Its regions are tile_first[t] ..
-// tile_first[t+1] (local indices 0 .. nr-1; local 0 holds the tile's first
-// entry).  In LDS the tile keeps a bitmap of the entries (other than the
-// first) that begin a region, so the local region of an entry is the number
-// of marked entries up to it, and a row's marks form one 64-bit word.  A row
-// with no mark belongs entirely to the wavefront's open region, whose fields
-// the wavefront keeps in scalar registers; only rows with a mark look up
-// region fields per lane.  Region fields come from LDS when the tile has at
-// most kStage regions, otherwise from the region table (a separate
-// instantiation, so no load has to choose between the two at run time).
-// Each workgroup walks its tiles with the next tile's entries and bounds
-// already in flight.
+// A level's list is cut into tasks: up to task_steps consecutive steps of
+// one region's list, a step being kStepRows rows of 64 entries.  A wavefront
+// takes tasks one after another -- from a fixed share (task = its wavefront
+// index + k * all wavefronts of the grid) or from the level's work queue (an
+// atomic head in its LevelInfo, queue_batch tasks at a time, the next batch
+// requested while the current one runs) -- and streams a task one step at a
+// time, the next step's entries already in flight while it tests the
+// current one.  All lines of a task belong to one region, so the region's
+// part of the vote test is wavefront-uniform and sits in scalar registers,
+// and a row is one test per lane.  Workgroups share nothing: a workgroup is
+// only a unit of launch.
 
 __device__ inline uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
-template <typename Entry>
-__device__ inline void load_rows(const Entry* list, int64_t L, int64_t tile, int wave, int lane, Entry (&ent)[kRows])
-{
-    const int64_t rb = tile * kTile + (int64_t)wave * (kRows * kWave);
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const int64_t e = rb + k * kWave + lane;
-        ent[k] = e < L ? list[e] : Entry(0);
-    }
-}
+// Task ids of one wavefront.
+struct TaskFeed {
+    int64_t* head;
+    int64_t NT, cur, end, stride;
+    int64_t req;     // queue mode, lane 0: start of the batch requested in advance
+    int32_t batch;   // 0: fixed share
 
-struct TileBounds {
-    int r0, r1;
-};
-
-__device__ inline TileBounds tile_bounds(const int32_t* tile_first, int64_t tile, int64_t nt, int64_t P)
-{
-    TileBounds b{0, -1};
-    if (tile < nt) {
-        b.r0 = tile_first[tile];
-        b.r1 = tile + 1 < nt ? tile_first[tile + 1] : (int)(P - 1);
-    }
-    return b;
-}
-
-// <= kTile + 1 regions: every region holds at least one entry
-__device__ inline bool bounds_ok(const TileBounds& b, int64_t P)
-{
-    const int nr = b.r1 - b.r0 + 1;
-    return b.r0 >= 0 && b.r1 < P && nr >= 1 && nr <= kTile + 1;
-}
-
-__device__ inline uint64_t row_word(const uint32_t* bm, int row)
-{
-    return uniform64((uint64_t)bm[2 * row] | ((uint64_t)bm[2 * row + 1] << 32));
-}
-
-// marked entries in the rows before wavefront `wave`
-__device__ inline int starts_before(const uint32_t* bm, int wave, int lane)
-{
-    const int nw = 2 * kRows * wave;   // bitmap words before the wavefront's rows (< 64)
-    const int c = lane < nw ? __popc(bm[lane]) : 0;
-    return __builtin_amdgcn_readfirstlane(wave_sum32(c));
-}
-
-// Staged fields of a tile's first kStage regions.
-struct StagedRegions {
-    uint32_t ij[kStage];
-    uint32_t meta[kStage];
-};
-
-// Fields of local region `local`: from LDS (kStaged) or the region table.
-template <bool kStaged>
-struct RegionSource {
-    const StagedRegions& S;
-    const Region* regions;
-    int r0;
-    __device__ void fields(int local, uint32_t& ij, uint32_t& meta) const
+    __device__ __forceinline__ int64_t request() const
     {
-        if constexpr (kStaged) {
-            ij = S.ij[local];
-            meta = S.meta[local];
+        int64_t v = 0;
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            v = (int64_t)__hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(G(head)),
+                                                (unsigned long long)batch, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        return v;
+    }
+    __device__ __forceinline__ void init(int64_t* h, int64_t nt, int32_t b, int64_t wave_id, int64_t waves)
+    {
+        head = h;
+        NT = nt;
+        batch = b;
+        stride = waves;
+        req = 0;
+        if (batch <= 0) {
+            cur = wave_id;
+            end = 0;
         } else {
-            ij = regions[r0 + local].ij;
-            meta = regions[r0 + local].meta;
+            cur = (int64_t)uniform64((uint64_t)request());
+            end = cur + batch;
+            req = request();
         }
+    }
+    // the next task id (wavefront-uniform), or -1 when the level's tasks are
+    // all taken
+    __device__ __forceinline__ int64_t take()
+    {
+        int64_t t;
+        if (batch <= 0) {
+            t = cur;
+            cur += stride;
+        } else {
+            if (cur >= end && cur < NT) {
+                cur = (int64_t)uniform64((uint64_t)req);
+                end = cur + batch;
+                if (cur < NT) req = request();
+            }
+            t = cur;
+            if (cur < NT) ++cur;
+        }
+        return (int64_t)uniform64((uint64_t)(t < NT ? t : -1));
     }
 };
 
-// Region marks and staged fields of one tile; returns whether local region 0
-// began in an earlier tile.
-__device__ inline bool stage_tile(uint32_t* bm, StagedRegions& sr, const Region* regions, int64_t t0,
-                                  const TileBounds& tb)
+// A task as a wavefront sees it (all fields wavefront-uniform).
+struct TaskView {
+    int64_t t;       // task id
+    int64_t b;       // first entry in the level's list
+    int32_t n;       // entries
+    int32_t r;       // region
+    int32_t c;       // task index within the region
+    bool last;       // the region's last task
+    bool single;     // the region's only task
+    uint32_t ij, meta;
+};
+
+// Reads task t (scalar loads); false if its fields are out of range.
+__device__ __forceinline__ bool view_task(const Task* tasks, const Region* regions, int64_t P, int64_t L,
+                                          int64_t task_len, int64_t t, TaskView& v)
 {
-    const int nr = tb.r1 - tb.r0 + 1;
-    for (int k = threadIdx.x; k < nr; k += kBlock) {
-        const Region R = regions[tb.r0 + k];
-        const int64_t rel = R.start - t0;
-        if (rel >= 1 && rel < kTile) atomicOr(&bm[rel >> 5], 1u << (rel & 31));
-        if (k < kStage) {
-            sr.ij[k] = R.ij;
-            sr.meta[k] = R.meta;
-        }
+    const Task tk = ld_const(tasks, t);
+    v.t = t;
+    v.r = tk.r;
+    v.c = tk.c;
+    if (tk.r < 0 || tk.r >= P || tk.c < 0 || tk.c > t) return false;
+    const Region R = ld_const(regions, (int64_t)tk.r);
+    const int64_t off = (int64_t)tk.c * task_len;
+    if (off >= R.len || R.start < 0 || R.start + R.len > L) return false;
+    v.b = R.start + off;
+    v.n = (int32_t)std::min<int64_t>(task_len, R.len - off);
+    v.last = off + task_len >= R.len;
+    v.single = tk.c == 0 && v.last;
+    v.ij = R.ij;
+    v.meta = R.meta;
+    return true;
+}
+
+// An entry whose line votes for no region in the code variant: u = 0,
+// v = 65535 is the horizontal parameter line b = 65535, above every corner
+// (b <= 2S <= 32768), so every corner is below it (code 1111).  Lanes past a
+// task's end hold it and need no mask.  The circle variant masks them.
+template <typename Entry, int kVariant>
+__device__ constexpr Entry pad_entry()
+{
+    return kVariant == 0 ? (Entry)0xFFFF0000u : (Entry)0;
+}
+
+// Entries of step s of a task (n entries from b).
+template <typename Entry, int kVariant>
+__device__ __forceinline__ void load_step(const Entry* list, int64_t b, int32_t n, int s, int lane, Entry (&ent)[kStepRows])
+{
+    const Entry* const p = list + b + (int64_t)s * kStep;
+    const int32_t rem = n - s * kStep;
+#pragma unroll
+    for (int k = 0; k < kStepRows; ++k) {
+        const int32_t o = k * kWave + lane;
+        ent[k] = o < rem ? p[o] : pad_entry<Entry, kVariant>();
     }
-    return regions[tb.r0].start < t0;
+}
+
+// Valid lanes of row k of a step with rem entries left (circle variant only).
+__device__ inline uint64_t row_mask(int32_t rem, int k)
+{
+    const int32_t left = rem - k * kWave;
+    return left >= kWave ? ~0ull : (left <= 0 ? 0ull : bits_below(left));
 }
 
 // ------------------------------------------------------------------ k_count
 //
-// Child-vote counts of every region piece of a tile.  A wavefront walks its
-// rows keeping the counts of the region open at the current entry in scalar
-// registers.  A region that begins and ends inside one tile has its total
-// stored in cv at once (by the wavefront where it ends, or by the tile's
-// combine step when it crosses wavefronts); the pieces of a region that
-// crosses tiles are added to cv atomically, and the tile keeps for the
-// compaction pass: head (the piece in the region's first tile), tcar (the
-// piece of the region carried in from earlier tiles) and woff (the votes of
-// each wavefront's first region counted before that wavefront in the tile).
+// One read of every entry: per task, the votes of its lines for each child
+// of its region (the 4-bit code of Sec. 2 and the vote rule of Sec. 3 as
+// lane masks, counted with popcounts in scalar registers).  A task stores
+// its four counts (for the ranks of the compaction pass) and adds them to
+// its region's totals: a plain store when it is the region's only task,
+// atomics otherwise.
 
-// Vote bits (NE, NW, SW, SE in bits 0..3) of the line `point` for the
-// children of a region with constants c, 32-bit compares.  With
-// d_cr = t_c - B_r - 1, corner (c, r) is below iff d_cr >= 0, so a child votes
-// iff the sign bit of ~d_SW & d_NE is set (see code_masks).
-__device__ inline uint32_t code_votes(uint32_t point, const CodeConsts& c, int lc)
-{
-    const int32_t u = (int32_t)(point & 0xFFFFu), v = (int32_t)(point >> 16);
-    const int32_t t0 = (v << lc) - __mul24(u, c.M0);   // |u| < 2^14, |M0| <= 2^15
-    const int32_t du = 2 * u;
-    const int32_t t1 = t0 - du;
-    const int32_t t2 = t1 - du;
-    const int32_t d00 = t0 + c.nB0, d01 = t0 + c.nB1;
-    const int32_t d10 = t1 + c.nB0, d11 = t1 + c.nB1, d12 = t1 + c.nB2;
-    const int32_t d21 = t2 + c.nB1, d22 = t2 + c.nB2;
-    const uint32_t ne = (uint32_t)(~d11 & d22) >> 31;
-    const uint32_t nw = (uint32_t)(~d01 & d12) >> 31;
-    const uint32_t sw = (uint32_t)(~d00 & d11) >> 31;
-    const uint32_t se = (uint32_t)(~d10 & d21) >> 31;
-    return ne | (nw << 1) | (sw << 2) | (se << 3);
-}
-
-struct CountLds {
-    uint32_t bm[kTile / 32];
-    StagedRegions sr;
-    CodeConsts cc[kStage];
-    int32_t wfirst[kWaves][4];   // per wavefront: votes of the region open at its first entry (up to its close)
-    int32_t wlast[kWaves][4];    //   votes of the region open at its end, from that region's start
-    int32_t wlocal[kWaves];      //   local index of that region
-    int32_t wclosed[kWaves];     //   whether the region open at its first entry ended inside it
-};
-
-struct WaveCount {
-    int open;          // local index of the open region
-    bool closed;       // the first region ended inside the wavefront
-    int32_t run[4];    // votes of the open region counted inside the wavefront
-    int32_t first[4];  // votes of the first region inside the wavefront
-    uint32_t vword;    // this lane's vote bits, row k in bits 4k .. 4k+3
-};
-
-__device__ inline uint32_t lane_bits(const uint64_t (&cm)[4], int lane)
-{
-    uint32_t b = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b |= (uint32_t)((cm[q] >> lane) & 1u) << q;
-    return b;
-}
-
-// Vote bits of one lane's line for the children of its region (local index
-// `local`): the staged code constants for 32-bit compares, otherwise the
-// general lane-mask form.
-template <int kVariant, typename CT, bool kStaged>
-__device__ inline uint32_t lane_votes(const RegionSource<kStaged>& src, const CodeConsts* cc, int local,
-                                      uint32_t point, uint64_t vm, int lc, int lane)
-{
-    if constexpr (kVariant == 0 && sizeof(CT) == 4) {
-        // staged: cc is the tile's LDS copy; otherwise the level's table from
-        // region r0.  Lanes past the list end compute on a zero entry and are
-        // masked afterwards (no branch).
-        const uint32_t vb = code_votes(point, cc[local], lc);
-        return ((vm >> lane) & 1u) ? vb : 0u;
-    } else {
-        uint32_t ij, meta;
-        src.fields(local, ij, meta);
-        uint64_t cm[4];
-        child_masks<kVariant, CT>(vm, point, meta, ij, lc, cm);
-        return lane_bits(cm, lane);
-    }
-}
-
-template <typename Entry, int kVariant, typename CT, bool kStaged>
-__device__ __forceinline__ void count_rows(const RegionSource<kStaged>& src, const CodeConsts* cc, const uint32_t* bm,
-                                           const Entry (&ent)[kRows], int64_t rb, int64_t L, int lc, int wave,
-                                           int lane, int nr, int32_t* cv, WaveCount& wc)
-{
-    int open = starts_before(bm, wave, lane);
-    bool open_here = false;   // the open region began inside this wavefront
-    bool closed = false;
-    int32_t run[4] = {0, 0, 0, 0}, first[4] = {0, 0, 0, 0};
-    uint32_t vword = 0;
-    const int lim = (int)std::max<int64_t>(0, std::min<int64_t>(L - rb, kRows * kWave));   // valid entries
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const int left = lim - k * kWave;
-        const uint64_t vm = left >= kWave ? ~0ull : (left <= 0 ? 0ull : bits_below(left));
-        const uint64_t W = row_word(bm, wave * kRows + k);
-        const int local = std::min(open + (int)__popcll(W & ((2ull << lane) - 1)), nr - 1);
-        const uint32_t vb = lane_votes<kVariant, CT, kStaged>(src, cc, local, EntryOps<Entry>::point(ent[k]), vm, lc,
-                                                                lane);
-        vword |= vb << (4 * k);
-        uint64_t cm[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cm[q] = __ballot((vb >> q) & 1u);
-        uint64_t rest = W;
-        int prev = 0;
-        while (rest) {   // regions that end inside this row
-            const int p = __builtin_ctzll(rest);
-            rest &= rest - 1;
-            const uint64_t seg = bits_below(p) & ~bits_below(prev);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & seg);
-            if (open_here) {   // began and ended in this wavefront: its total
-                if (lane == 0)
-                    *reinterpret_cast<int4*>(cv + (int64_t)(src.r0 + open) * 4) = int4{run[0], run[1], run[2], run[3]};
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) first[q] = run[q];
-                closed = true;
-            }
-            ++open;
-            open_here = true;
-            prev = p;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) run[q] = 0;
-        }
-        const uint64_t tail = ~bits_below(prev);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & tail);
-    }
-    wc.open = open;
-    wc.closed = closed;
-    wc.vword = vword;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        wc.run[q] = run[q];
-        wc.first[q] = closed ? first[q] : run[q];
-    }
-}
-
-// Register budgets: k_count at 6 wavefronts per SIMD (80 VGPRs, no spills) and
-// k_write at 7 (65 VGPRs, scalar spills to VGPR lanes only) hide more latency
-// than the compiler's defaults; both measured faster (-7% and -5%).
 template <typename Entry, int kVariant, typename CT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_count(LevelArgs a)
+__device__ __forceinline__ void count_step(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[kStepRows],
+                                           int32_t rem, int lc, int32_t (&acc)[4])
 {
-    __shared__ CountLds S;
+#pragma unroll
+    for (int k = 0; k < kStepRows; ++k) {
+        if (k * kWave >= rem) break;
+        const uint64_t vm = kVariant == 0 ? ~0ull : row_mask(rem, k);
+        uint64_t cm[4];
+        rt.masks(vm, EntryOps<Entry>::point(ent[k]), lc, cm);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += (int32_t)__popcll(cm[q]);
+    }
+}
+
+template <typename Entry, int kVariant, typename CT>
+__global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
+{
     const Arena& ar = a.ar;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = (int)rfl(threadIdx.x / kWave);
     const int l = a.level;
     const int lc = l + 1;
     const uint32_t err = *G(ar.error);
-    const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    LevelInfo* const info = ar.info + l;
+    const int64_t P = info->P, L = info->L, NT = info->NT, steps = info->task_steps;
     if (stopped(err) || P == 0) return;
-    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
-    const WorkLayout wl = work_layout(ar.work, P, L);
-    if (hl.end > ar.half_cap || wl.end > ar.work_cap) {
-        if (tid == 0 && blockIdx.x == 0) raise_error(ar.error, kErrArena);
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, NT, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, NT);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap || steps < 1 || steps > kMaxTaskSteps) {
+        if (threadIdx.x == 0 && blockIdx.x == 0) raise_error(ar.error, kErrArena);
         return;
     }
     const Entry* const list = G(static_cast<const Entry*>(hl.list));
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
-    const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
+    const Task* const tasks = G(static_cast<const Task*>(hl.tasks));
     int32_t* const cv = G(hl.cv);
-    const CodeConsts* const ccg = G(static_cast<const CodeConsts*>(hl.cc));
-    int32_t* const head = G(wl.head);
-    int32_t* const tcar = G(wl.tcar);
-    int32_t* const woff = G(wl.woff);
-    const int64_t nt = cdiv(L, kTile);
-    int64_t tile = blockIdx.x;
-    if (tile >= nt) return;
+    int32_t* const tcnt = G(wl.tcnt);
+    const int64_t task_len = steps * kStep;
 
-    if (tid < kTile / 32) S.bm[tid] = 0u;
-    Entry ent[kRows];
-    load_rows(list, L, tile, wave, lane, ent);
-    TileBounds tb = tile_bounds(tile_first, tile, nt, P);
-    for (;;) {
-        const int64_t next = tile + gridDim.x;
-        const int64_t t0 = tile * kTile;
-        const int64_t rb = t0 + (int64_t)wave * (kRows * kWave);
-        if (!bounds_ok(tb, P)) {
-            if (tid == 0) raise_error(ar.error, kErrInternal);
+    TaskFeed feed;
+    feed.init(&info->queue[0], NT, a.queue_batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves);
+    TaskView cur;
+    {
+        const int64_t t = feed.take();
+        if (t < 0) return;
+        if (!view_task(tasks, regions, P, L, task_len, t, cur)) {
+            if (lane == 0) raise_error(ar.error, kErrInternal);
             return;
         }
-        const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
-        lds_barrier();   // the previous tile is done with S (its bitmap is clear again)
-        const bool carried = stage_tile(S.bm, S.sr, regions, t0, tb);
-        if constexpr (kVariant == 0 && sizeof(CT) == 4)
-            for (int k = tid; k < nr && k < kStage; k += kBlock) S.cc[k] = ccg[r0 + k];
-        lds_barrier();
-        // the next tile's entries and bounds, issued only now: loads complete in
-        // order, so a wait for this tile's region fields would otherwise wait
-        // for them too
-        Entry nent[kRows];
-        load_rows(list, L, next, wave, lane, nent);
-        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
-        WaveCount wc;
-        if (nr <= kStage)
-            count_rows<Entry, kVariant, CT, true>(RegionSource<true>{S.sr, regions, r0}, S.cc, S.bm, ent, rb, L, lc,
-                                                  wave, lane, nr, cv, wc);
-        else
-            count_rows<Entry, kVariant, CT, false>(RegionSource<false>{S.sr, regions, r0}, ccg + r0, S.bm, ent, rb,
-                                                   L, lc, wave, lane, nr, cv, wc);
-        G(wl.vbits)[tile * kBlock + tid] = wc.vword;
-        if (lane < 4) {
-            S.wfirst[wave][lane] = pick4(wc.first, lane);
-            S.wlast[wave][lane] = pick4(wc.run, lane);
-        }
-        if (lane == 0) {
-            S.wlocal[wave] = wc.open;
-            S.wclosed[wave] = wc.closed ? 1 : 0;
-        }
-        lds_barrier();
-        if (tid < 4) {   // one thread per child slot
-            const int q = tid;
-            int cur = 0;
-            bool cur_carried = carried;
-            int32_t cnt = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                woff[(tile * kWaves + w) * 4 + q] = cnt;
-                cnt += S.wfirst[w][q];
-                if (S.wclosed[w]) {
-                    if (cur_carried) {   // the last piece of a region from earlier tiles
-                        tcar[tile * 4 + q] = cnt;
-                        atomicAdd(&cv[(int64_t)r0 * 4 + q], cnt);
-                    } else {
-                        cv[(int64_t)(r0 + cur) * 4 + q] = cnt;   // began and ended in this tile
-                    }
-                    cur = S.wlocal[w];
-                    cur_carried = false;
-                    cnt = S.wlast[w][q];
-                }
-            }
-            // the region open at the tile's end (it may continue in the next tile)
-            if (cur_carried) tcar[tile * 4 + q] = cnt;
-            else head[(int64_t)(r0 + cur) * 4 + q] = cnt;
-            atomicAdd(&cv[(int64_t)(r0 + cur) * 4 + q], cnt);
-        }
-        if (tid < kTile / 32) S.bm[tid] = 0u;   // every wavefront has read the bitmap
-
-        if (next >= nt) break;
-        tile = next;
-        tb = ntb;
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) ent[k] = nent[k];
     }
+    RegionTest<kVariant, CT> rt;
+    rt.set(cur.ij, cur.meta, lc);
+    Entry ent[kStepRows];
+    load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
+    int s = 0;
+    int32_t acc[4] = {0, 0, 0, 0};
+    for (;;) {
+        // the next step: this task's, or the first of the next task
+        const bool more = (s + 1) * kStep < cur.n;
+        TaskView nxt;
+        bool have_next = false;
+        Entry nent[kStepRows];
+        if (more) {
+            load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
+        } else {
+            const int64_t t = feed.take();
+            if (t >= 0) {
+                if (!view_task(tasks, regions, P, L, task_len, t, nxt)) {
+                    if (lane == 0) raise_error(ar.error, kErrInternal);
+                    return;
+                }
+                have_next = true;
+                load_step<Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
+            }
+        }
+        count_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, acc);
+        if (more) {
+            ++s;
+        } else {
+            if (lane < 4) {
+                const int32_t v = pick4(acc, lane);
+                tcnt[cur.t * 4 + lane] = v;
+                if (cur.single) cv[(int64_t)cur.r * 4 + lane] = v;
+                else if (v) atomicAdd(&cv[(int64_t)cur.r * 4 + lane], v);
+            }
+            if (!have_next) break;
+            cur = nxt;
+            rt.set(cur.ij, cur.meta, lc);
+            s = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
+    }
+}
+
+// ------------------------------------------------------------------ k_write
+//
+// Second read of every entry of a region with a kept child.  A vote of the
+// entry for kept child q of its region r goes to dst[r][q] + its rank among
+// the votes of r for q in list order: the votes counted by the region's
+// earlier tasks (summed from tcnt), plus those of the earlier rows of this
+// task (a running count in scalar registers), plus the voting lanes below
+// it in its row (mbcnt).  Ranks are clamped to the child's count so no store
+// leaves the child's slot (the emit step checked every slot against its
+// buffer); the region's last task checks that each kept child got exactly
+// its count, else the call fails with an internal error.  Tasks of regions
+// without a kept child are skipped without reading their entries.
+
+// Kept children of a task's region.  The emit step lays a region's kept
+// children out one after another in quad order (in the next level's list, or
+// in the member buffer at the finest level), so one base pointer serves all
+// four: pos[q] is the slot (counted from base) of the next vote for child q,
+// and every store is clamped into the region's slots [0, total).
+template <typename Entry>
+struct Kids {
+    Entry* base;
+    int32_t pos[4];
+    int32_t total;      // votes of the kept children
+    uint32_t last;      // total - 1, the region's last slot
+    uint32_t keep;      // bit q: child q's voters are kept
+    bool unswap;        // member entries are stored as (x, y) whatever the pass
+};
+
+// Where each kept child's slot starts (from the first kept child's) and
+// the region's kept votes.
+__device__ __forceinline__ void kid_slots(const int32_t (&c)[4], uint32_t keep, int32_t (&lo)[4], int32_t& total)
+{
+    total = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        lo[q] = total;
+        if ((keep >> q) & 1u) total += c[q];
+    }
+}
+
+__device__ __forceinline__ uint32_t keep_bits(const int64_t* dsti, int32_t r)
+{
+    uint32_t keep = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) keep |= (ld_const(dsti, (int64_t)r * 4 + q) >= 0 ? 1u : 0u) << q;
+    return keep;
+}
+
+template <typename Entry>
+__device__ __forceinline__ void load_kids(const TaskView& v, const int64_t* dsti, const int32_t* cvi,
+                                          const int32_t* tcnt, Entry* nlist, Entry* members, Kids<Entry>& k)
+{
+    const bool finest = (v.meta & kMetaChildFinest) != 0;
+    k.unswap = finest && (v.meta & kMetaPass);
+    k.keep = keep_bits(dsti, v.r);
+    const int4 c4 = ld_const(reinterpret_cast<const int4*>(cvi), (int64_t)v.r);
+    const int32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+    int32_t lo[4];
+    kid_slots(c, k.keep, lo, k.total);
+    const int q0 = __builtin_ctz(k.keep | 16u);   // first kept child (keep != 0 here)
+    k.base = (finest ? members : nlist) + (q0 < 4 ? ld_const(dsti, (int64_t)v.r * 4 + q0) : 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) k.pos[q] = lo[q];
+    k.last = (uint32_t)(k.total - 1);
+    if (v.c > 0) {
+        // votes of the region's earlier tasks, by scalar loads: a vector load
+        // here would wait for every store the wavefront still has in flight
+        const int4* const tc = reinterpret_cast<const int4*>(tcnt);
+        for (int64_t t = v.t - v.c; t < v.t; ++t) {
+            const int4 x = ld_const(tc, t);
+            k.pos[0] += x.x;
+            k.pos[1] += x.y;
+            k.pos[2] += x.z;
+            k.pos[3] += x.w;
+        }
+    }
+}
+
+// At a region's last task each kept child must have got exactly its votes.
+template <typename Entry>
+__device__ __forceinline__ bool kids_complete(const TaskView& v, const int32_t* cvi, const Kids<Entry>& k)
+{
+    const int4 c4 = ld_const(reinterpret_cast<const int4*>(cvi), (int64_t)v.r);
+    const int32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
+    int32_t lo[4], total;
+    kid_slots(c, k.keep, lo, total);
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((k.keep >> q) & 1u) ok = ok && k.pos[q] == lo[q] + c[q];
+    return ok;
+}
+
+template <typename Entry, int kVariant, typename CT>
+__device__ __forceinline__ void write_step(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[kStepRows],
+                                           int32_t rem, int lc, int lane, Kids<Entry>& k)
+{
+#pragma unroll
+    for (int r = 0; r < kStepRows; ++r) {
+        if (r * kWave >= rem) break;
+        const uint32_t vb = rt.lane_votes(kVariant == 0 || r * kWave + lane < rem, EntryOps<Entry>::point(ent[r]), lc);
+        const Entry e_out = EntryOps<Entry>::natural(ent[r], k.unswap);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!((k.keep >> q) & 1u)) continue;
+            const bool mine = (vb >> q) & 1u;
+            const uint64_t cm = __ballot(mine);
+            // clamped into the region's slots (pos >= 0 by construction; a
+            // negative value would wrap to a large unsigned one and be clamped)
+            if (mine) k.base[std::min((uint32_t)k.pos[q] + lanes_below(cm), k.last)] = e_out;
+            k.pos[q] += (int32_t)__popcll(cm);
+        }
+    }
+}
+
+template <typename Entry, int kVariant, typename CT>
+__global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
+{
+    const Arena& ar = a.ar;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = (int)rfl(threadIdx.x / kWave);
+    const int l = a.level;
+    const int lc = l + 1;
+    const uint32_t err = *G(ar.error);
+    LevelInfo* const info = ar.info + l;
+    const int64_t P = info->P, L = info->L, NT = info->NT, steps = info->task_steps;
+    if (stopped(err) || P == 0) return;
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, NT, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, NT);
+    if (hl.end > ar.half_cap || wl.end > ar.work_cap || steps < 1 || steps > kMaxTaskSteps) return;
+    // the next level's list and the member buffer were checked by the emit step
+    const LevelInfo* const ni = ar.info + lc;
+    const HalfLayout nx = half_layout(ar.half[lc & 1], ni->P, ni->L, ni->NT, ar.entry_bytes);
+    const Entry* const list = G(static_cast<const Entry*>(hl.list));
+    const Region* const regions = G(static_cast<const Region*>(hl.regions));
+    const Task* const tasks = G(static_cast<const Task*>(hl.tasks));
+    const int64_t* const dsti = G(static_cast<const int64_t*>(wl.dst));
+    const int32_t* const tcnt = G(static_cast<const int32_t*>(wl.tcnt));
+    const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
+    Entry* const nlist = G(static_cast<Entry*>(nx.list));
+    Entry* const members = G(static_cast<Entry*>(ar.members));
+    const int64_t task_len = steps * kStep;
+
+    TaskFeed feed;
+    feed.init(&info->queue[1], NT, a.queue_batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves);
+    bool bad = false;
+    // the next task whose region keeps a child (its id, first entry and
+    // length only: the rest is read again when it becomes current), or -1
+    auto next_task = [&](int64_t& b, int32_t& n) -> int64_t {
+        for (;;) {
+            const int64_t t = feed.take();
+            if (t < 0) return -1;
+            TaskView v;
+            if (!view_task(tasks, regions, P, L, task_len, t, v)) {
+                bad = true;
+                return -1;
+            }
+            if (keep_bits(dsti, v.r)) {
+                b = v.b;
+                n = v.n;
+                return t;
+            }
+        }
+    };
+    int64_t nb = 0;
+    int32_t nn = 0;
+    int64_t t = next_task(nb, nn);
+    if (t >= 0) {
+        TaskView cur;
+        RegionTest<kVariant, CT> rt;
+        Kids<Entry> kc;
+        auto become = [&](int64_t id) {
+            if (!view_task(tasks, regions, P, L, task_len, id, cur)) return false;
+            rt.set(cur.ij, cur.meta, lc);
+            load_kids(cur, dsti, cvi, tcnt, nlist, members, kc);
+            return true;
+        };
+        if (become(t)) {
+            Entry ent[kStepRows];
+            load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
+            int s = 0;
+            for (;;) {
+                const bool more = (s + 1) * kStep < cur.n;
+                int64_t nt = -1;
+                Entry nent[kStepRows];
+                if (more) {
+                    load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
+                } else {
+                    nt = next_task(nb, nn);
+                    if (nt >= 0) load_step<Entry, kVariant>(list, nb, nn, 0, lane, nent);
+                }
+                write_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, lane, kc);
+                if (more) {
+                    ++s;
+                } else {
+                    if (cur.last && !kids_complete(cur, cvi, kc)) bad = true;
+                    if (nt < 0 || !become(nt)) break;
+                    s = 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
+            }
+        } else {
+            bad = true;
+        }
+    }
+    if (bad && lane == 0) raise_error(ar.error, kErrInternal);
 }
 
 // ------------------------------------------------------------------ k_decide / k_emit
@@ -678,8 +767,11 @@ __device__ inline void range_of(int64_t nb, int g, int64_t& b0, int64_t& b1)
     }
 }
 
-// Decision channels of one region from its child votes.
-__device__ inline void decision(const int32_t (&cv)[4], int32_t thr, bool finest, int64_t (&dv)[kAggCh])
+// Decision channels of one region from its child votes: regions, list
+// entries and tasks of the next level (children that split), cells and
+// their voters (children detected at the finest level), votes.
+__device__ inline void decision(const int32_t (&cv)[4], int32_t thr, bool finest, int64_t steps,
+                                int64_t (&dv)[kAggCh])
 {
 #pragma unroll
     for (int c = 0; c < kAggCh; ++c) dv[c] = 0;
@@ -693,13 +785,15 @@ __device__ inline void decision(const int32_t (&cv)[4], int32_t thr, bool finest
             } else {
                 dv[0] += 1;
                 dv[1] += cv[q];
+                dv[5] += region_tasks(cv[q], steps);
             }
         }
     }
 }
 
 __device__ inline void region_decision(const Region* regions, const int32_t* cvi, const TreeDesc* trees, int64_t r,
-                                       Region& R, int32_t (&cv)[4], int32_t& thr, int64_t (&dv)[kAggCh])
+                                       int64_t steps, Region& R, int32_t (&cv)[4], int32_t& thr,
+                                       int64_t (&dv)[kAggCh])
 {
     R = regions[r];
     const int4 c = reinterpret_cast<const int4*>(cvi)[r];
@@ -708,7 +802,7 @@ __device__ inline void region_decision(const Region* regions, const int32_t* cvi
     cv[2] = c.z;
     cv[3] = c.w;
     thr = trees[R.tree].threshold;
-    decision(cv, thr, (R.meta & kMetaChildFinest) != 0, dv);
+    decision(cv, thr, (R.meta & kMetaChildFinest) != 0, steps, dv);
 }
 
 __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
@@ -720,10 +814,10 @@ __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
     const int wave = tid / kWave;
     const int l = a.level;
     const uint32_t err = *G(ar.error);
-    const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    const int64_t P = ar.info[l].P, L = ar.info[l].L, NT = ar.info[l].NT;
     if (stopped(err) || P == 0) return;
-    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
-    const WorkLayout wl = work_layout(ar.work, P, L);
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, NT, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, NT);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;   // k_count raised the error
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
@@ -733,12 +827,12 @@ __global__ __launch_bounds__(kBlock) void k_decide(LevelArgs a)
     for (int g = blockIdx.x; g < kRangeGrid; g += gridDim.x) {
         int64_t b0, b1;
         range_of(nb, g, b0, b1);
-        int64_t acc[kAggCh] = {0, 0, 0, 0, 0};
+        int64_t acc[kAggCh] = {0, 0, 0, 0, 0, 0};
         for (int64_t r = b0 * kBlock + tid; r < std::min(P, b1 * kBlock); r += kBlock) {
             Region R;
             int32_t cv[4], thr;
             int64_t dv[kAggCh];
-            region_decision(regions, cvi, trees, r, R, cv, thr, dv);
+            region_decision(regions, cvi, trees, r, a.task_steps, R, cv, thr, dv);
 #pragma unroll
             for (int c = 0; c < kAggCh; ++c) acc[c] += dv[c];
         }
@@ -779,7 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
     const int l = a.level;
     const int lc = l + 1;
     const uint32_t err = *G(ar.error);
-    const int64_t P = ar.info[l].P, L = ar.info[l].L;
+    const int64_t P = ar.info[l].P, L = ar.info[l].L, NT = ar.info[l].NT;
     if (stopped(err)) return;
     const int64_t cells_base = ar.info[l].cells_base + ar.info[l].cells;
     const int64_t mem_base = ar.info[l].mem_base + ar.info[l].mem;
@@ -788,6 +882,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
             LevelInfo& nx = ar.info[lc];
             nx.P = 0;
             nx.L = 0;
+            nx.NT = 0;
+            nx.task_steps = a.task_steps;
+            nx.queue[0] = nx.queue[1] = 0;
             nx.cells = 0;
             nx.mem = 0;
             nx.cells_base = cells_base;
@@ -795,8 +892,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
         }
         return;
     }
-    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
-    const WorkLayout wl = work_layout(ar.work, P, L);
+    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, NT, ar.entry_bytes);
+    const WorkLayout wl = work_layout(ar.work, P, NT);
     if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
     const int64_t* const agg = G(static_cast<const int64_t*>(wl.agg));
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
@@ -839,15 +936,18 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
             }
             __syncthreads();
         }
-        const int64_t P2 = tot[0], L2 = tot[1];
-        const HalfLayout nx = half_layout(ar.half[lc & 1], P2, L2, ar.entry_bytes);
-        const bool fits = nx.end <= ar.half_cap && work_layout(ar.work, P2, L2).end <= ar.work_cap &&
+        const int64_t P2 = tot[0], L2 = tot[1], NT2 = tot[5];
+        const HalfLayout nx = half_layout(ar.half[lc & 1], P2, L2, NT2, ar.entry_bytes);
+        const bool fits = nx.end <= ar.half_cap && work_layout(ar.work, P2, NT2).end <= ar.work_cap &&
                           cells_base + tot[2] <= ar.cells_cap &&
                           (!a.keep_members || mem_base + tot[3] <= ar.mem_cap);
         if (g == 0 && tid == 0) {
             LevelInfo& ni = ar.info[lc];
             ni.P = P2;
             ni.L = L2;
+            ni.NT = NT2;
+            ni.task_steps = a.task_steps;
+            ni.queue[0] = ni.queue[1] = 0;
             ni.cells = tot[2];
             ni.cells_base = cells_base;
             ni.mem = tot[3];
@@ -857,17 +957,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
         }
         if (!fits) return;
         Region* const nreg = G(nx.regions);
-        int32_t* const ntf = G(nx.tile_first);
+        Task* const ntask = G(nx.tasks);
         int32_t* const ncv = G(nx.cv);
-        const int64_t n_ntiles = cdiv(L2, kTile);
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t r = b * kBlock + tid;
             const bool valid = r < P;
             Region R{};
             int32_t cv[4] = {0, 0, 0, 0};
             int32_t thr = 0;
-            int64_t dv[kAggCh] = {0, 0, 0, 0, 0};
-            if (valid) region_decision(regions, cvi, trees, r, R, cv, thr, dv);
+            int64_t dv[kAggCh] = {0, 0, 0, 0, 0, 0};
+            if (valid) region_decision(regions, cvi, trees, r, a.task_steps, R, cv, thr, dv);
             int64_t ex[kAggCh], inc[kAggCh];
 #pragma unroll
             for (int c = 0; c < kAggCh; ++c) {
@@ -891,7 +990,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                 const TreeDesc T = trees[R.tree];
                 const bool finest = R.meta & kMetaChildFinest;
                 const int32_t pi = (int32_t)(R.ij & 0xFFFFu), pj = (int32_t)(R.ij >> 16);
-                int64_t ri = ex[0], start = ex[1], ci = cells_base + ex[2], mo = mem_base + ex[3];
+                int64_t ri = ex[0], start = ex[1], ci = cells_base + ex[2], mo = mem_base + ex[3], tk = ex[5];
                 int64_t dq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -912,7 +1011,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         if (a.keep_members) dq[q] = mo;
                         mo += cv[q];
                     } else {
-                        if (ri >= P2) {
+                        const int64_t nt = region_tasks(cv[q], a.task_steps);
+                        if (ri >= P2 || tk + nt > NT2) {
                             raise_error(ar.error, kErrInternal);
                             continue;
                         }
@@ -923,11 +1023,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         C.tree = R.tree;
                         C.meta = (R.meta & ~kMetaChildFinest) | (lc + 1 == T.dmax ? kMetaChildFinest : 0u);
                         nreg[ri] = C;
-                        G(nx.cc)[ri] = code_consts(C.ij, C.meta, lc + 1);
                         reinterpret_cast<int4*>(ncv)[ri] = int4{0, 0, 0, 0};
-                        // next-level tiles whose first entry falls inside this region
-                        for (int64_t t = cdiv(start, kTile); t * kTile < start + cv[q] && t < n_ntiles; ++t)
-                            ntf[t] = (int32_t)ri;
+                        for (int64_t k = 0; k < nt; ++k) ntask[tk + k] = Task{(int32_t)ri, (int32_t)k};
+                        tk += nt;
                         dq[q] = start;
                         ++ri;
                         start += cv[q];
@@ -952,260 +1050,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
             for (int c = 0; c < kAggCh; ++c) pre[c] += btot[c];
         }
     }
-}
-
-// ------------------------------------------------------------------ k_write
-//
-// Second read of every entry.  A vote of the entry for child q of its region
-// r goes to dst[r][q] + its rank among the votes of r for q in list order.
-// Within a row the rank is a lane count: for the lanes of the region open at
-// the row's first entry the wavefront's running count plus the lanes below,
-// for a region that begins in the row the lanes below minus the lanes below
-// its first entry.  A wavefront starts its running counts from woff, plus,
-// for a region carried in from earlier tiles, its votes in those tiles
-// (head of its first tile and tcar of the tiles between), so wavefronts never
-// exchange counts.
-
-struct WriteLds {
-    uint32_t bm[2][kTile / 32];  // alternate tiles: one is cleared while the other is in use
-    StagedRegions sr;
-    int64_t dst[kStage][4];
-    int32_t cv[kStage][4];
-    int32_t tpre[4];             // votes of the carried region before this tile
-};
-
-// Child destinations and child votes of local region `local`.
-template <bool kStaged>
-struct KidSource {
-    const int64_t (*s_dst)[4];
-    const int32_t (*s_cv)[4];
-    const int64_t* dsti;
-    const int32_t* cvi;
-    int r0;
-    __device__ int64_t dst(int local, int q) const
-    {
-        if constexpr (kStaged) return s_dst[local][q];
-        else return dsti[(int64_t)(r0 + local) * 4 + q];
-    }
-    __device__ int32_t votes(int local, int q) const
-    {
-        if constexpr (kStaged) return s_cv[local][q];
-        else return cvi[(int64_t)(r0 + local) * 4 + q];
-    }
-};
-
-// Rows of one wavefront.  Per child slot q the open region keeps bq[q], the
-// start of that child's list (in the next level's list, or the member buffer
-// at the finest level), run[q], its votes for q so far, and cv[q], its total
-// votes for q from the count pass (the emit step checked every child's slot
-// [dst, dst + cv) against its buffer).  The lanes voting for q write at
-// run[q] + their rank in the row, the offset clamped to cv[q] - 1 so that no
-// store leaves the child's slot; when a region closes, run must equal cv
-// (else the call fails with an internal error).  A row without a region start
-// continues the open region's counts; in a row where regions start, each lane
-// takes its destination on its own: the lanes of the region open at the row
-// start continue its counts, the others count from their region's first lane
-// in the row.
-template <typename Entry, bool kStaged>
-__device__ __forceinline__ void write_rows(const RegionSource<kStaged>& src, const KidSource<kStaged>& kids,
-                                           const uint32_t* bm, const Entry (&ent)[kRows], uint32_t vword, int wave,
-                                           int lane, int nr, const int32_t (&run0)[4], int open, Entry* nlist,
-                                           Entry* members, bool& bad)
-{
-    Entry* bq[4];
-    int32_t run[4], cv[4];
-    uint32_t keep;     // bit q: child q's voters are kept
-    bool unswap;       // member entries are stored as (x, y) whatever the pass
-    auto open_fields = [&]() {
-        const int o = std::min(open, nr - 1);
-        uint32_t ij, meta;
-        src.fields(o, ij, meta);
-        meta = rfl(meta);
-        const bool finest = meta & kMetaChildFinest;
-        Entry* const out = finest ? members : nlist;
-        unswap = finest && (meta & kMetaPass);
-        keep = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t d = (int64_t)uniform64((uint64_t)kids.dst(o, q));
-            keep |= (d >= 0 ? 1u : 0u) << q;
-            bq[q] = out + (d >= 0 ? d : 0);
-            cv[q] = (int32_t)rfl((uint32_t)kids.votes(o, q));
-            run[q] = 0;
-        }
-    };
-    auto close_check = [&]() {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (((keep >> q) & 1u) && run[q] != cv[q]) bad = true;
-    };
-    open_fields();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) run[q] = run0[q];
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const uint32_t vb = (vword >> (4 * k)) & 15u;
-        uint64_t cm[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cm[q] = __ballot((vb >> q) & 1u);
-        const uint64_t W = row_word(bm, wave * kRows + k);
-        const int starts = (int)__popcll(W);
-        if (starts == 0) {   // the whole row belongs to the open region
-            const Entry e_out = EntryOps<Entry>::natural(ent[k], unswap);
-            const uint32_t vk = vb & keep;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if ((vk >> q) & 1u) bq[q][std::min(run[q] + (int32_t)lanes_below(cm[q]), cv[q] - 1)] = e_out;
-                run[q] += (int32_t)__popcll(cm[q]);
-            }
-            continue;
-        }
-        // a region starts in this row: per-lane destinations
-        const uint64_t le = W & ((2ull << lane) - 1);
-        const bool seg0 = le == 0;
-        const int local = std::min(open + (int)__popcll(le), nr - 1);
-        const int p = seg0 ? 0 : 63 - __builtin_clzll(le);   // first lane of this lane's region in the row
-        uint32_t ij, meta;
-        src.fields(local, ij, meta);
-        uint32_t m[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) m[q] = lanes_below(cm[q]);
-        const uint32_t packed = m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24);
-        const uint32_t at_p = (uint32_t)__shfl((int)packed, p, kWave);
-        const bool finest = meta & kMetaChildFinest;
-        Entry* const out = finest ? members : nlist;
-        const Entry e_out = EntryOps<Entry>::natural(ent[k], finest && (meta & kMetaPass));
-        const uint64_t first = bits_below(__builtin_ctzll(W));   // the lanes of the region open at the row start
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (!((vb >> q) & 1u)) continue;
-            const int32_t rank = (int32_t)m[q] - (int32_t)((at_p >> (8 * q)) & 255u);
-            if (seg0) {
-                if ((keep >> q) & 1u) bq[q][std::min(run[q] + rank, cv[q] - 1)] = e_out;
-            } else {
-                const int64_t d = kids.dst(local, q);
-                if (d >= 0) out[d + std::min(rank, kids.votes(local, q) - 1)] = e_out;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) run[q] += (int32_t)__popcll(cm[q] & first);
-        close_check();
-        open += starts;
-        const int h = 63 - __builtin_clzll(W);
-        open_fields();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) run[q] = (int32_t)__popcll(cm[q] & ~bits_below(h));
-    }
-}
-
-template <typename Entry>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_write(LevelArgs a)
-{
-    __shared__ WriteLds S;
-    const Arena& ar = a.ar;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int l = a.level;
-    const int lc = l + 1;
-    const uint32_t err = *G(ar.error);
-    const int64_t P = ar.info[l].P, L = ar.info[l].L;
-    if (stopped(err) || P == 0) return;
-    const HalfLayout hl = half_layout(ar.half[l & 1], P, L, ar.entry_bytes);
-    const WorkLayout wl = work_layout(ar.work, P, L);
-    if (hl.end > ar.half_cap || wl.end > ar.work_cap) return;
-    // the next level's list and the member buffer were checked by the emit step
-    const HalfLayout nx = half_layout(ar.half[lc & 1], ar.info[lc].P, ar.info[lc].L, ar.entry_bytes);
-    const Entry* const list = G(static_cast<const Entry*>(hl.list));
-    const Region* const regions = G(static_cast<const Region*>(hl.regions));
-    const int32_t* const tile_first = G(static_cast<const int32_t*>(hl.tile_first));
-    const int64_t* const dsti = G(static_cast<const int64_t*>(wl.dst));
-    const int32_t* const head = G(static_cast<const int32_t*>(wl.head));
-    const int32_t* const tcar = G(static_cast<const int32_t*>(wl.tcar));
-    const int32_t* const woff = G(static_cast<const int32_t*>(wl.woff));
-    const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
-    Entry* const nlist = G(static_cast<Entry*>(nx.list));
-    Entry* const members = G(static_cast<Entry*>(ar.members));
-    const int64_t nt = cdiv(L, kTile);
-    int64_t tile = blockIdx.x;
-    if (tile >= nt) return;
-
-    if (tid < kTile / 32) {
-        S.bm[0][tid] = 0u;
-        S.bm[1][tid] = 0u;
-    }
-    const uint32_t* const vbits = G(static_cast<const uint32_t*>(wl.vbits));
-    Entry ent[kRows];
-    load_rows(list, L, tile, wave, lane, ent);
-    uint32_t vword = vbits[tile * kBlock + tid];
-    TileBounds tb = tile_bounds(tile_first, tile, nt, P);
-    bool bad = false;
-    for (int it = 0;; ++it) {
-        const int64_t next = tile + gridDim.x;
-        const int64_t t0 = tile * kTile;
-        if (!bounds_ok(tb, P)) {
-            if (tid == 0) raise_error(ar.error, kErrInternal);
-            return;
-        }
-        const int r0 = tb.r0, nr = tb.r1 - tb.r0 + 1;
-        uint32_t* const bm = S.bm[it & 1];
-        lds_barrier();   // the previous tile is done with S
-        if (tid < kTile / 32) S.bm[(it + 1) & 1][tid] = 0u;   // last read two tiles ago
-        const bool carried = stage_tile(bm, S.sr, regions, t0, tb);
-        for (int k = tid; k < nr && k < kStage; k += kBlock) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) S.dst[k][q] = dsti[(int64_t)(r0 + k) * 4 + q];
-            *reinterpret_cast<int4*>(S.cv[k]) = reinterpret_cast<const int4*>(cvi)[r0 + k];
-        }
-        if (carried && wave == 0) {
-            // votes of the carried region before this tile: its first tile's
-            // piece plus the whole tiles in between
-            const int64_t ts = regions[r0].start / kTile;
-            int32_t c[4] = {0, 0, 0, 0};
-            for (int64_t t = ts + 1 + lane; t < tile; t += kWave) {
-                const int4 v = reinterpret_cast<const int4*>(tcar)[t];
-                c[0] += v.x;
-                c[1] += v.y;
-                c[2] += v.z;
-                c[3] += v.w;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) c[q] = wave_sum32(c[q]);
-            if (lane < 4) S.tpre[lane] = pick4(c, lane) + head[(int64_t)r0 * 4 + lane];
-        }
-        lds_barrier();
-
-        const int open = starts_before(bm, wave, lane);
-        int32_t run[4];
-        {
-            const bool first_carried = open == 0 && carried;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                run[q] = woff[(tile * kWaves + wave) * 4 + q] + (first_carried ? S.tpre[q] : 0);
-        }
-        // the next tile's entries, vote bits and bounds, issued only once this
-        // tile's tables are read (loads complete in order)
-        Entry nent[kRows];
-        load_rows(list, L, next, wave, lane, nent);
-        const uint32_t nvword = next < nt ? vbits[next * kBlock + tid] : 0u;
-        const TileBounds ntb = tile_bounds(tile_first, next, nt, P);
-        if (nr <= kStage)
-            write_rows<Entry, true>(RegionSource<true>{S.sr, regions, r0},
-                                    KidSource<true>{S.dst, S.cv, dsti, cvi, r0}, bm, ent, vword, wave, lane, nr, run,
-                                    open, nlist, members, bad);
-        else
-            write_rows<Entry, false>(RegionSource<false>{S.sr, regions, r0},
-                                     KidSource<false>{S.dst, S.cv, dsti, cvi, r0}, bm, ent, vword, wave, lane, nr,
-                                     run, open, nlist, members, bad);
-
-        if (next >= nt) break;
-        tile = next;
-        tb = ntb;
-        vword = nvword;
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) ent[k] = nent[k];
-    }
-    if (__any(bad) && lane == 0) raise_error(ar.error, kErrInternal);
 }
 
 // Edge staging: nonzero pixels of each image of a batch, row-major.  A
@@ -1522,16 +1366,17 @@ __global__ void k_pack_points(const PointsDesc* lists, int32_t n_lists, int64_t 
 // Root setup: level 0 holds one region per tree whose root splits (every
 // line crosses the root, code 0011, so it splits iff the tree has more than T
 // points and depth > 0), its list the tree's points in input order.
-// k_roots (one workgroup) lays the regions out; k_root_lists writes the lists
-// and the tile map.
+// k_roots (one workgroup) lays the regions and their tasks out;
+// k_root_lists writes the lists.
 constexpr int kRootThreads = 1024;
 
-__global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc* trees, int32_t n_trees)
+__global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc* trees, int32_t n_trees,
+                                                        int32_t task_steps)
 {
-    __shared__ int64_t s_w[kRootThreads / kWave][2];
+    __shared__ int64_t s_w[kRootThreads / kWave][3];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     constexpr int kPer = kMaxTrees / kRootThreads;   // trees per thread
-    int64_t len[kPer], cnt = 0, sum = 0;
+    int64_t len[kPer], cnt = 0, sum = 0, tsum = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int t = tid * kPer + k;
@@ -1542,26 +1387,34 @@ __global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc
         }
         cnt += len[k] > 0;
         sum += len[k];
+        tsum += region_tasks(len[k], task_steps);
     }
     const int64_t ci = wave_incl_scan64(cnt, lane), si = wave_incl_scan64(sum, lane);
+    const int64_t ti = wave_incl_scan64(tsum, lane);
     if (lane == kWave - 1) {
         s_w[wave][0] = ci;
         s_w[wave][1] = si;
+        s_w[wave][2] = ti;
     }
     __syncthreads();
-    int64_t r = ci - cnt, start = si - sum, P0 = 0, L0 = 0;
+    int64_t r = ci - cnt, start = si - sum, tk = ti - tsum, P0 = 0, L0 = 0, NT0 = 0;
     for (int w = 0; w < kRootThreads / kWave; ++w) {
         if (w < wave) {
             r += s_w[w][0];
             start += s_w[w][1];
+            tk += s_w[w][2];
         }
         P0 += s_w[w][0];
         L0 += s_w[w][1];
+        NT0 += s_w[w][2];
     }
     if (tid == 0) {
         LevelInfo& in = ar.info[0];
         in.P = P0;
         in.L = L0;
+        in.NT = NT0;
+        in.task_steps = task_steps;
+        in.queue[0] = in.queue[1] = 0;
         in.votes = 0;
         in.cells = 0;
         in.cells_base = 0;
@@ -1569,8 +1422,8 @@ __global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc
         in.mem_base = 0;
     }
     if (P0 == 0) return;
-    const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
-    if (hl.end > ar.half_cap || work_layout(ar.work, P0, L0).end > ar.work_cap) {
+    const HalfLayout hl = half_layout(ar.half[0], P0, L0, NT0, ar.entry_bytes);
+    if (hl.end > ar.half_cap || work_layout(ar.work, P0, NT0).end > ar.work_cap) {
         if (tid == 0) raise_error(ar.error, kErrArena);
         return;
     }
@@ -1587,8 +1440,10 @@ __global__ __launch_bounds__(kRootThreads) void k_roots(Arena ar, const TreeDesc
         R.meta = (T.pass ? kMetaPass : 0u) | ((uint32_t)T.s_log2 << kMetaSlogShift) |
                  (T.dmax == 1 ? kMetaChildFinest : 0u);
         G(hl.regions)[r] = R;
-        G(hl.cc)[r] = code_consts(R.ij, R.meta, 1);
         reinterpret_cast<int4*>(G(hl.cv))[r] = int4{0, 0, 0, 0};
+        const int64_t nt = region_tasks(len[k], task_steps);
+        for (int64_t c = 0; c < nt; ++c) G(hl.tasks)[tk + c] = Task{(int32_t)r, (int32_t)c};
+        tk += nt;
         ++r;
         start += len[k];
     }
@@ -1602,7 +1457,7 @@ __global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc*
     const uint32_t err = *G(ar.error);
     const int64_t P0 = ar.info[0].P, L0 = ar.info[0].L;
     if (stopped(err) || P0 == 0) return;
-    const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.entry_bytes);
+    const HalfLayout hl = half_layout(ar.half[0], P0, L0, ar.info[0].NT, ar.entry_bytes);
     const Region* const regions = G(static_cast<const Region*>(hl.regions));
     for (int64_t r = threadIdx.x; r < P0; r += kBlock) s_start[r] = regions[r].start;
     __syncthreads();
@@ -1616,7 +1471,6 @@ __global__ __launch_bounds__(kBlock) void k_root_lists(Arena ar, const TreeDesc*
     };
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    for (int64_t t = g; t < cdiv(L0, kTile); t += stride) G(hl.tile_first)[t] = region_of(t * kTile);
     Entry* const list = G(static_cast<Entry*>(hl.list));
     int cur = -1;
     int64_t lo = 0, hi = -1, base = 0;
@@ -1747,18 +1601,18 @@ hipError_t launch_extract(const ExtractArgs& a, hipStream_t s)
 }
 
 hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy,
-                        const int32_t* ids, int grid, hipStream_t s)
+                        const int32_t* ids, int32_t task_steps, int grid, hipStream_t s)
 {
-    if (n_trees > kMaxTrees) return hipErrorInvalidValue;
-    k_roots<<<1, kRootThreads, 0, s>>>(ar, trees, n_trees);
+    if (n_trees > kMaxTrees || task_steps < 1 || task_steps > kMaxTaskSteps) return hipErrorInvalidValue;
+    k_roots<<<1, kRootThreads, 0, s>>>(ar, trees, n_trees, task_steps);
     if (ar.entry_bytes == 8) k_root_lists<uint64_t><<<grid, kBlock, 0, s>>>(ar, trees, xy, ids);
     else k_root_lists<uint32_t><<<grid, kBlock, 0, s>>>(ar, trees, xy, nullptr);
     return hipGetLastError();
 }
 
 // Workgroups of the count / compaction kernels that fit on the device at
-// once: each walks its share of the tiles, so a grid larger than what is
-// resident would run in two rounds.
+// once (each wavefront walks tasks until the level's are all taken, so a
+// larger grid would only queue behind the resident one).
 template <typename K>
 int resident_grid(K kernel, int cu_count)
 {
@@ -1786,7 +1640,7 @@ int level_grid(int which, int variant, bool wide, int entry_bytes, int cu_count)
 {
     const bool ids = entry_bytes == 8;
     if (which == 0) HH_LEVEL_GRID(k_count);
-    return ids ? resident_grid(k_write<uint64_t>, cu_count) : resident_grid(k_write<uint32_t>, cu_count);
+    HH_LEVEL_GRID(k_write);
 }
 
 hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
@@ -1807,10 +1661,9 @@ hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s)
+hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s)
 {
-    if (a.ar.entry_bytes == 8) k_write<uint64_t><<<grid, kBlock, 0, s>>>(a);
-    else k_write<uint32_t><<<grid, kBlock, 0, s>>>(a);
+    HH_LEVEL_LAUNCH(k_write);
     return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@ struct LevelArgs {
     const uint32_t* xy;        // packed edge points
     int32_t level;             // l: the parents' level; children are at l + 1
     int32_t keep_members;      // 0: detected cells get member_off = -1 and keep no voters
+    int32_t task_steps;        // steps per task of the tasks the emit step makes for the next level
+    int32_t queue_batch;       // tasks a wavefront takes from the level's queue at once; 0: fixed share
 };
 
 // Edge staging of a batch of binary images: the nonzero pixels of image k,
@@ -62,24 +64,25 @@ hipError_t launch_extract(const ExtractArgs& a, hipStream_t s);
 // Gray images: Sobel gradients, the two point sets and the trees' ranges, in
 // three launches like launch_extract.
 hipError_t launch_sobel(const SobelArgs& a, hipStream_t s);
-// Root setup: level-0 sizes and root regions of every tree whose root splits
-// (more than T points and depth > 0), from the trees' point ranges; then the
-// root lists (the trees' points in input order) and the level-0 tile map.
+// Root setup: level-0 sizes, root regions and their tasks (task_steps steps
+// each) for every tree whose root splits (more than T points and depth > 0),
+// from the trees' point ranges; then the root lists (the trees' points in
+// input order).
 // With ids != nullptr (8-byte entries) a root entry takes its point id from
 // ids[] instead of its position in the tree's range.
 hipError_t launch_roots(const Arena& ar, const TreeDesc* trees, int32_t n_trees, const uint32_t* xy,
-                        const int32_t* ids, int grid, hipStream_t s);
-// One level: child-vote counts per tile, per-region totals and decisions,
-// the next level's tables, then the compaction of the voters of the kept
-// children (skipped by the host at the finest level without members).
-// Resident workgroups of the count (which = 0) or compaction (which = 1)
-// kernel of the given form on a device with cu_count compute units (the
-// compaction kernel depends on the entry size only).
+                        const int32_t* ids, int32_t task_steps, int grid, hipStream_t s);
+// One level: child-vote counts per task and per-region totals, the split
+// decisions, the next level's region and task tables, then the compaction of
+// the voters of the kept children (skipped by the host at the finest level
+// without members).  Resident workgroups of the count (which = 0) or
+// compaction (which = 1) kernel of the given form on a device with cu_count
+// compute units.
 int level_grid(int which, int variant, bool wide, int entry_bytes, int cu_count);
 hipError_t launch_count(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
 hipError_t launch_decide(const LevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_emit(const LevelArgs& a, int grid, hipStream_t s);
-hipError_t launch_write(const LevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_write(const LevelArgs& a, int variant, bool wide, int grid, hipStream_t s);
 // Point ids of the voters of detected cells (see k_member_ids): cell c's
 // voters are src[cells[c].member_off ...]; they go to dst[dst_off[c] ...], or
 // with dst_off == nullptr to dst[cells[c].member_off - dst_base ...].

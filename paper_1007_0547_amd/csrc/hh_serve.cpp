@@ -1,13 +1,14 @@
 // Continuous batching of detection requests on one context.
 //
 // Each lane is a worker thread with a context of its own (own HIP stream,
-// pool and arena).  A free lane takes the pending requests in arrival order
-// while they fit its admission budget, runs them as one batch, brings every
-// result's cells and statistics to the host and completes the tickets.
-// Requests arriving while batches run wait for the next free lane, so
-// batches of different lanes overlap on the device.  A batch that fails as a
-// whole is run again request by request, so that each request gets its own
-// status.
+// pool and arena): a slot.  A free lane takes the pending requests in
+// arrival order while their predicted device footprint fits what the
+// batches already running leave of the context's device-memory budget, runs
+// them as one batch, brings every result's cells and statistics to the host
+// and completes the tickets.  Requests arriving while batches run are taken
+// by the next lane that is free once memory allows, so batches of different
+// lanes overlap on the device.  A batch that fails as a whole is run again
+// request by request, so that each request gets its own status.
 #include "hh_serve.hpp"
 
 #include <algorithm>
@@ -42,25 +43,46 @@ hh_status capture(F&& f, std::string& error)
     }
 }
 
+// E * 2^depth of a request (E estimated from the edge density seen so far
+// when it is not known).
+double work_units(const Server* sv, const Request& r)
+{
+    const double e = r.points >= 0 ? (double)r.points : sv->density * (double)r.pixels;
+    return std::max(1.0, e) * (double)((int64_t)1 << std::max(0, r.depth));
+}
+
 void run_lane(Server* sv, int lane)
 {
     hh_ctx* c = sv->lanes[(size_t)lane];
     for (;;) {
         std::vector<std::shared_ptr<Request>> batch;
+        int64_t batch_bytes = 0;
+        double units = 0.0;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->work_cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+            auto predicted = [&](const Request& r) { return (int64_t)(sv->beta * work_units(sv, r)); };
+            sv->work_cv.wait(lk, [&] {
+                return sv->stop || (!sv->pending.empty() &&
+                                    (sv->in_flight == 0 || sv->in_flight + predicted(*sv->pending.front()) <= sv->budget));
+            });
             if (sv->stop) return;
             const int32_t kind = sv->pending.front()->in.kind;
-            int64_t cost = 0;
+            int64_t pixels = 0;
             while (!sv->pending.empty() && (int32_t)batch.size() < sv->cfg.max_batch) {
                 const auto& r = sv->pending.front();
                 if (r->in.kind != kind) break;   // one kind per batch
-                if (!batch.empty() && cost + r->cost > sv->cfg.max_batch_pixels) break;
-                cost += r->cost;
+                const int64_t b = predicted(*r);
+                if (!batch.empty() && (sv->in_flight + batch_bytes + b > sv->budget ||
+                                       (sv->cfg.max_batch_pixels > 0 && pixels + r->pixels > sv->cfg.max_batch_pixels)))
+                    break;
+                r->bytes = b;
+                batch_bytes += b;
+                units += work_units(sv, *r);
+                pixels += r->pixels;
                 batch.push_back(r);
                 sv->pending.pop_front();
             }
+            sv->in_flight += batch_bytes;
             if (!sv->pending.empty()) sv->work_cv.notify_one();   // another lane may take the rest
         }
         const Clock::time_point t_start = Clock::now();
@@ -104,6 +126,14 @@ void run_lane(Server* sv, int lane)
         const Clock::time_point t_done = Clock::now();
         {
             std::lock_guard<std::mutex> lk(sv->mu);
+            sv->in_flight -= batch_bytes;
+            // learn the footprint per unit and the edge density from this batch
+            if (c->last_call_bytes > 0 && units > 0.0)
+                sv->beta = std::min(1e4, std::max(0.05, 0.7 * sv->beta + 0.3 * (double)c->last_call_bytes / units));
+            for (int32_t k = 0; k < n; ++k)
+                if (outs[(size_t)k] && batch[(size_t)k]->pixels > 0 && batch[(size_t)k]->in.kind != 0)
+                    sv->density = 0.9 * sv->density +
+                                  0.1 * (double)outs[(size_t)k]->info.n_points / (double)batch[(size_t)k]->pixels;
             for (int32_t k = 0; k < n; ++k) {
                 Request& r = *batch[(size_t)k];
                 r.t_start = t_start;
@@ -119,6 +149,7 @@ void run_lane(Server* sv, int lane)
             }
         }
         sv->done_cv.notify_all();
+        sv->work_cv.notify_all();   // memory freed up: a waiting lane may admit now
     }
 }
 
@@ -127,30 +158,32 @@ void run_lane(Server* sv, int lane)
 hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
 {
     if (ctx->server) throw Error{HH_EINVAL, "the context is already serving"};
+    if (ctx->cfg.arena) throw Error{HH_EINVAL, "a context with a caller arena cannot serve"};
     hh_serve_config cfg{};
     if (cfg_in) cfg = *cfg_in;
     if (cfg.lanes == 0) cfg.lanes = 2;
     if (cfg.max_batch == 0) cfg.max_batch = 32;
-    if (cfg.max_batch_pixels == 0) cfg.max_batch_pixels = (int64_t)1 << 24;
     if (cfg.queue_capacity == 0) cfg.queue_capacity = 4096;
     if (cfg.lanes < 1 || cfg.lanes > 8 || cfg.max_batch < 1 || cfg.max_batch > kMaxTrees ||
-        cfg.max_batch_pixels < 1 || cfg.queue_capacity < 1)
+        cfg.max_batch_pixels < 0 || cfg.queue_capacity < 1)
         throw Error{HH_EINVAL, "bad serving configuration"};
     if ((int64_t)cfg.max_batch * __builtin_popcount(ctx->cfg.passes) > kMaxTrees)
         throw Error{HH_EINVAL, "max_batch times the enabled passes exceeds 2048 trees"};
     auto sv = std::make_unique<Server>();
     sv->cfg = cfg;
-    // the lanes share the context's arena limit
-    int64_t limit_mib = ctx->cfg.arena_limit_mib;
-    if (limit_mib <= 0) {
+    // the device-memory budget of all lanes together; one lane's arena may
+    // take all of it when it runs alone
+    int64_t budget = (int64_t)ctx->cfg.hbm_budget_bytes;
+    if (budget <= 0 && ctx->cfg.arena_limit_mib > 0) budget = (int64_t)ctx->cfg.arena_limit_mib << 20;
+    if (budget <= 0) {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
             (void)hipGetLastError();
             total_b = (size_t)64 << 30;
         }
-        limit_mib = (int64_t)(0.35 * (double)total_b) >> 20;
+        budget = (int64_t)(0.35 * (double)total_b);
     }
-    const int32_t lane_limit_mib = (int32_t)std::max<int64_t>(1, limit_mib / cfg.lanes);
+    sv->budget = budget;
     auto cleanup = [&] {
         for (hh_ctx* l : sv->lanes) engine_destroy(l);
         for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
@@ -165,7 +198,7 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
         sv->streams.push_back(s);
         hh_config lc = ctx->cfg;
         lc.stream = s;
-        lc.arena_limit_mib = lane_limit_mib;
+        lc.hbm_budget_bytes = (uint64_t)budget;
         hh_ctx* lane = nullptr;
         const hh_status st = engine_create(&lc, &lane);
         if (st != HH_OK) {
@@ -173,6 +206,9 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg_in)
             throw Error{st, "lane context creation failed"};
         }
         lane->compact_results = true;   // a queued result holds its cells and voters only
+        lane->task_steps = ctx->task_steps;
+        lane->queue_batch = ctx->queue_batch;
+        lane->wg_per_cu = ctx->wg_per_cu;
         sv->lanes.push_back(lane);
     }
     Server* raw = sv.get();
@@ -189,7 +225,25 @@ hh_status serve_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket)
     if (in->width < 1 || in->height < 1) throw Error{HH_EINVAL, "width and height must be >= 1"};
     auto r = std::make_shared<Request>();
     r->in = *in;
-    r->cost = in->kind != 0 ? (int64_t)in->width * in->height : std::max<int64_t>(in->n_points, 1);
+    r->pixels = in->kind != 0 ? (int64_t)in->width * in->height : std::max<int64_t>(in->n_points, 1);
+    if (in->kind == 0) {
+        r->points = in->n_points;
+    } else if (in->kind == 1 && !in->on_device && in->image) {   // a host binary image: count its edge points
+        const int64_t stride = in->row_stride ? in->row_stride : in->width;
+        int64_t e = 0;
+        for (int32_t y = 0; y < in->height; ++y) {
+            const uint8_t* row = in->image + (int64_t)y * stride;
+            for (int32_t x = 0; x < in->width; ++x) e += row[x] != 0;
+        }
+        r->points = e;
+    }
+    {
+        const int32_t side = std::max(in->width, in->height);
+        int32_t s2 = 0;
+        while ((1 << s2) < side) ++s2;
+        const int32_t d = in->max_depth == INT32_MIN ? ctx->cfg.max_depth : in->max_depth;
+        r->depth = d == 0 ? s2 : std::max(d, 0);
+    }
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(sv->mu);

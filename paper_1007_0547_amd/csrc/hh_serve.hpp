@@ -23,7 +23,10 @@ using Clock = std::chrono::steady_clock;
 struct Request {
     uint64_t ticket = 0;
     hh_input in{};
-    int64_t cost = 0;              // admission cost: image pixels, or points of a list
+    int64_t pixels = 0;            // image pixels, or points of a list
+    int64_t points = -1;           // edge points if known at submission (point lists, host binary images)
+    int32_t depth = 0;             // finest level the request will run to
+    int64_t bytes = 0;             // predicted device footprint, set when a lane admits it
     Clock::time_point t_submit, t_start, t_done;
     bool done = false;
     hh_status status = HH_OK;
@@ -43,6 +46,16 @@ struct Server {
     std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;   // not yet claimed by poll
     uint64_t next_ticket = 1;
     bool stop = false;
+    // admission by device memory: the predicted footprints of the batches
+    // running on the lanes may not exceed `budget` (a batch alone on the
+    // device always runs).  A request's footprint is predicted as
+    // beta * E * 2^depth bytes, with E its edge points (or pixels times the
+    // edge density seen so far); beta and the density are running averages
+    // over completed batches (measured footprint / sum of E * 2^depth).
+    int64_t budget = 0;
+    int64_t in_flight = 0;
+    double beta = 12.0;
+    double density = 0.03;
 };
 
 }  // namespace hh

@@ -11,15 +11,14 @@ namespace hh {
 constexpr int kWave = 64;                   // CDNA wavefront width
 constexpr int kBlock = 256;                 // threads per workgroup (4 wavefronts)
 constexpr int kWaves = kBlock / kWave;
-constexpr int kRows = 8;                    // 64-entry rows per wavefront in a tile
-constexpr int kTileRows = kWaves * kRows;   // 32 rows
-constexpr int kTile = kTileRows * kWave;    // 2048 list entries per tile
-constexpr int kStage = 256;                 // regions of a tile whose fields are staged in LDS
+constexpr int kStepRows = 8;                // 64-entry rows a wavefront holds in registers at once
+constexpr int kStep = kStepRows * kWave;    // 512 list entries
+constexpr int kMaxTaskSteps = 64;           // a task covers 1 .. 64 steps of one region's list
 constexpr int kPixPerThread = 16;           // image bytes per lane in edge staging
 constexpr int kPixTile = kBlock * kPixPerThread;
 constexpr int kMaxLevels = 16;              // depth <= 15
 constexpr int kNumStats = 6;                // evaluated, votes, split, detected, code_tests, entries
-constexpr int kAggCh = 5;                   // decision sums: next regions, next entries, cells, member entries, votes
+constexpr int kAggCh = 6;                   // decision sums: next regions, next entries, cells, member entries, votes, next tasks
 constexpr int kRecCh = 7;                   // tree record: p, start, then the decision prefixes
 constexpr int kRangeGrid = 512;             // region ranges of the split-decision launches
 constexpr int kMaxTrees = 2048;             // trees (image passes) in one call
@@ -92,7 +91,18 @@ struct LevelInfo {
     int64_t cells_base; // cells detected at shallower levels
     int64_t mem;        // voter entries of the cells detected at this level
     int64_t mem_base;   // voter entries of the cells detected at shallower levels
+    int64_t NT;         // tasks over the level's list
+    int64_t task_steps; // steps (kStep entries) per task of this level
+    int64_t queue[2];   // work queue heads of the count and compaction launches
     int64_t pad;
+};
+
+// A task of a level: steps [c * task_steps, (c + 1) * task_steps) of region
+// r's list (the last task of a region may be shorter).  The tasks of a
+// region are consecutive, c = 0, 1, ..., so task t - c is its first.
+struct Task {
+    int32_t r;
+    int32_t c;
 };
 
 // A detected cell; layout equal to the public hh_cell.
@@ -107,53 +117,27 @@ struct Cell {
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t align256(int64_t bytes) { return (bytes + 255) & ~(int64_t)255; }
 
-// The part of the corner test (Sec. 2) a region shares with all its lines,
-// for the 4-bit code variant with 32-bit compares: M0 = M of the first corner
-// column of its children's grid and nB_r = -B_r - 1 for the three corner rows,
-// at the children's level.
-struct CodeConsts {
-    int32_t M0, nB0, nB1, nB2;
-};
-
-__host__ __device__ inline CodeConsts code_consts(uint32_t ij, uint32_t meta, int lc)
-{
-    const int s_log2 = (int)((meta >> 1) & 15u);
-    const int32_t S = 1 << s_log2;
-    const int32_t pi = (int32_t)(ij & 0xFFFFu), pj = (int32_t)(ij >> 16);
-    const int32_t B0 = 6 * S * pj - (S << lc);
-    CodeConsts c;
-    c.M0 = 4 * pi - (1 << lc);
-    c.nB0 = -B0 - 1;
-    c.nB1 = -(B0 + 3 * S) - 1;
-    c.nB2 = -(B0 + 6 * S) - 1;
-    return c;
-}
-
-// A level's data inside its arena half (l & 1): the region table, the tile
-// map, the regions' code constants and the child-vote totals (zeroed),
-// written by the previous level's split decision (or the root setup), then
-// the level's list, written by the previous level's compaction.
-// tile_first[t] is the region holding entry t * kTile; cv[r][q] collects the
-// votes of child q of region r.
+// A level's data inside its arena half (l & 1): the region table, the task
+// table and the child-vote totals (zeroed), written by the previous level's
+// split decision (or the root setup), then the level's list, written by the
+// previous level's compaction.  cv[r][q] collects the votes of child q of
+// region r.
 struct HalfLayout {
     Region* regions;
-    int32_t* tile_first;
-    CodeConsts* cc;
+    Task* tasks;
     int32_t* cv;
     void* list;
     int64_t end;        // bytes used from the half's start
 };
 
-__host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t L, int entry_bytes)
+__host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t L, int64_t NT, int entry_bytes)
 {
     HalfLayout y;
     int64_t off = 0;
     y.regions = reinterpret_cast<Region*>(half + off);
     off += align256(P * (int64_t)sizeof(Region));
-    y.tile_first = reinterpret_cast<int32_t*>(half + off);
-    off += align256((cdiv(L, kTile) + 1) * 4);
-    y.cc = reinterpret_cast<CodeConsts*>(half + off);
-    off += align256(P * (int64_t)sizeof(CodeConsts));
+    y.tasks = reinterpret_cast<Task*>(half + off);
+    off += align256(NT * (int64_t)sizeof(Task));
     y.cv = reinterpret_cast<int32_t*>(half + off);
     off += align256(P * 16);
     y.list = half + off;
@@ -162,42 +146,31 @@ __host__ __device__ inline HalfLayout half_layout(char* half, int64_t P, int64_t
     return y;
 }
 
+// Tasks of a region with n list entries.
+__host__ __device__ inline int64_t region_tasks(int64_t n, int64_t task_steps)
+{
+    return n > 0 ? cdiv(n, task_steps * kStep) : 0;
+}
+
 // Per-level scratch, reused by every level.
-//   head  [P][4]  child votes of a region in the tile where it starts, for
-//                 regions that run past that tile
-//   dst   [P][4]  where the child's voters go (next list or member buffer), -1: dropped
-//   tcar  [nt][4] child votes of the region carried into tile t from earlier tiles
-//   woff  [nt][kWaves][4] child votes of the region open at each wavefront's
-//                 first entry, counted from its first entry in the tile
-//   vbits [nt][kBlock] the vote bits of the count pass for the compaction
-//                 pass: lane t of a tile, bits 4k .. 4k+3 = votes of the
-//                 entry in its wavefront's row k for the children NE, NW, SW, SE
-//   agg   [kRangeGrid][kAggCh] decision sums per range of regions
+//   dst  [P][4]  where the child's voters go (next list or member buffer), -1: dropped
+//   tcnt [NT][4] child votes counted by each task
+//   agg  [kRangeGrid][kAggCh] decision sums per range of regions
 struct WorkLayout {
-    int32_t* head;
     int64_t* dst;
-    int32_t* tcar;
-    int32_t* woff;
-    uint32_t* vbits;
+    int32_t* tcnt;
     int64_t* agg;
     int64_t end;
 };
 
-__host__ __device__ inline WorkLayout work_layout(char* work, int64_t P, int64_t L)
+__host__ __device__ inline WorkLayout work_layout(char* work, int64_t P, int64_t NT)
 {
     WorkLayout w;
-    const int64_t nt = cdiv(L, kTile);
     int64_t off = 0;
-    w.head = reinterpret_cast<int32_t*>(work + off);
-    off += align256(P * 16);
     w.dst = reinterpret_cast<int64_t*>(work + off);
     off += align256(P * 32);
-    w.tcar = reinterpret_cast<int32_t*>(work + off);
-    off += align256(nt * 16);
-    w.woff = reinterpret_cast<int32_t*>(work + off);
-    off += align256(nt * kWaves * 16);
-    w.vbits = reinterpret_cast<uint32_t*>(work + off);
-    off += align256(nt * kBlock * 4);
+    w.tcnt = reinterpret_cast<int32_t*>(work + off);
+    off += align256(NT * 16);
     w.agg = reinterpret_cast<int64_t*>(work + off);
     off += align256((int64_t)kRangeGrid * kAggCh * 8);
     w.end = off;

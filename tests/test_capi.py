@@ -4,6 +4,7 @@ touching a device."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -32,20 +33,37 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     # nothing else with the prefix is exported by accident
-    import subprocess
     out = subprocess.run(["nm", "-D", "--defined-only", hh.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = sorted(set(re.findall(r"\b(hough_hier_\w+)\b", out)))
     assert exported == declared_functions()
 
 
-def test_struct_layouts_match_header():
+def header_sizes(tmp_path):
+    """sizeof of the ABI structs as the C compiler lays them out from the header."""
+    src = tmp_path / "sizes.c"
+    names = ["hh_config", "hh_input", "hh_solution", "hh_cell", "hh_level_stats", "hh_launch",
+             "hh_result_info", "hh_timing", "hh_serve_config"]
+    src.write_text('#include <stdio.h>\n#include "hough_hier.h"\nint main(void) {\n' +
+                   "".join(f'printf("{n} %zu\\n", sizeof({n}));\n' for n in names) + "return 0; }\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+def test_struct_layouts_match_header(tmp_path):
     import paper_1007_0547_amd as hh
-    assert C.sizeof(hh._Config) == 48
-    assert C.sizeof(hh._Input) == 72
-    assert C.sizeof(hh._Solution) == 48
-    assert hh.CELL_DTYPE.itemsize == 32
-    assert hh.STATS_DTYPE.itemsize == 48
+    sz = header_sizes(tmp_path)
+    assert C.sizeof(hh._Config) == sz["hh_config"]
+    assert C.sizeof(hh._Input) == sz["hh_input"]
+    assert C.sizeof(hh._Solution) == sz["hh_solution"]
+    assert C.sizeof(hh._Launch) == sz["hh_launch"]
+    assert C.sizeof(hh._Info) == sz["hh_result_info"]
+    assert C.sizeof(hh._Timing) == sz["hh_timing"]
+    assert C.sizeof(hh._ServeConfig) == sz["hh_serve_config"]
+    assert hh.CELL_DTYPE.itemsize == sz["hh_cell"]
+    assert hh.STATS_DTYPE.itemsize == sz["hh_level_stats"]
 
 
 def test_null_arguments_and_bad_config():

@@ -57,14 +57,34 @@ def test_served_equals_alone(hh):
             assert tm["service_ms"] > 0 and tm["queue_ms"] >= 0
             one = plain.detect(image=w.image, width=w.width, height=w.height, threshold=w.threshold)
             assert_same(view(r), view(one), f"request {k}")
-            if k % 8 == 0:
-                x, y = oracle.edge_points(w.image)
-                ref = oracle.detect(x, y, w.width, w.height, w.threshold, 0)
-                for p in (0, 1):
-                    np.testing.assert_array_equal(r.cells(p)["key"], ref.pass_cells(p)["key"])
-                    np.testing.assert_array_equal(r.stats_array(p), ref.stats[p])
+            # every request against the oracle: cells, statistics and voters
+            x, y = oracle.edge_points(w.image)
+            ref = oracle.detect(x, y, w.width, w.height, w.threshold, 0)
+            members = r.members()
+            for p in (0, 1):
+                got, want = r.cells(p), ref.pass_cells(p)
+                for f in ("i", "j", "key", "votes"):
+                    np.testing.assert_array_equal(got[f], want[f], err_msg=f"request {k} pass {p} {f}")
+                np.testing.assert_array_equal(r.stats_array(p), ref.stats[p])
+                for c in range(len(got)):
+                    o, v, wo = int(got["member_off"][c]), int(got["votes"][c]), int(want["member_off"][c])
+                    np.testing.assert_array_equal(members[o:o + v], ref.members[wo:wo + v],
+                                                  err_msg=f"request {k} pass {p} cell {c}")
             one.free()
             r.free()
+
+
+def test_served_result_errors_carry_their_text(hh):
+    """An error on a served result (made by a serving lane) reports its
+    message through the result."""
+    w = synth.workload("line256", 2)
+    with hh.HoughHier(threshold=w.threshold, max_depth=w.max_depth) as srv:
+        srv.serve_start(lanes=2, max_batch=4)
+        r = srv.poll(srv.submit(image=w.image, width=w.width, height=w.height))
+        with pytest.raises(hh.HHError) as e:
+            r.solution(0)   # hough_hier_solution has not run on it
+        assert e.value.status == -1 and "hough_hier_solution" in str(e.value)
+        r.free()
 
 
 def test_served_failure_stays_with_its_request(hh):
