@@ -427,6 +427,36 @@ HH_API hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_
 HH_API hh_status hough_hier_result_solution_image(hh_result* res, uint8_t* image, int64_t row_stride,
                                                   int32_t on_device);
 
+/* ---- For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ *
+ * hough_hier_detect_noalloc runs one detection like hough_hier_detect (same
+ * cells, voters and statistics) but takes every device buffer it needs from
+ * a fixed scratch array inside the library, HH_NOALLOC_SCRATCH_BYTES per
+ * device (held by each device the library runs on until the process ends),
+ * and calls no device allocation or free.  The caller passes the input and
+ * the output buffers:
+ *   cells    device array of cells_cap hh_cell: the detected cells in
+ *            (pass, key) order, member_off indexing `members`;
+ *   members  device array of members_cap int32 point ids (each cell's voters,
+ *            ascending, cells after cells), or NULL when membership is off;
+ *   stats    host array of 2 * (HH_MAX_DEPTH + 1) hh_level_stats: pass p's
+ *            level l at stats[p * (HH_MAX_DEPTH + 1) + l], zero past the
+ *            finest level and for a pass not enabled;
+ *   n_cells  host int64[2]: detected cells per pass; *n_members: voter ids.
+ * A host input is staged into the scratch by copies.  The call waits until
+ * the outputs are written.  Every call on a device uses that device's one
+ * scratch array (the contents of the last call stay there): calls that
+ * overlap on one device -- on two contexts, or on two threads -- race, so
+ * serialise them.  Calls on one context are serialised by its lock.
+ * Errors: as hough_hier_detect; HH_ECAPACITY when the call needs more scratch
+ * than HH_NOALLOC_SCRATCH_BYTES, or more cells or ids than the output buffers
+ * hold (then n_cells and *n_members report what the call found). */
+#define HH_NOALLOC_SCRATCH_BYTES (256ull << 20)
+HH_API hh_status hough_hier_detect_noalloc(hh_ctx* ctx, const hh_input* in, hh_cell* cells, int64_t cells_cap,
+                                           int32_t* members, int64_t members_cap, hh_level_stats* stats,
+                                           int64_t* n_cells, int64_t* n_members);
+
 /* Text of the last error recorded by a call on res (its accessors, solution
  * and image calls).  Results of a serving context record their errors on the
  * serving lane that made them, not on the context passed to poll, so read

@@ -105,6 +105,7 @@ STATS_DTYPE = np.dtype([("evaluated", np.int64), ("votes", np.int64), ("split", 
 assert CELL_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 48
 
 MAX_DEPTH = 15          # HH_MAX_DEPTH
+NOALLOC_SCRATCH_BYTES = 256 << 20   # HH_NOALLOC_SCRATCH_BYTES
 _p = C.c_void_p
 _lib.hough_hier_create.restype = C.c_int
 _lib.hough_hier_create.argtypes = [C.POINTER(_Config), C.POINTER(_p)]
@@ -147,6 +148,9 @@ _lib.hough_hier_autotune.restype = C.c_int
 _lib.hough_hier_autotune.argtypes = [_p, C.POINTER(_Input), C.c_int32, C.POINTER(_Launch), C.POINTER(C.c_int32)]
 _lib.hough_hier_get_launch.restype = C.c_int
 _lib.hough_hier_get_launch.argtypes = [_p, C.POINTER(_Launch)]
+_lib.hough_hier_detect_noalloc.restype = C.c_int
+_lib.hough_hier_detect_noalloc.argtypes = [_p, C.POINTER(_Input), C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                           C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.hough_hier_result_last_error.restype = C.c_char_p
 _lib.hough_hier_result_last_error.argtypes = [_p]
 _lib.hough_hier_result_free.restype = None
@@ -431,6 +435,34 @@ class HoughHier:
         if s != 0:
             raise HHError(s, self.last_error())
         return Result(self, out.value)
+
+    def detect_noalloc(self, x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int,
+                       height: int, threshold: int = -1, max_depth: Optional[int] = None, cells_out,
+                       members_out=None) -> dict:
+        """``hough_hier_detect_noalloc``: one detection in the library's fixed
+        device scratch, cells and voter ids written to the caller's torch
+        device tensors ``cells_out`` (uint8, 32 bytes per cell) and
+        ``members_out`` (int32).  Returns the counts and the statistics."""
+        assert _is_torch_cuda(cells_out) and cells_out.is_contiguous()
+        inp, keep = self._input(x, y, image=image, gray=gray, edge_threshold=edge_threshold, width=width,
+                                height=height, threshold=threshold, max_depth=max_depth)
+        nst = 2 * (MAX_DEPTH + 1)
+        stats = np.zeros(nst * 6, dtype=np.int64)
+        n_cells = (C.c_int64 * 2)()
+        n_members = C.c_int64()
+        mptr, mcap = None, 0
+        if members_out is not None:
+            assert _is_torch_cuda(members_out) and members_out.is_contiguous()
+            mptr, mcap = members_out.data_ptr(), members_out.numel()
+        s = _lib.hough_hier_detect_noalloc(self._h, C.byref(inp), C.c_void_p(cells_out.data_ptr()),
+                                           cells_out.numel() * cells_out.element_size() // CELL_DTYPE.itemsize,
+                                           mptr, mcap, stats.ctypes.data, n_cells, C.byref(n_members))
+        del keep
+        if s != 0:
+            raise HHError(s, self.last_error())
+        st = stats.reshape(2, MAX_DEPTH + 1, 6)
+        return {"n_cells": [n_cells[0], n_cells[1]], "n_members": n_members.value,
+                "stats": {p: st[p] for p in (0, 1)}}
 
     def detect_batch(self, inputs) -> list:
         """Run the vote on several inputs of one kind in one call

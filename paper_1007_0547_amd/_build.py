@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhough_hier.so")
-SOURCES = ["hh_kernels.hip", "hh_solution.hip", "hh_engine.cpp", "hh_serve.cpp", "hh_tune.cpp",
+SOURCES = ["hh_kernels.hip", "hh_solution.hip", "hh_noalloc.hip", "hh_engine.cpp", "hh_serve.cpp", "hh_tune.cpp",
            "hh_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

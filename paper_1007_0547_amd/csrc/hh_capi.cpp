@@ -146,6 +146,20 @@ hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out)
     return guarded(ctx, [&] { return hh::engine_detect(ctx, in, out); });
 }
 
+hh_status hough_hier_detect_noalloc(hh_ctx* ctx, const hh_input* in, hh_cell* cells, int64_t cells_cap,
+                                    int32_t* members, int64_t members_cap, hh_level_stats* stats, int64_t* n_cells,
+                                    int64_t* n_members)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!in || !stats || !n_cells || !n_members)
+        return fail(ctx, HH_EINVAL, "input, stats and count pointers must not be NULL");
+    clear_error(ctx);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return guarded(ctx, [&] {
+        return hh::engine_detect_noalloc(ctx, in, cells, cells_cap, members, members_cap, stats, n_cells, n_members);
+    });
+}
+
 hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh_result** out)
 {
     if (!ctx) return HH_EINVAL;

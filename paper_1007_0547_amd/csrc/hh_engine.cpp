@@ -308,6 +308,7 @@ hh_status engine_create(const hh_config* cfg, hh_ctx** out)
             }
         }
         ctx->grid = std::max(1, ctx->cu_count) * 8;
+        noalloc_scratch(cfg->device);   // the device address of the fixed scratch, once per device
         const FixedLayout f = fixed_layout(kMaxTrees, 0);
         check(hipHostMalloc((void**)&ctx->h_fixed, (size_t)f.head_bytes, hipHostMallocDefault), "hipHostMalloc");
         check(hipHostMalloc((void**)&ctx->h_call, (size_t)call_layout(kMaxTrees * 2, kMaxTrees).bytes,
@@ -1145,6 +1146,70 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         ctx->live_results.insert(out[k]);
         if (out[k]->in_arena) ++ctx->arena_results;
     }
+    return HH_OK;
+}
+
+hh_status engine_detect_noalloc(hh_ctx* ctx, const hh_input* in, hh_cell* cells, int64_t cells_cap,
+                                int32_t* members, int64_t members_cap, hh_level_stats* stats, int64_t* n_cells,
+                                int64_t* n_members)
+{
+    check(hipSetDevice(ctx->device), "hipSetDevice");
+    if (cells_cap < 0 || members_cap < 0 || (cells_cap > 0 && !cells) || (members_cap > 0 && !members))
+        throw Error{HH_EINVAL, "bad output buffers"};
+    CallMem mem;
+    mem.base = static_cast<char*>(noalloc_scratch(ctx->device));
+    mem.cap = kNoAllocScratchBytes;
+    hh_result* raw = nullptr;
+    engine_detect_batch(ctx, in, 1, &raw, &mem);
+    // the result lives only for this call
+    {
+        std::lock_guard<std::mutex> g(ctx->results_mu);
+        ctx->live_results.erase(raw);
+    }
+    std::unique_ptr<hh_result> r(raw);
+    const hh_result_info& info = r->info;
+    const int64_t nc = r->n_cells_total;
+    // voters, compact: a depth-0 cell holds every point
+    const int64_t nm = !r->have_members ? 0 : r->depth0 ? (int64_t)info.n_points * nc : info.member_slots;
+    n_cells[0] = info.n_cells[0];
+    n_cells[1] = info.n_cells[1];
+    *n_members = nm;
+    for (int p = 0; p < 2; ++p)
+        for (int l = 0; l <= HH_MAX_DEPTH; ++l)
+            stats[p * (HH_MAX_DEPTH + 1) + l] =
+                l < (int)r->stats[p].size() ? r->stats[p][(size_t)l] : hh_level_stats{};
+    if (nc > cells_cap) throw Error{HH_ECAPACITY, "the cell buffer holds " + std::to_string(cells_cap) +
+                                                      " cells; the call found " + std::to_string(nc)};
+    if (r->have_members && members && nm > members_cap)
+        throw Error{HH_ECAPACITY, "the member buffer holds " + std::to_string(members_cap) +
+                                      " ids; the call found " + std::to_string(nm)};
+    hipStream_t st = ctx->stream;
+    if (r->depth0) {
+        // the root is the only level: one cell per pass, every point votes
+        hh_cell h[2]{};
+        int64_t c = 0;
+        for (int p = 0; p < 2; ++p) {
+            if (info.n_cells[p] == 0) continue;
+            h[c].votes = (int32_t)info.n_points;
+            h[c].pass = p;
+            h[c].member_off = r->have_members ? c * info.n_points : -1;
+            ++c;
+        }
+        if (nc > 0) check(hipMemcpyAsync(cells, h, (size_t)nc * sizeof(hh_cell), hipMemcpyHostToDevice, st), "cells");
+        if (r->have_members && members)
+            for (int64_t c = 0; c < nc; ++c)
+                check(launch_iota(members + c * info.n_points, info.n_points, st), "member ids");
+    } else if (nc > 0) {
+        // cells after cells, voters dense: member_off counted from the image's first voter
+        check(launch_rebase_cells(r->cells, nc, r->have_members ? r->mem_base : 0, reinterpret_cast<Cell*>(cells),
+                                  st),
+              "cells");
+        if (r->have_members && members)
+            check(launch_member_ids(r->cells, nc, nullptr, r->mem_base, r->members_base, r->entry_bytes, r->xy,
+                                    info.n_points, members, st),
+                  "member ids");
+    }
+    sync(ctx);
     return HH_OK;
 }
 

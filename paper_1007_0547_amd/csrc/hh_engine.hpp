@@ -228,9 +228,19 @@ hh_status engine_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
 // allocation) and its results are not counted as the caller arena's.
 hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* in, int32_t n, hh_result** out,
                               CallMem* ext = nullptr);
+// One detection whose device memory is the library's fixed scratch array of
+// this device (hough_hier_detect_noalloc): outputs go to the caller's
+// buffers; nothing is allocated on the device.
+hh_status engine_detect_noalloc(hh_ctx* ctx, const hh_input* in, hh_cell* cells, int64_t cells_cap,
+                                int32_t* members, int64_t members_cap, hh_level_stats* stats, int64_t* n_cells,
+                                int64_t* n_members);
 // Autotuner (hh_tune.cpp): the launch shape for calls like in[0 .. n), from
 // the cache or by timing candidates on this call; set on ctx and returned.
 hh_status engine_autotune(hh_ctx* ctx, const hh_input* in, int32_t n, hh_launch* chosen, int32_t* from_cache);
+// The fixed scratch array of the current device (its device address, taken
+// once per device with hipGetSymbolAddress) and its size.
+void* noalloc_scratch(int device);
+extern const int64_t kNoAllocScratchBytes;
 hh_status engine_host_cells(hh_result* res);
 hh_status engine_host_members(hh_result* res);
 hh_status engine_device_ids(hh_result* res);
