@@ -177,11 +177,15 @@ def cpu_baseline(w, budget_s=10.0, split=4):
             "host_cpu": model, "host_threads": os.cpu_count()}
 
 
-def bench_batched(seed, reps=3):
+def bench_batched(seed, reps=3, arena_gb=160, variants=("pool", "tuned", "graph", "plain")):
     """The 512-image batch (sides log-uniform in 128..2048, Poisson(24)
     segments, noise U[0.5%, 3%], T = floor(side / 10), depth
-    ceil(log2(side))): one hough_hier_detect_batch call per step against the
-    same images in one hough_hier_detect call each."""
+    ceil(log2(side))), resident in HBM.  Per step one
+    hough_hier_detect_batch call over all 512 images, against the same
+    images in one hough_hier_detect call each.  Batched forms: the library's
+    pool (the batch runs in groups under its memory budget), the launch
+    shape from the autotuner, and one group in a caller arena of `arena_gb`
+    GB with the level launches captured once into a HIP graph and replayed."""
     import numpy as np
     import torch
 
@@ -194,36 +198,73 @@ def bench_batched(seed, reps=3):
     imgs = [torch.from_numpy(w.image).to(dev) for w in ws]
     inputs = [dict(image=d, width=w.width, height=w.height, threshold=w.threshold)
               for d, w in zip(imgs, ws)]
-    ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
-    for _ in range(2):   # the first call learns the arena sizes and groups
-        for r in ctx.detect_batch(inputs):
-            r.free()
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def timed(ctx, warm=2):
+        for _ in range(warm):   # the first calls learn the arena sizes and groups
+            for r in ctx.detect_batch(inputs):
+                r.free()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rs = ctx.detect_batch(inputs)
+            for r in rs:
+                r.free()
+        torch.cuda.synchronize(dev)
+        dt = (time.perf_counter() - t0) / reps
         rs = ctx.detect_batch(inputs)
+        t = rs[0].timing()
+        info = [r.info for r in rs]
         for r in rs:
             r.free()
-    torch.cuda.synchronize(dev)
-    batch_s = (time.perf_counter() - t0) / reps
-    rs = ctx.detect_batch(inputs)
-    code_tests = sum(r.info["code_tests"] for r in rs)
-    points = sum(r.info["n_points"] for r in rs)
-    cells = sum(sum(r.info["n_cells"]) for r in rs)
-    tmb = rs[0].timing()
-    for r in rs:
-        r.free()
+        return dt, t, info
+
+    ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
+    batch_s, tmb, info = timed(ctx)
+    code_tests = sum(i["code_tests"] for i in info)
+    points = sum(i["n_points"] for i in info)
+    cells = sum(sum(i["n_cells"]) for i in info)
     ctx.close()
 
     ctx_t = HoughHier(threshold=0, membership=True, device=0, stream=stream, timing=True)
-    for _ in range(2):
-        for r in ctx_t.detect_batch(inputs):
-            r.free()
-    rs = ctx_t.detect_batch(inputs)
-    kt = rs[0].timing()
-    for r in rs:
-        r.free()
+    _, kt, _ = timed(ctx_t, warm=2)
     ctx_t.close()
+    out = {
+        "workload": f"512 images, seed {seed}, sides log-uniform 128..2048 "
+                    f"(max side {max(max(w.width, w.height) for w in ws)}), "
+                    "Poisson(24) segments, noise U[0.5%,3%], T=floor(side/10), depth ceil(log2 side), "
+                    "both passes, voters kept on device",
+        "edge_points": points, "cells": cells, "code_tests": code_tests,
+        "batched": {"ms_per_batch": batch_s * 1e3, "images_per_s": 512 / batch_s,
+                    "code_tests_per_s": code_tests / batch_s, "groups": tmb["groups"],
+                    "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"],
+                                  "decide": kt["decide_ms"], "extract": kt["extract_ms"]},
+                    "vote_entries": kt["vote_entries"], "vote_written": kt["vote_written"]},
+        "entry_bytes_model": {k: {"bytes": v, "GB/s": v / (kt[f"{k}_ms"] / 1e3) / 1e9,
+                                  "frac": v / (kt[f"{k}_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+                              for k, v in kernel_bytes(kt, 4).items()},
+    }
+    if "tuned" not in variants:
+        return out
+
+    ctx_a = HoughHier(threshold=0, membership=True, device=0, stream=stream)
+    tuned = ctx_a.autotune(inputs)
+    tuned_s, _, _ = timed(ctx_a)
+    ctx_a.close()
+
+    graph = None
+    try:
+        arena = torch.empty(int(arena_gb * 1e9), dtype=torch.uint8, device=dev)
+        side = torch.cuda.Stream(dev)
+        torch.cuda.synchronize(dev)
+        ctx_g = HoughHier(threshold=0, membership=True, device=0, stream=side, arena=arena, graph=True)
+        ctx_g.set_launch(**{k: tuned[k] for k in ("task_steps", "queue_batch", "wg_per_cu")})
+        graph_s, tg, _ = timed(ctx_g)
+        graph = {"ms_per_batch": graph_s * 1e3, "images_per_s": 512 / graph_s,
+                 "graph_replayed": tg["graph_replayed"], "arena_gb": arena_gb, "groups": tg["groups"]}
+        ctx_g.close()
+        del arena
+    except Exception as e:   # not enough device memory for one group: reported, not fatal
+        graph = {"error": str(e)}
 
     ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
     for inp in inputs:   # one untimed pass: the arena reaches the sizes the largest images need
@@ -238,26 +279,17 @@ def bench_batched(seed, reps=3):
     torch.cuda.synchronize(dev)
     plain_s = time.perf_counter() - t0
     ctx.close()
-    sides = [max(w.width, w.height) for w in ws]
-    return {
-        "workload": f"512 images, seed {seed}, sides log-uniform 128..2048 (max side {max(sides)}), "
-                    "Poisson(24) segments, noise U[0.5%,3%], T=floor(side/10), depth ceil(log2 side), "
-                    "both passes, voters kept on device",
-        "edge_points": points, "cells": cells, "code_tests": code_tests,
-        "batched": {"ms_per_batch": batch_s * 1e3, "images_per_s": 512 / batch_s,
-                    "code_tests_per_s": code_tests / batch_s, "groups": tmb["groups"],
-                    "kernel_ms": {"count": kt["count_ms"], "write": kt["write_ms"],
-                                  "decide": kt["decide_ms"], "extract": kt["extract_ms"]},
-                    "vote_entries": kt["vote_entries"], "vote_written": kt["vote_written"]},
+    best = min(batch_s, tuned_s, graph.get("ms_per_batch", 1e30) / 1e3)
+    out.update({
+        "batched_autotuned": {"launch": tuned, "ms_per_batch": tuned_s * 1e3, "images_per_s": 512 / tuned_s},
+        "batched_arena_graph": graph,
         "plain": {"s_per_512": plain_s, "images_per_s": 512 / plain_s,
                   "code_tests_per_s": code_tests / plain_s,
                   "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                  "p99": float(np.percentile(lat, 99) * 1e3)}},
-        "batched_over_plain": plain_s / batch_s,
-        "roofline": {k: {"alg_bytes": v, "GB/s": v / (kt[f"{k}_ms"] / 1e3) / 1e9,
-                         "frac": v / (kt[f"{k}_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}
-                     for k, v in kernel_bytes(kt, 4).items()},
-    }
+        "batched_over_plain": plain_s / best,
+    })
+    return out
 
 
 def solution_bytes(r):
@@ -446,15 +478,18 @@ def bench_gray(seed, reps=20):
             "code_tests_per_s": info["code_tests"] / (ms / 1e3)}
 
 
-def bench_serving(seed, seconds, pool_size=128):
-    """Serving: Poisson arrivals of images (sides log-uniform 256..4096,
-    Poisson(48) segments, 1% noise, T = floor(side / 10), default depth),
-    drawn in turn from a pool of `pool_size` images of that distribution
-    resident on the device.  Each rate runs `seconds` of arrivals through
-    (a) continuous batching (2 lanes, up to 32 requests and 2^24 pixels per
-    batch) and (b) per-request plain launches (1 lane, batches of 1).  The
-    rates are 0.9x and 1.5x the measured plain capacity.  Latency = arrival
-    to cells and statistics on the host, measured inside the library."""
+def bench_serving(seed, seconds, pool_size=384, lanes=3):
+    """Serving: a Poisson stream of requests for `seconds` seconds per rate,
+    images drawn in turn from a pool of `pool_size` distinct images of the
+    serving distribution (sides log-uniform 256..4096, Poisson(48) segments,
+    1% noise, T = floor(side / 10), default depth) resident on the device.
+    The capacity is measured first: a burst of requests through per-request
+    launches (one lane, batches of one) until the queue drains.  Then, at
+    0.9x and 1.5x that capacity, the same arrivals go through (a) continuous
+    batching (`lanes` lanes, admission by predicted device memory) and (b)
+    per-request launches.  Latency = arrival to cells and statistics on the
+    host, measured inside the library; p50 / p99 over the requests of the
+    stream."""
     import queue
     import threading
 
@@ -471,38 +506,15 @@ def bench_serving(seed, seconds, pool_size=128):
     torch.cuda.synchronize(dev)
     inputs = [dict(image=d, width=w.width, height=w.height, threshold=w.threshold) for d, w in zip(imgs, pool)]
 
-    # plain capacity: back-to-back single calls over the pool, cells and
-    # statistics brought to the host as a served request's are
-    def plain_one(c, inp):
-        r = c.detect(**inp)
-        r.cells(0)
-        r.cells(1)
-        r.free()
-
-    ctx = HoughHier(threshold=0, membership=True, device=0)
-    for inp in inputs:
-        plain_one(ctx, inp)
-    t0 = time.perf_counter()
-    for _ in range(2):
-        for inp in inputs:
-            plain_one(ctx, inp)
-    capacity = 2 * len(inputs) / (time.perf_counter() - t0)
-    ctx.close()
-
-    def run(rate, lanes, max_batch, burst=0):
-        rng = np.random.default_rng(seed + 1)
-        if burst:   # every request at once: the sustained throughput
-            arrivals = np.zeros(burst)
-        else:
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
-            arrivals = arrivals[arrivals < seconds]
+    def server(n_lanes, max_batch):
         srv = HoughHier(threshold=0, membership=True, device=0)
-        srv.serve_start(lanes=lanes, max_batch=max_batch, max_batch_pixels=1 << 24,
-                        queue_capacity=max(4096, len(arrivals) + 16))
-        for _ in range(3):   # warm the lanes: arena sizes and group limits for full batches
-            warm = [srv.submit(**inp) for inp in inputs]
-            for t in warm:
+        srv.serve_start(lanes=n_lanes, max_batch=max_batch, queue_capacity=1 << 16)
+        for _ in range(2):   # warm the lanes: arena sizes, group limits, the footprint model
+            for t in [srv.submit(**inp) for inp in inputs]:
                 srv.poll(t).free()
+        return srv
+
+    def run(srv, arrivals):
         tickets = queue.Queue()
         lat, failed = [], []
 
@@ -533,28 +545,37 @@ def bench_serving(seed, seconds, pool_size=128):
         tickets.put(None)
         th.join()
         wall = time.perf_counter() - t0
-        srv.close()
-        res = {"requests": len(arrivals), "images_per_s": len(lat) / wall,
+        res = {"requests": len(arrivals), "completed": len(lat), "images_per_s": len(lat) / wall,
+               "wall_s": wall,
                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}}
         if failed:
             res["failed"] = len(failed)
             res["first_failure"] = failed[0]
         return res
 
-    out = {"workload": f"Poisson arrivals for {seconds:g} s per rate; images from a pool of {len(pool)} "
-                       f"(seed {seed}): sides log-uniform 256..4096, Poisson(48) segments, 1% noise, "
+    plain = server(1, 1)
+    burst = run(plain, np.zeros(2 * len(inputs)))
+    capacity = burst["images_per_s"]
+    batching = server(lanes, 32)
+    out = {"workload": f"Poisson arrivals for {seconds:g} s per rate; images in turn from a pool of {len(pool)} "
+                       f"distinct images (seed {seed}): sides log-uniform 256..4096, Poisson(48) segments, 1% noise, "
                        "T=floor(side/10), depth ceil(log2 side), both passes, voters kept on device",
            "mean_edge_points": float(np.mean([np.count_nonzero(w.image) for w in pool])),
-           "plain_capacity_images_per_s": capacity, "rates": {}}
+           "capacity": {"what": "per-request launches (1 lane, batches of 1) under a burst of "
+                                f"{2 * len(inputs)} requests", "images_per_s": capacity,
+                        "latency_ms": burst["latency_ms"]},
+           "continuous_batching_burst": run(batching, np.zeros(2 * len(inputs))),
+           "rates": {}}
     for f in (0.9, 1.5):
         rate = f * capacity
+        rng = np.random.default_rng(seed + 1)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
+        arrivals = arrivals[arrivals < seconds]
         out["rates"][f"{f}x"] = {"arrival_rate_hz": rate,
-                                 "continuous_batching": run(rate, 2, 32),
-                                 "plain_per_request": run(rate, 1, 1)}
-    n_burst = 4 * len(inputs)
-    out["burst"] = {"requests": n_burst,
-                    "continuous_batching": run(0, 2, 32, burst=n_burst),
-                    "plain_per_request": run(0, 1, 1, burst=n_burst)}
+                                 "continuous_batching": run(batching, arrivals),
+                                 "per_request": run(plain, arrivals)}
+    batching.close()
+    plain.close()
     return out
 
 
@@ -622,6 +643,43 @@ def bench_single(name, seed, steps, warmup, variant="code", wide=False, kernel_s
             "alg_bytes": algorithmic_bytes(stats, det_votes, E)}
 
 
+def bench_small_graph(seed, steps=300):
+    """The launch-bound 256x256 image (line256: 8 full-span lines, 1% noise,
+    T = 40, depth 8, both passes) one call per image, three ways: the
+    library's pool; a caller arena; a caller arena with the level launches
+    replayed from a captured HIP graph (HH_FLAG_GRAPH).  Wall time per image
+    over `steps` calls (each result's cells brought to the host and freed)."""
+    import torch
+
+    import synth
+    from paper_1007_0547_amd import HoughHier
+
+    dev = torch.device("cuda:0")
+    w = synth.workload("line256", seed)
+    img = torch.from_numpy(w.image).to(dev)
+    side = torch.cuda.Stream(dev)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize(dev)
+    out = {"workload": f"line256: 256x256, seed {seed}, T={w.threshold}, depth {w.max_depth}, both passes, "
+                       "cells to the host per call"}
+    for name, kw in (("pool", {}), ("arena", {"arena": arena}), ("arena_graph", {"arena": arena, "graph": True})):
+        ctx = HoughHier(threshold=w.threshold, max_depth=w.max_depth, device=0, stream=side, **kw)
+        replays = 0
+        for k in range(steps + 5):
+            if k == 5:
+                torch.cuda.synchronize(dev)
+                t0 = time.perf_counter()
+                replays = 0
+            r = ctx.detect(image=img, width=w.width, height=w.height)
+            r.cells(0)
+            replays += r.timing()["graph_replayed"]
+            r.free()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_image": dt * 1e3, "images_per_s": 1.0 / dt, "graph_replays": replays}
+        ctx.close()
+    return out
+
+
 def single_summary(b):
     """The extra-block form of a bench_single run."""
     kt = b["kt"]
@@ -656,6 +714,11 @@ def main():
     ap.add_argument("--no-solution", action="store_true", help="skip solution() with point removal")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window per rate of the serving run (0 skips it)")
+    ap.add_argument("--only", default="", choices=["", "batch512", "seg1024", "line256", "line256_graph", "serving",
+                                                   "solution"],
+                    help="run only this extra block (printed as its own JSON line), e.g. for a profiler")
+    ap.add_argument("--batch-variants", default="pool,tuned,graph,plain",
+                    help="with --only batch512: which batched forms to run (pool only for a profiler)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times), the "
                          "reference kernel for scaling HBM byte counters")
@@ -670,7 +733,7 @@ def main():
 
     # the CPU baseline forks a process pool, so it runs before the GPU is touched
     cpu = None
-    if not args.no_cpu_baseline and not args.calibrate_copy:
+    if not args.no_cpu_baseline and not args.calibrate_copy and not args.only:
         cpu = cpu_baseline(synth.workload(args.workload, args.seed))
 
     import torch
@@ -683,6 +746,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
+
+    if args.only:
+        fn = {"batch512": lambda: bench_batched(args.seed, variants=args.batch_variants.split(",")),
+              "seg1024": lambda: single_summary(bench_single("seg1024", args.seed, args.steps, args.warmup)),
+              "line256": lambda: single_summary(bench_single("line256", args.seed, args.steps, args.warmup)),
+              "line256_graph": lambda: bench_small_graph(args.seed),
+              "serving": lambda: bench_serving(args.seed, args.serve_seconds),
+              "solution": lambda: bench_solution(args.seed)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
         return
 
     b = bench_single(args.workload, args.seed, args.steps, args.warmup, args.variant, args.wide)
@@ -736,6 +809,7 @@ def main():
         if args.workload != "seg1024":
             out["seg1024"] = single_summary(bench_single("seg1024", args.seed, 30, 3))
         out["line256"] = single_summary(bench_single("line256", args.seed, 100, 10))
+        out["line256_graph"] = bench_small_graph(args.seed)
         if bits == 32:
             out["wide_compares"] = single_summary(bench_single(args.workload, args.seed, 5, 2, wide=True))
         if not args.no_batched:

@@ -126,9 +126,10 @@ typedef struct {
                                  front to back and allocates no device memory; the
                                  level arena's parts are split in the proportions the
                                  context has learnt.  When a level does not fit, the
-                                 call reruns once with the parts re-split by the sizes
-                                 it measured, then fails with HH_ECAPACITY (nothing is
-                                 grouped or resumed in a larger arena).  The results of
+                                 call reruns from the root with the parts re-split by
+                                 the sizes measured so far (at most three reruns), then
+                                 fails with HH_ECAPACITY (nothing is grouped or resumed
+                                 in a larger arena).  The results of
                                  a call point into the arena: free them before the
                                  next call (that call fails with HH_EBUSY otherwise).
                                  The memory stays the caller's; it must stay valid

@@ -621,16 +621,17 @@ void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, T
     };
 
     if (mem.base) {
-        // the caller's arena: the rest of it is the level arena; one rerun
-        // with the parts re-split by the sizes the first run measured.  With
-        // HH_FLAG_GRAPH the first run's launches are a captured graph,
-        // replayed when the next call bakes in the same addresses and sizes.
+        // the caller's arena: the rest of it is the level arena; up to three
+        // reruns from the root, each with the parts re-split by the sizes the
+        // runs so far measured.  With HH_FLAG_GRAPH the first run's launches
+        // are a captured graph, replayed when the next call bakes in the same
+        // addresses and sizes.
         const bool graph = (ctx->cfg.flags & HH_FLAG_GRAPH) && !timing && mem.graph_ok && st != nullptr;
         const int64_t avail = mem.left() & ~(int64_t)255;
         DevBuf whole = mem.get((size_t)std::max<int64_t>(avail, 256), "level arena");
         mem.taken -= (int64_t)whole.bytes();
         mem.arena_peak = std::max<int64_t>(mem.arena_peak, avail);
-        for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int attempt = 0; attempt < 4; ++attempt) {
             const Caps want{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
             const Caps caps = fit_caps(want, avail, n_trees, entry_bytes, members);
             g.fl = fixed_layout(n_trees, caps.cells);

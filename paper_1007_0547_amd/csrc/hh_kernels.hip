@@ -377,8 +377,6 @@ struct TaskView {
     int32_t r;       // region
     int32_t c;       // task index within the region
     bool last;       // the region's last task
-    bool single;     // the region's only task
-    uint32_t ij, meta;
 };
 
 // Reads task t (scalar loads); false if its fields are out of range.
@@ -396,10 +394,16 @@ __device__ __forceinline__ bool view_task(const Task* tasks, const Region* regio
     v.b = R.start + off;
     v.n = (int32_t)std::min<int64_t>(task_len, R.len - off);
     v.last = off + task_len >= R.len;
-    v.single = tk.c == 0 && v.last;
-    v.ij = R.ij;
-    v.meta = R.meta;
     return true;
+}
+
+// The region's indices and meta bits (read when its task becomes current, so
+// they do not occupy registers while the previous task runs).
+__device__ __forceinline__ void region_code(const Region* regions, int32_t r, uint32_t& ij, uint32_t& meta)
+{
+    const Region R = ld_const(regions, (int64_t)r);
+    ij = R.ij;
+    meta = R.meta;
 }
 
 // An entry whose line votes for no region in the code variant: u = 0,
@@ -493,11 +497,15 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
         }
     }
     RegionTest<kVariant, CT> rt;
-    rt.set(cur.ij, cur.meta, lc);
+    {
+        uint32_t ij, meta;
+        region_code(regions, cur.r, ij, meta);
+        rt.set(ij, meta, lc);
+    }
     Entry ent[kStepRows];
     load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
     int s = 0;
-    int32_t acc[4] = {0, 0, 0, 0};
+    int32_t acc[4] = {0, 0, 0, 0};    // this task's votes per child
     for (;;) {
         // the next step: this task's, or the first of the next task
         const bool more = (s + 1) * kStep < cur.n;
@@ -521,15 +529,21 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
         if (more) {
             ++s;
         } else {
+            // the task's counts (ranks of the compaction pass) and the
+            // region's totals: a plain store for a one-task region, else atomics
             if (lane < 4) {
                 const int32_t v = pick4(acc, lane);
                 tcnt[cur.t * 4 + lane] = v;
-                if (cur.single) cv[(int64_t)cur.r * 4 + lane] = v;
+                if (cur.c == 0 && cur.last) cv[(int64_t)cur.r * 4 + lane] = v;
                 else if (v) atomicAdd(&cv[(int64_t)cur.r * 4 + lane], v);
             }
             if (!have_next) break;
+            {
+                uint32_t ij, meta;
+                region_code(regions, nxt.r, ij, meta);
+                rt.set(ij, meta, lc);
+            }
             cur = nxt;
-            rt.set(cur.ij, cur.meta, lc);
             s = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = 0;
@@ -588,11 +602,11 @@ __device__ __forceinline__ uint32_t keep_bits(const int64_t* dsti, int32_t r)
 }
 
 template <typename Entry>
-__device__ __forceinline__ void load_kids(const TaskView& v, const int64_t* dsti, const int32_t* cvi,
+__device__ __forceinline__ void load_kids(const TaskView& v, uint32_t meta, const int64_t* dsti, const int32_t* cvi,
                                           const int32_t* tcnt, Entry* nlist, Entry* members, Kids<Entry>& k)
 {
-    const bool finest = (v.meta & kMetaChildFinest) != 0;
-    k.unswap = finest && (v.meta & kMetaPass);
+    const bool finest = (meta & kMetaChildFinest) != 0;
+    k.unswap = finest && (meta & kMetaPass);
     k.keep = keep_bits(dsti, v.r);
     const int4 c4 = ld_const(reinterpret_cast<const int4*>(cvi), (int64_t)v.r);
     const int32_t c[4] = {c4.x, c4.y, c4.z, c4.w};
@@ -685,64 +699,57 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     TaskFeed feed;
     feed.init(&info->queue[1], NT, a.queue_batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves);
     bool bad = false;
-    // the next task whose region keeps a child (its id, first entry and
-    // length only: the rest is read again when it becomes current), or -1
-    auto next_task = [&](int64_t& b, int32_t& n) -> int64_t {
+    // the next task whose region keeps a child, false at the end
+    auto next_task = [&](TaskView& v) -> bool {
         for (;;) {
             const int64_t t = feed.take();
-            if (t < 0) return -1;
-            TaskView v;
+            if (t < 0) return false;
             if (!view_task(tasks, regions, P, L, task_len, t, v)) {
                 bad = true;
-                return -1;
+                return false;
             }
-            if (keep_bits(dsti, v.r)) {
-                b = v.b;
-                n = v.n;
-                return t;
-            }
+            if (keep_bits(dsti, v.r)) return true;
         }
     };
-    int64_t nb = 0;
-    int32_t nn = 0;
-    int64_t t = next_task(nb, nn);
-    if (t >= 0) {
-        TaskView cur;
+    TaskView cur;
+    if (next_task(cur)) {
         RegionTest<kVariant, CT> rt;
         Kids<Entry> kc;
-        auto become = [&](int64_t id) {
-            if (!view_task(tasks, regions, P, L, task_len, id, cur)) return false;
-            rt.set(cur.ij, cur.meta, lc);
-            load_kids(cur, dsti, cvi, tcnt, nlist, members, kc);
-            return true;
+        // a task becomes current: its region's test and kept children, and
+        // the votes of the region's tasks before it
+        auto enter = [&]() {
+            uint32_t ij, meta;
+            region_code(regions, cur.r, ij, meta);
+            rt.set(ij, meta, lc);
+            load_kids(cur, meta, dsti, cvi, tcnt, nlist, members, kc);
         };
-        if (become(t)) {
-            Entry ent[kStepRows];
-            load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
-            int s = 0;
-            for (;;) {
-                const bool more = (s + 1) * kStep < cur.n;
-                int64_t nt = -1;
-                Entry nent[kStepRows];
-                if (more) {
-                    load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
-                } else {
-                    nt = next_task(nb, nn);
-                    if (nt >= 0) load_step<Entry, kVariant>(list, nb, nn, 0, lane, nent);
-                }
-                write_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, lane, kc);
-                if (more) {
-                    ++s;
-                } else {
-                    if (cur.last && !kids_complete(cur, cvi, kc)) bad = true;
-                    if (nt < 0 || !become(nt)) break;
-                    s = 0;
-                }
-#pragma unroll
-                for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
+        enter();
+        Entry ent[kStepRows];
+        load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
+        int s = 0;
+        for (;;) {
+            const bool more = (s + 1) * kStep < cur.n;
+            TaskView nxt;
+            bool have_next = false;
+            Entry nent[kStepRows];
+            if (more) {
+                load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
+            } else if (next_task(nxt)) {
+                have_next = true;
+                load_step<Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
             }
-        } else {
-            bad = true;
+            write_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, lane, kc);
+            if (more) {
+                ++s;
+            } else {
+                if (cur.last && !kids_complete(cur, cvi, kc)) bad = true;
+                if (!have_next) break;
+                cur = nxt;
+                enter();
+                s = 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
         }
     }
     if (bad && lane == 0) raise_error(ar.error, kErrInternal);
