@@ -83,6 +83,10 @@ __device__ inline uint32_t lanes_below(uint64_t b)
 
 __device__ inline uint64_t bits_below(int p) { return ((uint64_t)1 << p) - 1; }   // p in 0..63
 
+// This lane's bit of a wavefront-uniform lane mask, as a lane predicate: the
+// mask itself serves as the execution mask, with no vector instruction.
+__device__ inline bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 // v (equal in every lane) as a wavefront-uniform value.  readfirstlane
 // returns int: widen through uint32_t so bit 31 does not sign-extend.
 __device__ inline uint64_t uniform64(uint64_t v)
@@ -239,32 +243,6 @@ struct RegionTest {
             child_masks<kVariant, CT>(vm, point, meta, ij, lc, cm);
         }
     }
-    // The same test as per-lane flags (vote of this lane's line for child q in
-    // bit q): used as store predicates, so no lane has to pick its bit out of
-    // a mask.  vm as in masks().
-    __device__ __forceinline__ uint32_t lane_votes(bool valid, uint32_t point, int lc) const
-    {
-        if constexpr (kVariant == 0) {
-            const CT u = (CT)(point & 0xFFFFu), v = (CT)(point >> 16);
-            const CT t0 = (v << lc) - mul(u, M0);
-            const CT du = 2 * u;
-            const CT t1 = t0 - du;
-            const CT t2 = t1 - du;
-            const bool ne = (B1 < t1) && !(B2 < t2);
-            const bool nw = (B1 < t0) && !(B2 < t1);
-            const bool sw = (B0 < t0) && !(B1 < t1);
-            const bool se = (B0 < t1) && !(B1 < t2);
-            return (uint32_t)ne | ((uint32_t)nw << 1) | ((uint32_t)sw << 2) | ((uint32_t)se << 3);
-        } else {
-            uint64_t cm[4];
-            child_masks<kVariant, CT>(valid ? ~0ull : 0ull, point, meta, ij, lc, cm);
-            const int lane = threadIdx.x & (kWave - 1);
-            uint32_t b = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) b |= (uint32_t)((cm[q] >> lane) & 1u) << q;
-            return valid ? b : 0u;
-        }
-    }
     // |u| < 2^14 and |M0| <= 2^15: a 24-bit multiply is exact for 32-bit compares
     __device__ static CT mul(CT u, CT m)
     {
@@ -303,13 +281,13 @@ __device__ inline int64_t wave_sum64(int64_t x)
 // ------------------------------------------------------------------ tasks
 //
 // A level's list is cut into tasks: up to task_steps consecutive steps of
-// one region's list, a step being kStepRows rows of 64 entries.  A wavefront
-// takes tasks one after another -- from a fixed share (task = its wavefront
-// index + k * all wavefronts of the grid) or from the level's work queue (an
-// atomic head in its LevelInfo, queue_batch tasks at a time, the next batch
-// requested while the current one runs) -- and streams a task one step at a
-// time, the next step's entries already in flight while it tests the
-// current one.  All lines of a task belong to one region, so the region's
+// one region's list, a step being 512 entries.  A wavefront takes tasks one
+// after another -- from a fixed share (task = its wavefront index + k * all
+// wavefronts of the grid) or from the level's work queue (an atomic head in
+// its LevelInfo, queue_batch tasks at a time, the next batch requested while
+// the current one runs) -- and streams a task one chunk of rows at a time,
+// the next chunk's entries already in flight while it tests the current
+// one.  All lines of a task belong to one region, so the region's
 // part of the vote test is wavefront-uniform and sits in scalar registers,
 // and a row is one test per lane.  Workgroups share nothing: a workgroup is
 // only a unit of launch.
@@ -416,16 +394,33 @@ __device__ constexpr Entry pad_entry()
     return kVariant == 0 ? (Entry)0xFFFF0000u : (Entry)0;
 }
 
-// Entries of step s of a task (n entries from b).
-template <typename Entry, int kVariant>
-__device__ __forceinline__ void load_step(const Entry* list, int64_t b, int32_t n, int s, int lane, Entry (&ent)[kStepRows])
+// A wavefront holds a chunk of R rows of 64 entries of a task in registers,
+// and loads the next chunk while it tests this one.  k_count keeps 8 rows;
+// k_write, with more arithmetic per row, keeps 16 rows of 4-byte entries
+// (8 KB of the list in flight per wavefront) and 8 of 8-byte ones.  Measured
+// on the 4096x4096 image and the 512-image batch, each choice was the
+// faster of the two for its kernel.
+constexpr int kCountRows = 8;
+template <typename Entry>
+constexpr int kWriteRows = sizeof(Entry) == 4 ? 16 : 8;
+
+// Entries of chunk s (R rows) of a task (n entries from b); a full chunk
+// loads without lane masks.
+template <int R, typename Entry, int kVariant>
+__device__ __forceinline__ void load_chunk(const Entry* list, int64_t b, int32_t n, int s, int lane, Entry (&ent)[R])
 {
-    const Entry* const p = list + b + (int64_t)s * kStep;
-    const int32_t rem = n - s * kStep;
+    constexpr int kChunk = R * kWave;
+    const Entry* const p = list + b + (int64_t)s * kChunk;
+    const int32_t rem = n - s * kChunk;
+    if (rem >= kChunk) {
 #pragma unroll
-    for (int k = 0; k < kStepRows; ++k) {
-        const int32_t o = k * kWave + lane;
-        ent[k] = o < rem ? p[o] : pad_entry<Entry, kVariant>();
+        for (int k = 0; k < R; ++k) ent[k] = p[k * kWave + lane];
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int32_t o = k * kWave + lane;
+            ent[k] = o < rem ? p[o] : pad_entry<Entry, kVariant>();
+        }
     }
 }
 
@@ -440,24 +435,56 @@ __device__ inline uint64_t row_mask(int32_t rem, int k)
 //
 // One read of every entry: per task, the votes of its lines for each child
 // of its region (the 4-bit code of Sec. 2 and the vote rule of Sec. 3 as
-// lane masks, counted with popcounts in scalar registers).  A task stores
-// its four counts (for the ranks of the compaction pass) and adds them to
-// its region's totals: a plain store when it is the region's only task,
-// atomics otherwise.
+// lane masks).  Each lane counts its own votes per child, one vector add
+// per row and child, and the task's four counts are summed over the
+// wavefront at its end: this keeps the per-row work on the vector unit,
+// which issues as often as the scalar unit but had slack.  A task stores its
+// four counts (for the ranks of the compaction pass) and adds them to its
+// region's totals: a plain store when it is the region's only task, atomics
+// otherwise.
 
-template <typename Entry, int kVariant, typename CT>
-__device__ __forceinline__ void count_step(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[kStepRows],
-                                           int32_t rem, int lc, int32_t (&acc)[4])
+template <int R, typename Entry, int kVariant, typename CT, bool kFull>
+__device__ __forceinline__ void count_rows(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[R], int32_t rem,
+                                           int lc, int32_t (&lacc)[4])
 {
 #pragma unroll
-    for (int k = 0; k < kStepRows; ++k) {
-        if (k * kWave >= rem) break;
-        const uint64_t vm = kVariant == 0 ? ~0ull : row_mask(rem, k);
+    for (int k = 0; k < R; ++k) {
+        if (!kFull && k * kWave >= rem) break;
+        const uint64_t vm = (kFull || kVariant == 0) ? ~0ull : row_mask(rem, k);
         uint64_t cm[4];
         rt.masks(vm, EntryOps<Entry>::point(ent[k]), lc, cm);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += (int32_t)__popcll(cm[q]);
+        for (int q = 0; q < 4; ++q) lacc[q] += lane_bit(cm[q]) ? 1 : 0;
     }
+}
+
+// The rows of a chunk with rem entries left in the task: a full chunk runs
+// without per-row bounds.
+template <int R, typename Entry, int kVariant, typename CT>
+__device__ __forceinline__ void count_chunk(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[R], int32_t rem,
+                                            int lc, int32_t (&lacc)[4])
+{
+    if (rem >= R * kWave) count_rows<R, Entry, kVariant, CT, true>(rt, ent, rem, lc, lacc);
+    else count_rows<R, Entry, kVariant, CT, false>(rt, ent, rem, lc, lacc);
+}
+
+// The four per-lane counts summed over the wavefront (every lane gets the
+// sums).  Two counts share a 32-bit word, 16 bits each: a task's count for
+// one child is at most its length, kMaxTaskSteps * kStep = 32768 < 2^16.
+__device__ __forceinline__ void wave_sum4(const int32_t (&x)[4], int32_t (&sum)[4])
+{
+    static_assert(kMaxTaskSteps * kStep < (1 << 16), "a task's count must fit 16 bits");
+    uint32_t a = (uint32_t)x[0] | ((uint32_t)x[1] << 16);
+    uint32_t b = (uint32_t)x[2] | ((uint32_t)x[3] << 16);
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        a += (uint32_t)__shfl_xor((int)a, d, kWave);
+        b += (uint32_t)__shfl_xor((int)b, d, kWave);
+    }
+    sum[0] = (int32_t)(a & 0xFFFFu);
+    sum[1] = (int32_t)(a >> 16);
+    sum[2] = (int32_t)(b & 0xFFFFu);
+    sum[3] = (int32_t)(b >> 16);
 }
 
 template <typename Entry, int kVariant, typename CT>
@@ -502,18 +529,19 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
         region_code(regions, cur.r, ij, meta);
         rt.set(ij, meta, lc);
     }
-    Entry ent[kStepRows];
-    load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
+    constexpr int R = kCountRows;
+    Entry ent[R];
+    load_chunk<R, Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
     int s = 0;
-    int32_t acc[4] = {0, 0, 0, 0};    // this task's votes per child
+    int32_t lacc[4] = {0, 0, 0, 0};    // this lane's votes per child in this task
     for (;;) {
-        // the next step: this task's, or the first of the next task
-        const bool more = (s + 1) * kStep < cur.n;
+        // the next chunk: this task's, or the first of the next task
+        const bool more = (s + 1) * R * kWave < cur.n;
         TaskView nxt;
         bool have_next = false;
-        Entry nent[kStepRows];
+        Entry nent[R];
         if (more) {
-            load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
+            load_chunk<R, Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
         } else {
             const int64_t t = feed.take();
             if (t >= 0) {
@@ -522,15 +550,17 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
                     return;
                 }
                 have_next = true;
-                load_step<Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
+                load_chunk<R, Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
             }
         }
-        count_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, acc);
+        count_chunk<R, Entry, kVariant, CT>(rt, ent, cur.n - s * R * kWave, lc, lacc);
         if (more) {
             ++s;
         } else {
             // the task's counts (ranks of the compaction pass) and the
             // region's totals: a plain store for a one-task region, else atomics
+            int32_t acc[4];
+            wave_sum4(lacc, acc);
             if (lane < 4) {
                 const int32_t v = pick4(acc, lane);
                 tcnt[cur.t * 4 + lane] = v;
@@ -546,10 +576,10 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
             cur = nxt;
             s = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = 0;
+            for (int q = 0; q < 4; ++q) lacc[q] = 0;
         }
 #pragma unroll
-        for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
+        for (int k = 0; k < R; ++k) ent[k] = nent[k];
     }
 }
 
@@ -560,25 +590,27 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
 // the votes of r for q in list order: the votes counted by the region's
 // earlier tasks (summed from tcnt), plus those of the earlier rows of this
 // task (a running count in scalar registers), plus the voting lanes below
-// it in its row (mbcnt).  Ranks are clamped to the child's count so no store
-// leaves the child's slot (the emit step checked every slot against its
-// buffer); the region's last task checks that each kept child got exactly
-// its count, else the call fails with an internal error.  Tasks of regions
-// without a kept child are skipped without reading their entries.
+// it in its row (mbcnt).  No store leaves the destination buffer: a task
+// whose every kept child has room in the buffer for all of the task's
+// entries stores without further checks (a task of n entries adds at most
+// n votes to a child); any other task checks each row's run against the
+// region's slots and drops a run that would leave them.  The region's last
+// task checks that each kept child got exactly its count, else the call
+// fails with an internal error.  Tasks of regions without a kept child are
+// skipped without reading their entries.
 
 // Kept children of a task's region.  The emit step lays a region's kept
 // children out one after another in quad order (in the next level's list, or
 // in the member buffer at the finest level), so one base pointer serves all
-// four: pos[q] is the slot (counted from base) of the next vote for child q,
-// and every store is clamped into the region's slots [0, total).
+// four: pos[q] is the slot (counted from base) of the next vote for child q.
 template <typename Entry>
 struct Kids {
     Entry* base;
     int32_t pos[4];
-    int32_t total;      // votes of the kept children
-    uint32_t last;      // total - 1, the region's last slot
+    int32_t total;      // votes of the kept children: the region's slots are [0, total)
     uint32_t keep;      // bit q: child q's voters are kept
     bool unswap;        // member entries are stored as (x, y) whatever the pass
+    bool roomy;         // every kept child has room in the buffer for the whole task
 };
 
 // Where each kept child's slot starts (from the first kept child's) and
@@ -601,9 +633,12 @@ __device__ __forceinline__ uint32_t keep_bits(const int64_t* dsti, int32_t r)
     return keep;
 }
 
+// nlist_cap / mem_cap: entries the next level's list / the member buffer
+// can hold.
 template <typename Entry>
 __device__ __forceinline__ void load_kids(const TaskView& v, uint32_t meta, const int64_t* dsti, const int32_t* cvi,
-                                          const int32_t* tcnt, Entry* nlist, Entry* members, Kids<Entry>& k)
+                                          const int32_t* tcnt, Entry* nlist, int64_t nlist_cap, Entry* members,
+                                          int64_t mem_cap, Kids<Entry>& k)
 {
     const bool finest = (meta & kMetaChildFinest) != 0;
     k.unswap = finest && (meta & kMetaPass);
@@ -613,10 +648,11 @@ __device__ __forceinline__ void load_kids(const TaskView& v, uint32_t meta, cons
     int32_t lo[4];
     kid_slots(c, k.keep, lo, k.total);
     const int q0 = __builtin_ctz(k.keep | 16u);   // first kept child (keep != 0 here)
-    k.base = (finest ? members : nlist) + (q0 < 4 ? ld_const(dsti, (int64_t)v.r * 4 + q0) : 0);
+    const int64_t dst = q0 < 4 ? ld_const(dsti, (int64_t)v.r * 4 + q0) : 0;
+    k.base = (finest ? members : nlist) + dst;
+    const int64_t cap = finest ? mem_cap : nlist_cap;
 #pragma unroll
     for (int q = 0; q < 4; ++q) k.pos[q] = lo[q];
-    k.last = (uint32_t)(k.total - 1);
     if (v.c > 0) {
         // votes of the region's earlier tasks, by scalar loads: a vector load
         // here would wait for every store the wavefront still has in flight
@@ -629,6 +665,10 @@ __device__ __forceinline__ void load_kids(const TaskView& v, uint32_t meta, cons
             k.pos[3] += x.w;
         }
     }
+    k.roomy = dst >= 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((k.keep >> q) & 1u) k.roomy = k.roomy && k.pos[q] >= 0 && dst + k.pos[q] + v.n <= cap;
 }
 
 // At a region's last task each kept child must have got exactly its votes.
@@ -646,25 +686,46 @@ __device__ __forceinline__ bool kids_complete(const TaskView& v, const int32_t* 
     return ok;
 }
 
-template <typename Entry, int kVariant, typename CT>
-__device__ __forceinline__ void write_step(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[kStepRows],
-                                           int32_t rem, int lc, int lane, Kids<Entry>& k)
+// One row of a chunk into the kept children's lists; vm = the lanes that
+// hold an entry of the task.  kChecked: each run is checked against the
+// region's slots (tasks without room for all their entries, and partial
+// chunks).
+template <bool kChecked, typename Entry, int kVariant, typename CT>
+__device__ __forceinline__ void write_row(const RegionTest<kVariant, CT>& rt, Entry e, uint64_t vm, int lc,
+                                          Kids<Entry>& k)
 {
+    uint64_t cm[4];
+    rt.masks(vm, EntryOps<Entry>::point(e), lc, cm);
+    const Entry e_out = EntryOps<Entry>::natural(e, k.unswap);
 #pragma unroll
-    for (int r = 0; r < kStepRows; ++r) {
-        if (r * kWave >= rem) break;
-        const uint32_t vb = rt.lane_votes(kVariant == 0 || r * kWave + lane < rem, EntryOps<Entry>::point(ent[r]), lc);
-        const Entry e_out = EntryOps<Entry>::natural(ent[r], k.unswap);
+    for (int q = 0; q < 4; ++q) {
+        if (!((k.keep >> q) & 1u)) continue;
+        // The row's voters for child q fill slots pos .. pos + n - 1, a lane
+        // taking pos + (voting lanes below it).  A checked run that would
+        // leave the region's slots [0, total) is not stored (a negative pos
+        // wraps to a large unsigned value); pos still advances, so the
+        // region's closing check reports it.
+        const int32_t n = (int32_t)__popcll(cm[q]);
+        const bool fits = !kChecked || (uint32_t)(k.pos[q] + n) <= (uint32_t)k.total;
+        if (fits && lane_bit(cm[q])) k.base[(uint32_t)k.pos[q] + lanes_below(cm[q])] = e_out;
+        k.pos[q] += n;
+    }
+}
+
+// A full chunk of a task with room runs unrolled without bounds; any other
+// chunk (the last, partial one of a task, or a task without room) runs row
+// by row with checks in a rolled loop (rare, so kept small).
+template <int R, typename Entry, int kVariant, typename CT>
+__device__ __forceinline__ void write_chunk(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[R], int32_t rem,
+                                            int lc, int lane, Kids<Entry>& k)
+{
+    if (rem >= R * kWave && k.roomy) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (!((k.keep >> q) & 1u)) continue;
-            const bool mine = (vb >> q) & 1u;
-            const uint64_t cm = __ballot(mine);
-            // clamped into the region's slots (pos >= 0 by construction; a
-            // negative value would wrap to a large unsigned one and be clamped)
-            if (mine) k.base[std::min((uint32_t)k.pos[q] + lanes_below(cm), k.last)] = e_out;
-            k.pos[q] += (int32_t)__popcll(cm);
-        }
+        for (int r = 0; r < R; ++r) write_row<false, Entry, kVariant, CT>(rt, ent[r], ~0ull, lc, k);
+    } else {
+#pragma nounroll
+        for (int r = 0; r * kWave < rem; ++r)
+            write_row<true, Entry, kVariant, CT>(rt, ent[r], kVariant == 0 ? ~0ull : row_mask(rem, r), lc, k);
     }
 }
 
@@ -694,6 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
     const int32_t* const cvi = G(static_cast<const int32_t*>(hl.cv));
     Entry* const nlist = G(static_cast<Entry*>(nx.list));
     Entry* const members = G(static_cast<Entry*>(ar.members));
+    const int64_t nlist_cap = (ar.half_cap - (static_cast<char*>(nx.list) - ar.half[lc & 1])) / (int64_t)sizeof(Entry);
     const int64_t task_len = steps * kStep;
 
     TaskFeed feed;
@@ -721,24 +783,25 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             uint32_t ij, meta;
             region_code(regions, cur.r, ij, meta);
             rt.set(ij, meta, lc);
-            load_kids(cur, meta, dsti, cvi, tcnt, nlist, members, kc);
+            load_kids(cur, meta, dsti, cvi, tcnt, nlist, nlist_cap, members, ar.mem_cap, kc);
         };
         enter();
-        Entry ent[kStepRows];
-        load_step<Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
+        constexpr int R = kWriteRows<Entry>;
+        Entry ent[R];
+        load_chunk<R, Entry, kVariant>(list, cur.b, cur.n, 0, lane, ent);
         int s = 0;
         for (;;) {
-            const bool more = (s + 1) * kStep < cur.n;
+            const bool more = (s + 1) * R * kWave < cur.n;
             TaskView nxt;
             bool have_next = false;
-            Entry nent[kStepRows];
+            Entry nent[R];
             if (more) {
-                load_step<Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
+                load_chunk<R, Entry, kVariant>(list, cur.b, cur.n, s + 1, lane, nent);
             } else if (next_task(nxt)) {
                 have_next = true;
-                load_step<Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
+                load_chunk<R, Entry, kVariant>(list, nxt.b, nxt.n, 0, lane, nent);
             }
-            write_step<Entry, kVariant, CT>(rt, ent, cur.n - s * kStep, lc, lane, kc);
+            write_chunk<R, Entry, kVariant, CT>(rt, ent, cur.n - s * R * kWave, lc, lane, kc);
             if (more) {
                 ++s;
             } else {
@@ -749,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
                 s = 0;
             }
 #pragma unroll
-            for (int k = 0; k < kStepRows; ++k) ent[k] = nent[k];
+            for (int k = 0; k < R; ++k) ent[k] = nent[k];
         }
     }
     if (bad && lane == 0) raise_error(ar.error, kErrInternal);

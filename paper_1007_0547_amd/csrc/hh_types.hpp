@@ -11,8 +11,7 @@ namespace hh {
 constexpr int kWave = 64;                   // CDNA wavefront width
 constexpr int kBlock = 256;                 // threads per workgroup (4 wavefronts)
 constexpr int kWaves = kBlock / kWave;
-constexpr int kStepRows = 8;                // 64-entry rows a wavefront holds in registers at once
-constexpr int kStep = kStepRows * kWave;    // 512 list entries
+constexpr int kStep = 8 * kWave;            // 512 list entries: the unit a task's length is counted in
 constexpr int kMaxTaskSteps = 64;           // a task covers 1 .. 64 steps of one region's list
 constexpr int kPixPerThread = 16;           // image bytes per lane in edge staging
 constexpr int kPixTile = kBlock * kPixPerThread;
