@@ -252,6 +252,7 @@ def bench_batched(seed, reps=3, arena_gb=160, variants=("pool", "tuned", "graph"
     ctx_a.close()
 
     graph = None
+    arena = ctx_g = None
     try:
         arena = torch.empty(int(arena_gb * 1e9), dtype=torch.uint8, device=dev)
         side = torch.cuda.Stream(dev)
@@ -261,10 +262,14 @@ def bench_batched(seed, reps=3, arena_gb=160, variants=("pool", "tuned", "graph"
         graph_s, tg, _ = timed(ctx_g)
         graph = {"ms_per_batch": graph_s * 1e3, "images_per_s": 512 / graph_s,
                  "graph_replayed": tg["graph_replayed"], "arena_gb": arena_gb, "groups": tg["groups"]}
-        ctx_g.close()
-        del arena
     except Exception as e:   # not enough device memory for one group: reported, not fatal
         graph = {"error": str(e)}
+    finally:
+        if ctx_g is not None:
+            ctx_g.close()
+    # the arena goes back to the device, not to torch's cache, for the blocks that follow
+    arena = ctx_g = None
+    torch.cuda.empty_cache()
 
     ctx = HoughHier(threshold=0, membership=True, device=0, stream=stream)
     for inp in inputs:   # one untimed pass: the arena reaches the sizes the largest images need
@@ -478,7 +483,7 @@ def bench_gray(seed, reps=20):
             "code_tests_per_s": info["code_tests"] / (ms / 1e3)}
 
 
-def bench_serving(seed, seconds, pool_size=384, lanes=3):
+def bench_serving(seed, seconds, pool_size=384, lanes=3, max_batch=4):
     """Serving: a Poisson stream of requests for `seconds` seconds per rate,
     images drawn in turn from a pool of `pool_size` distinct images of the
     serving distribution (sides log-uniform 256..4096, Poisson(48) segments,
@@ -510,8 +515,9 @@ def bench_serving(seed, seconds, pool_size=384, lanes=3):
         srv = HoughHier(threshold=0, membership=True, device=0)
         srv.serve_start(lanes=n_lanes, max_batch=max_batch, queue_capacity=1 << 16)
         for _ in range(2):   # warm the lanes: arena sizes, group limits, the footprint model
-            for t in [srv.submit(**inp) for inp in inputs]:
-                srv.poll(t).free()
+            for k in range(0, len(inputs), 16):   # a window at a time: results are freed as they come
+                for t in [srv.submit(**inp) for inp in inputs[k:k + 16]]:
+                    srv.poll(t).free()
         return srv
 
     def run(srv, arrivals):
@@ -556,7 +562,7 @@ def bench_serving(seed, seconds, pool_size=384, lanes=3):
     plain = server(1, 1)
     burst = run(plain, np.zeros(2 * len(inputs)))
     capacity = burst["images_per_s"]
-    batching = server(lanes, 32)
+    batching = server(lanes, max_batch)
     out = {"workload": f"Poisson arrivals for {seconds:g} s per rate; images in turn from a pool of {len(pool)} "
                        f"distinct images (seed {seed}): sides log-uniform 256..4096, Poisson(48) segments, 1% noise, "
                        "T=floor(side/10), depth ceil(log2 side), both passes, voters kept on device",
@@ -571,9 +577,12 @@ def bench_serving(seed, seconds, pool_size=384, lanes=3):
         rng = np.random.default_rng(seed + 1)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16))
         arrivals = arrivals[arrivals < seconds]
-        out["rates"][f"{f}x"] = {"arrival_rate_hz": rate,
-                                 "continuous_batching": run(batching, arrivals),
-                                 "per_request": run(plain, arrivals)}
+        cb = run(batching, arrivals)
+        note(f"serving {f}x capacity: continuous batching done")
+        pr = run(plain, arrivals)
+        note(f"serving {f}x capacity: per-request launches done")
+        out["rates"][f"{f}x"] = {"arrival_rate_hz": rate, "continuous_batching": cb, "per_request": pr}
+    out["slab"] = {"continuous_batching": batching.serve_stats(), "per_request": plain.serve_stats()}
     batching.close()
     plain.close()
     return out
@@ -697,6 +706,14 @@ def single_summary(b):
                           "frac": b["alg_bytes"] / (pass_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
 
 
+_T0 = time.time()
+
+
+def note(what):
+    """A progress line on stderr (the JSON result stays the only stdout line)."""
+    print(f"bench: {what} ({time.time() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -735,6 +752,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and not args.calibrate_copy and not args.only:
         cpu = cpu_baseline(synth.workload(args.workload, args.seed))
+        note("cpu baseline done")
 
     import torch
 
@@ -759,6 +777,7 @@ def main():
         return
 
     b = bench_single(args.workload, args.seed, args.steps, args.warmup, args.variant, args.wide)
+    note(f"{args.workload}: {args.steps} timed steps done")
     info, kt, w = b["info"], b["kt"], b["w"]
     pass_ms = kt["count_ms"] + kt["write_ms"]
     achieved = b["alg_bytes"] / (pass_ms / 1e3) / 1e9
@@ -808,20 +827,28 @@ def main():
     if not args.no_extras:
         if args.workload != "seg1024":
             out["seg1024"] = single_summary(bench_single("seg1024", args.seed, 30, 3))
+            note("seg1024 done")
         out["line256"] = single_summary(bench_single("line256", args.seed, 100, 10))
         out["line256_graph"] = bench_small_graph(args.seed)
+        note("line256 done")
         if bits == 32:
             out["wide_compares"] = single_summary(bench_single(args.workload, args.seed, 5, 2, wide=True))
+            note("wide compares done")
         if not args.no_batched:
             out["batch512"] = bench_batched(args.seed)
+            note("batch512 done")
         if not args.no_sweep:
             out["size_sweep"] = bench_sweep(args.seed)
+            note("size sweep done")
         if not args.no_gray:
             out["gray1024"] = bench_gray(args.seed)
+            note("gray1024 done")
         if not args.no_solution:
             out["solution"] = bench_solution(args.seed)
+            note("solution done")
         if args.serve_seconds > 0:
             out["serving"] = bench_serving(args.seed, args.serve_seconds)
+            note("serving done")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -280,7 +280,7 @@ HH_API const char* hough_hier_last_error(const hh_ctx* ctx);
  * borrowed for the duration of the call.  On HH_OK *out owns the result;
  * release it with hough_hier_result_free().  The result keeps the call's
  * arena (its cells and voters are inside) until it is freed, so free results
- * promptly when calls are many or large (served results are compact).
+ * promptly when calls are many or large.
  * Errors: HH_EINVAL (see hh_status; also for device point lists with a point
  * out of range), HH_ENOMEM, HH_EDEVICE, HH_EINTERNAL. */
 HH_API hh_status hough_hier_detect(hh_ctx* ctx, const hh_input* in, hh_result** out);
@@ -301,29 +301,40 @@ HH_API hh_status hough_hier_detect_batch(hh_ctx* ctx, const hh_input* inputs, in
 
 /* ---- Serving: continuous batching of requests on one context.
  *
- * hough_hier_serve_start starts `lanes` worker lanes (slots), each with its
- * own HIP stream and arena (default-priority streams).  A free lane takes the
- * pending requests in arrival order, as many as fit (at most max_batch
- * requests, at most max_batch_pixels image pixels if that is not 0, and --
- * the admission by device memory -- while the predicted footprints of the
- * batches running on all lanes plus this one stay within the context's
- * budget: hbm_budget_bytes, else arena_limit_mib, else 35% of the device
- * memory; a batch alone on the device always runs), runs them as one batch
+ * hough_hier_serve_start allocates one device slab of the context's budget
+ * (hbm_budget_bytes, else arena_limit_mib, else 35% of the device memory)
+ * and starts `lanes` worker lanes (slots), each with its own HIP stream
+ * (default-priority streams); the lanes draw all their device memory from
+ * the slab.  A free lane takes the pending requests in arrival order, as
+ * many as fit (at most max_batch requests, at most max_batch_pixels image
+ * pixels if that is not 0, and -- the admission by device memory -- while
+ * their predicted footprint fits the slab's largest free interval and, past
+ * the first request, half of 1/lanes of the slab; any request while no
+ * batch runs), runs them as one batch
  * (hough_hier_detect_batch), copies each result's cells and statistics to
- * the host and completes the tickets.  A request's footprint is predicted as
- * beta * E * 2^depth bytes, E its edge points (counted at submission for a
- * host binary image or a point list, else its pixels times the edge density
- * seen so far), beta a running average over completed batches of their
- * measured footprint per unit.  Requests that arrive while batches run are
- * admitted by the next lane that is free once memory allows, so batches of
- * different lanes overlap on the device.  A request's result is identical to
- * what hough_hier_detect returns for the same input.  A served result holds
- * exact copies of its cells and voters only (the arena goes to the lane's
- * next batch).  The context stays usable for plain calls.  Served results
- * carry queue_ms and service_ms in hh_timing. */
+ * the host and completes the tickets.  A request's footprint is predicted
+ * as beta * E * 2^depth bytes, E its edge points (counted at submission for
+ * a host binary image or a point list, else its pixels times the edge
+ * density seen so far), beta a running average over completed batches of
+ * their measured need per unit; the prediction also sizes the batch's
+ * first level arena, which grows from the level that overflows.  Requests
+ * that arrive while batches run are admitted by the next lane that is free
+ * once slab space allows, so batches of different lanes overlap on the
+ * device; serving allocates no device memory.  A served result keeps its
+ * device memory (cells and voters) until the last result of its batch is
+ * freed: free served results promptly.  A batch that finds the slab full
+ * gives its second half back to the head of the queue and runs its first
+ * half again; a single request runs again once space comes back, and if it
+ * still finds the slab full while no batch runs (the slab held by results
+ * not yet freed for a second, or a request larger than the slab) it runs
+ * outside the slab, in device memory returned as soon as its results are
+ * freed.  A request's result is identical to what
+ * hough_hier_detect returns for the same input.  The context stays usable
+ * for plain calls.  Served results carry queue_ms and service_ms in
+ * hh_timing. */
 typedef struct {
-    int32_t lanes;            /* concurrent batches, 1..8 (0: 2)                       */
-    int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 32)           */
+    int32_t lanes;            /* concurrent batches, 1..8 (0: 3)                       */
+    int32_t max_batch;        /* most requests in one batch, 1..2048 (0: 4)            */
     int64_t max_batch_pixels; /* most image pixels (points of lists) in a batch, 0: no
                                  limit besides the memory budget                        */
     int32_t queue_capacity;   /* most tickets not yet claimed by poll (0: 4096)        */
@@ -331,7 +342,8 @@ typedef struct {
 } hh_serve_config;
 
 /* Start serving on ctx (once per context).  cfg may be NULL for defaults.
- * Errors: HH_EINVAL (bad config, already serving), HH_EDEVICE, HH_ENOMEM. */
+ * Errors: HH_EINVAL (bad config, already serving), HH_EDEVICE, HH_ENOMEM
+ * (the slab could not be allocated). */
 HH_API hh_status hough_hier_serve_start(hh_ctx* ctx, const hh_serve_config* cfg);
 
 /* Queue one input (borrowed until its ticket completes; device inputs must be
@@ -347,6 +359,21 @@ HH_API hh_status hough_hier_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ti
  * and hough_hier_last_error() holds its text.
  * Errors: HH_EINVAL (unknown ticket, not serving), any error of the request. */
 HH_API hh_status hough_hier_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out);
+
+/* Serving counters of ctx (hough_hier_serve_stats). */
+typedef struct {
+    int64_t slab_bytes;        /* the slab allocated by hough_hier_serve_start        */
+    int64_t slab_used;         /* bytes of it held now by running batches and results */
+    int64_t slab_batches;      /* batches run inside the slab                         */
+    int64_t outside_batches;   /* batches run outside the slab                        */
+    int64_t retries;           /* runs that found the slab full and ran again         */
+    int64_t pending;           /* requests waiting for a lane                         */
+    double bytes_per_unit;     /* the footprint model's beta (bytes per E * 2^depth)  */
+} hh_serve_stats;
+
+/* Copy the serving counters of ctx into *out.
+ * Errors: HH_EINVAL (not serving, out NULL). */
+HH_API hh_status hough_hier_serve_stats(hh_ctx* ctx, hh_serve_stats* out);
 
 /* Cells of one pass (0 or 1), sorted by key.  on_device = 1 returns a device
  * pointer (member_off indexes the device members array); on_device = 0 copies

@@ -88,6 +88,12 @@ class _ServeConfig(C.Structure):
                 ("queue_capacity", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _ServeStats(C.Structure):
+    _fields_ = [("slab_bytes", C.c_int64), ("slab_used", C.c_int64), ("slab_batches", C.c_int64),
+                ("outside_batches", C.c_int64), ("retries", C.c_int64), ("pending", C.c_int64),
+                ("bytes_per_unit", C.c_double)]
+
+
 class _Launch(C.Structure):
     _fields_ = [("task_steps", C.c_int32), ("queue_batch", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -119,6 +125,8 @@ _lib.hough_hier_detect_batch.restype = C.c_int
 _lib.hough_hier_detect_batch.argtypes = [_p, C.POINTER(_Input), C.c_int32, C.POINTER(_p)]
 _lib.hough_hier_serve_start.restype = C.c_int
 _lib.hough_hier_serve_start.argtypes = [_p, C.POINTER(_ServeConfig)]
+_lib.hough_hier_serve_stats.restype = C.c_int
+_lib.hough_hier_serve_stats.argtypes = [_p, C.POINTER(_ServeStats)]
 _lib.hough_hier_submit.restype = C.c_int
 _lib.hough_hier_submit.argtypes = [_p, C.POINTER(_Input), C.POINTER(C.c_uint64)]
 _lib.hough_hier_poll.restype = C.c_int
@@ -502,6 +510,16 @@ class HoughHier:
             raise HHError(s, self.last_error())
         self._inflight = {}
 
+    def serve_stats(self) -> dict:
+        """Serving counters (``hough_hier_serve_stats``): the slab's size and
+        use, batches run inside and outside it, reruns in a larger interval,
+        waiting requests and the footprint model's bytes per unit."""
+        st = _ServeStats()
+        s = _lib.hough_hier_serve_stats(self._h, C.byref(st))
+        if s != 0:
+            raise HHError(s, self.last_error())
+        return {k: getattr(st, k) for k, _ in _ServeStats._fields_}
+
     def submit(self, x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int,
                height: int, threshold: int = -1, max_depth: Optional[int] = None) -> int:
         """Queue one input (``hough_hier_submit``, the arguments of
@@ -532,6 +550,7 @@ class HoughHier:
         if self._h:
             _lib.hough_hier_destroy(self._h)
             self._h = C.c_void_p()
+        self._arena = None   # a caller arena is released with the context
 
     def __enter__(self):
         return self

@@ -121,6 +121,13 @@ hh_status hough_hier_serve_start(hh_ctx* ctx, const hh_serve_config* cfg)
     return guarded(ctx, [&] { return hh::serve_start(ctx, cfg); });
 }
 
+hh_status hough_hier_serve_stats(hh_ctx* ctx, hh_serve_stats* out)
+{
+    if (!ctx) return HH_EINVAL;
+    if (!out) return fail(ctx, HH_EINVAL, "output pointer must not be NULL");
+    return guarded(ctx, [&] { return hh::serve_stats(ctx, out); });
+}
+
 hh_status hough_hier_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket)
 {
     if (!ctx) return HH_EINVAL;

@@ -24,10 +24,112 @@ namespace hh {
 
 // ---------------------------------------------------------------- pool
 
+void SlabSpace::init(char* base, int64_t bytes, std::condition_variable* freed)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    base_ = base;
+    freed_ = freed;
+    free_.clear();
+    live_.clear();
+    total_ = bytes & ~(int64_t)255;
+    used_ = 0;
+    if (total_ > 0) free_[0] = total_;
+}
+
+int64_t SlabSpace::take(int64_t bytes)
+{
+    bytes = (std::max<int64_t>(bytes, 256) + 255) & ~(int64_t)255;
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        const int64_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        live_[off] = bytes;
+        used_ += bytes;
+        return off;
+    }
+    return -1;
+}
+
+void SlabSpace::give(int64_t off)
+{
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = live_.find(off);
+        if (it == live_.end()) return;
+        int64_t bytes = it->second;
+        live_.erase(it);
+        used_ -= bytes;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {   // merge with the interval after
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        bool merged = false;
+        if (next != free_.begin()) {   // and with the one before
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                merged = true;
+            }
+        }
+        if (!merged) free_[off] = bytes;
+    }
+    if (freed_) freed_->notify_all();
+}
+
+int64_t SlabSpace::largest()
+{
+    std::lock_guard<std::mutex> g(mu_);
+    int64_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+}
+
+int64_t SlabSpace::used()
+{
+    std::lock_guard<std::mutex> g(mu_);
+    return used_;
+}
+
 DevicePool::~DevicePool()
 {
     trim_locked();
-    for (auto& kv : size_of_) (void)hipFree(kv.first);
+    for (auto& kv : size_of_) {
+        if (slab_ && slab_->holds(kv.first)) slab_->give(static_cast<char*>(kv.first) - slab_->base());
+        else (void)hipFree(kv.first);
+    }
+    for (void* p : deferred_) slab_->give(static_cast<char*>(p) - slab_->base());
+}
+
+void DevicePool::free_locked(void* p, size_t sz)
+{
+    live_ -= sz;
+    size_of_.erase(p);
+    if (slab_ && slab_->holds(p)) {
+        if (in_call_) deferred_.push_back(p);
+        else slab_->give(static_cast<char*>(p) - slab_->base());
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+void DevicePool::begin_call()
+{
+    std::lock_guard<std::mutex> g(mu_);
+    in_call_ = true;
+}
+
+void DevicePool::end_call()
+{
+    std::vector<void*> back;
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        in_call_ = false;
+        back.swap(deferred_);
+    }
+    for (void* p : back) slab_->give(static_cast<char*>(p) - slab_->base());
 }
 
 size_t DevicePool::round_size(size_t bytes)
@@ -42,6 +144,19 @@ void* DevicePool::alloc(size_t bytes)
 {
     std::lock_guard<std::mutex> g(mu_);
     const size_t sz = round_size(bytes);
+    if (slab_ && !outside_) {
+        const int64_t off = slab_->take((int64_t)sz);
+        if (off >= 0) {
+            void* p = slab_->base() + off;
+            size_of_[p] = sz;
+            live_ += sz;
+            return p;
+        }
+        // a full slab fails a call (its lane waits for space); a block made
+        // on request between calls (a result's ids or rebased cells) comes
+        // from hipMalloc instead
+        if (in_call_) return nullptr;
+    }
     auto it = free_.find(sz);
     if (it != free_.end() && !it->second.empty()) {
         void* p = it->second.back();
@@ -70,8 +185,12 @@ void DevicePool::release(void* p)
     std::lock_guard<std::mutex> g(mu_);
     auto it = size_of_.find(p);
     if (it == size_of_.end()) return;
-    free_[it->second].push_back(p);
+    if (!caching_ || (slab_ && slab_->holds(p))) {
+        free_locked(p, it->second);
+        return;
+    }
     live_ -= it->second;
+    free_[it->second].push_back(p);
     cached_ += it->second;
 }
 
@@ -81,9 +200,7 @@ void DevicePool::discard(void* p)
     std::lock_guard<std::mutex> g(mu_);
     auto it = size_of_.find(p);
     if (it == size_of_.end()) return;
-    live_ -= it->second;
-    size_of_.erase(it);
-    (void)hipFree(p);
+    free_locked(p, it->second);
 }
 
 void DevicePool::trim()
@@ -705,7 +822,15 @@ void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, T
     int from = -1;   // -1: from the root setup; l: from level l's split decision
     for (int run = 0;; ++run) {
         if (run >= 64) throw Error{HH_ECAPACITY, "arena sizing did not converge"};
-        const Caps caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        Caps caps{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
+        if (run == 0 && ctx->arena_hint_bytes > 0) {
+            // a size expected for this call (serving lanes): the parts in the
+            // learnt proportions, scaled to it; a resume grows what overflows
+            try {
+                caps = fit_caps(caps, ctx->arena_hint_bytes, n_trees, entry_bytes, members);
+            } catch (const Error&) {
+            }
+        }
         const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
         if (run == 0 && (double)arena_bytes(nfl, caps, entry_bytes) > budget) throw BudgetExceeded{budget};
         DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
@@ -1021,15 +1146,25 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
 
         const LevelInfo* info = reinterpret_cast<const LevelInfo*>(ctx->h_fixed + g.fl.info);
         const int64_t* rec = reinterpret_cast<const int64_t*>(ctx->h_fixed + g.fl.rec);
+        {
+            // the level arena this group needed at least: its largest level, its cells and voters
+            Caps need{info[dmax].cells_base + info[dmax].cells, p0.membership ? info[dmax].mem_base + info[dmax].mem : 0,
+                      0, 0};
+            for (int l = 0; l <= dmax; ++l) {
+                need.half = std::max(need.half, half_layout(nullptr, info[l].P, info[l].L, info[l].NT, entry_bytes).end);
+                need.work = std::max(need.work, work_layout(nullptr, info[l].P, info[l].NT).end);
+            }
+            mem.arena_need = std::max(mem.arena_need, arena_bytes(fixed_layout(ntg, need.cells), need, entry_bytes));
+        }
         auto gs = std::make_shared<GroupStore>();
         gs->call = store;
         const Cell* gcells = g.ar.cells;
         const void* gmembers = g.ar.members;
-        if (k0 == 0 && k1 == n && !ctx->compact_results) {
+        if (k0 == 0 && k1 == n) {
             gs->arena = std::move(g.arena);   // one group: results point into its arena
         } else {
-            // several groups, or compact results: keep exact copies of the
-            // cells and voters, and let the next group or call reuse the arena
+            // several groups: keep exact copies of the cells and voters, and
+            // let the next group reuse the arena
             const int64_t nc = info[dmax].cells_base + info[dmax].cells;
             const int64_t nm = p0.membership ? info[dmax].mem_base + info[dmax].mem : 0;
             gs->cells = DevBuf(pool, (size_t)std::max<int64_t>(nc, 1) * sizeof(Cell));
@@ -1134,6 +1269,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
     }
     sync(ctx);   // the copies of the last group
     ctx->last_call_bytes = mem.taken + mem.arena_peak;
+    ctx->last_call_need = mem.taken + mem.arena_need;
     if (timing) {
         tm.total_ms = elapsed(ctx, 0, 2);
         tm.extract_ms = elapsed(ctx, 0, 1);

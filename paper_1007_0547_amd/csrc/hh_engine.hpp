@@ -6,6 +6,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <condition_variable>
+#include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -18,12 +21,45 @@
 
 namespace hh {
 
+// Intervals of one device slab shared by several pools, handed out first
+// fit (256-byte aligned), with a lock of its own.  `freed` (if set) is
+// notified whenever an interval comes back.
+class SlabSpace {
+public:
+    void init(char* base, int64_t bytes, std::condition_variable* freed);
+    int64_t take(int64_t bytes);    // offset of a free interval of `bytes`, or -1
+    void give(int64_t off);         // return the interval at off
+    int64_t largest();              // the largest free interval
+    int64_t total() const { return total_; }
+    int64_t used();
+    char* base() const { return base_; }
+    bool holds(const void* p) const
+    {
+        return p >= base_ && static_cast<const char*>(p) < base_ + total_;
+    }
+
+private:
+    std::mutex mu_;
+    std::map<int64_t, int64_t> free_;   // offset -> bytes
+    std::map<int64_t, int64_t> live_;   // offset -> bytes
+    char* base_ = nullptr;
+    int64_t total_ = 0, used_ = 0;
+    std::condition_variable* freed_ = nullptr;
+};
+
 // Caching allocator over hipMalloc.  Sizes are rounded up to one of eight
 // steps per power of two; freed blocks wait in per-size free lists and are
 // handed out again without a hipMalloc.  All device work that uses a pool's
 // blocks runs on its context's stream, so reuse is ordered by the stream.
 // The pool is locked on its own, so that releasing a result's blocks never
 // waits for a call running on the context.
+//
+// A pool may instead draw its blocks from a slab that other pools (on other
+// streams) share: no caching, and a block released while a call runs goes
+// back to the slab only when the call has ended (its stream synchronized),
+// so no other stream can reuse it while this one's work may still touch it.
+// With the slab full, an allocation inside a call fails; one between calls
+// (made on request for a result) falls back to hipMalloc.
 class DevicePool {
 public:
     ~DevicePool();
@@ -31,16 +67,27 @@ public:
     void release(void* p);
     void discard(void* p);   // hipFree a live block instead of caching it
     void trim();
+    void set_caching(bool on) { caching_ = on; }   // off: a released block is freed at once
+    void back_with(SlabSpace* slab) { slab_ = slab; }
+    void draw_outside(bool on) { outside_ = on; }   // new blocks from hipMalloc even when backed
+    void begin_call();
+    void end_call();         // after the call's stream is synchronized
     size_t live_bytes() const { return live_; }
     size_t cached_bytes() const { return cached_; }
 
 private:
     static size_t round_size(size_t bytes);
     void trim_locked();
+    void free_locked(void* p, size_t sz);
     std::mutex mu_;
     std::unordered_map<size_t, std::vector<void*>> free_;
     std::unordered_map<void*, size_t> size_of_;
     size_t live_ = 0, cached_ = 0;
+    bool caching_ = true;
+    SlabSpace* slab_ = nullptr;
+    bool outside_ = false;
+    bool in_call_ = false;
+    std::vector<void*> deferred_;   // slab blocks released during a call
 };
 
 // A pool block that returns to its pool on destruction.
@@ -88,6 +135,7 @@ struct CallMem {
     bool graph_ok = false;  // every input is device resident (HH_FLAG_GRAPH may capture)
     int64_t taken = 0;      // bytes handed out (both kinds), for the footprint of the call
     int64_t arena_peak = 0; // largest level arena the call held
+    int64_t arena_need = 0; // largest level arena the call's groups needed (measured)
     DevBuf get(size_t bytes, const char* what);
     int64_t left() const { return cap - used; }
 };
@@ -111,6 +159,11 @@ struct GroupStore {
     DevBuf arena;
     DevBuf cells;
     DevBuf members;
+    std::function<void()> on_release;   // run when the last result of the group goes (serving slab space)
+    ~GroupStore()
+    {
+        if (on_release) on_release();
+    }
 };
 
 }  // namespace hh
@@ -187,10 +240,6 @@ struct hh_ctx {
     int64_t work_cap = 16ll << 20;      // bytes of per-level scratch
     int64_t mem_cap = 16ll << 20;       // member entries
     int64_t cells_cap = 1ll << 20;
-    // results keep exact copies of their cells and voters and release the
-    // arena at once (serving lanes); otherwise a one-group call's results
-    // keep its arena until the last of them is freed
-    bool compact_results = false;
     // most edge points one group of a batch may hold (0: no limit), learnt
     // when a group's level lists exceeded the memory budget
     int64_t group_points = 0;
@@ -201,6 +250,7 @@ struct hh_ctx {
     int32_t task_steps = 4;
     int32_t queue_batch = 0;
     int32_t wg_per_cu = 0;
+    int64_t arena_hint_bytes = 0;   // > 0: size of a call's first level arena (serving lanes set it per batch)
     // HIP events for HH_FLAG_TIMING: [0] call start, [1] staging end, [2] call end,
     // then four per level: before count, after count, after emit, after the compaction
     std::vector<hipEvent_t> events;
@@ -211,6 +261,7 @@ struct hh_ctx {
     // device bytes the last detection call held at most (inputs, staging,
     // level arena), for serving admission
     int64_t last_call_bytes = 0;
+    int64_t last_call_need = 0;   // device bytes the last call needed at least (inputs and level arena)
     // HH_FLAG_GRAPH: the captured level launches of the last call and what
     // they were captured for (sizes, parameters, addresses)
     hipGraphExec_t graph_exec = nullptr;
@@ -260,5 +311,6 @@ hh_status serve_start(hh_ctx* ctx, const hh_serve_config* cfg);
 hh_status serve_submit(hh_ctx* ctx, const hh_input* in, uint64_t* ticket);
 hh_status serve_poll(hh_ctx* ctx, uint64_t ticket, int32_t wait_us, hh_result** out);
 void serve_stop(hh_ctx* ctx);
+hh_status serve_stats(hh_ctx* ctx, hh_serve_stats* out);
 
 }  // namespace hh

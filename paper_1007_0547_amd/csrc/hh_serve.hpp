@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/hough_hier.h"
+#include "hh_engine.hpp"
 
 namespace hh {
 
@@ -39,21 +40,30 @@ struct Server {
     std::vector<hh_ctx*> lanes;        // one context per lane, each on its own stream
     std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
-    std::mutex mu;                     // queue, tickets and the stop flag
-    std::condition_variable work_cv;   // a request was queued, or stop
+    std::mutex mu;                     // queue, tickets, slab space and the stop flag
+    std::condition_variable work_cv;   // a request was queued, slab space came back, or stop
     std::condition_variable done_cv;   // a request completed, or stop
     std::deque<std::shared_ptr<Request>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;   // not yet claimed by poll
     uint64_t next_ticket = 1;
     bool stop = false;
-    // admission by device memory: the predicted footprints of the batches
-    // running on the lanes may not exceed `budget` (a batch alone on the
-    // device always runs).  A request's footprint is predicted as
-    // beta * E * 2^depth bytes, with E its edge points (or pixels times the
-    // edge density seen so far); beta and the density are running averages
-    // over completed batches (measured footprint / sum of E * 2^depth).
+    // Device state: one slab of `budget` bytes, allocated when serving
+    // starts.  The lanes' pools draw every block from it (inputs' staging,
+    // level lists, cells and voters), and a result keeps its batch's blocks
+    // until the last result of the batch is freed, so serving allocates no
+    // device memory.  Admission by device memory: a lane takes requests
+    // while their predicted footprint fits the slab's largest free interval.
+    // A request's footprint is predicted as beta * E * 2^depth bytes, with E
+    // its edge points (or pixels times the edge density seen so far); beta
+    // and the density are running averages over completed batches (measured
+    // need / sum of E * 2^depth).  The prediction sizes a batch's first
+    // level arena; lists that outgrow it grow it from the level that
+    // overflowed.
+    char* slab = nullptr;
+    SlabSpace space;
     int64_t budget = 0;
-    int64_t in_flight = 0;
+    int running = 0;                   // batches on the lanes
+    int64_t slab_batches = 0, outside_batches = 0, retries = 0;
     double beta = 12.0;
     double density = 0.03;
 };

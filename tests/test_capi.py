@@ -43,7 +43,7 @@ def header_sizes(tmp_path):
     """sizeof of the ABI structs as the C compiler lays them out from the header."""
     src = tmp_path / "sizes.c"
     names = ["hh_config", "hh_input", "hh_solution", "hh_cell", "hh_level_stats", "hh_launch",
-             "hh_result_info", "hh_timing", "hh_serve_config"]
+             "hh_result_info", "hh_timing", "hh_serve_config", "hh_serve_stats"]
     src.write_text('#include <stdio.h>\n#include "hough_hier.h"\nint main(void) {\n' +
                    "".join(f'printf("{n} %zu\\n", sizeof({n}));\n' for n in names) + "return 0; }\n")
     exe = tmp_path / "sizes"
@@ -62,6 +62,7 @@ def test_struct_layouts_match_header(tmp_path):
     assert C.sizeof(hh._Info) == sz["hh_result_info"]
     assert C.sizeof(hh._Timing) == sz["hh_timing"]
     assert C.sizeof(hh._ServeConfig) == sz["hh_serve_config"]
+    assert C.sizeof(hh._ServeStats) == sz["hh_serve_stats"]
     assert hh.CELL_DTYPE.itemsize == sz["hh_cell"]
     assert hh.STATS_DTYPE.itemsize == sz["hh_level_stats"]
 

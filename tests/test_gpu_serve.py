@@ -148,3 +148,42 @@ def test_queue_bounds_and_tickets(hh):
         r.free()
         # unclaimed tickets are released with the context
         srv.submit(image=img, width=300, height=300)
+
+
+def test_slab_holds_batches_and_held_results(hh):
+    """Every batch runs inside the serving slab; results keep their batch's
+    slab space until freed; a request that finds no room while results are
+    held runs outside the slab, with the same result as a plain call."""
+    trace = synth.serving_trace(seed=5, rate_hz=1000.0, duration_s=1.0, side_lo=256, side_hi=512,
+                                mean_segments=10.0, max_requests=18)
+    ws = [w for _, w in trace]
+    say(f"case serving slab: {len(ws)} requests, 256 MiB slab, 2 lanes")
+    with hh.HoughHier(threshold=0, hbm_budget_bytes=256 << 20) as srv, hh.HoughHier(threshold=0) as plain:
+        srv.serve_start(lanes=2, max_batch=4)
+        st = srv.serve_stats()
+        assert st["slab_bytes"] == 256 << 20 and st["slab_used"] == 0
+        # requests freed as they complete: all inside the slab
+        for w in ws[:8]:
+            r = srv.poll(srv.submit(image=w.image, width=w.width, height=w.height, threshold=w.threshold))
+            one = plain.detect(image=w.image, width=w.width, height=w.height, threshold=w.threshold)
+            assert_same(view(r), view(one), "freed request")
+            r.free()
+            one.free()
+        st = srv.serve_stats()
+        assert st["outside_batches"] == 0 and st["slab_batches"] >= 1 and st["slab_used"] == 0, st
+        # results held by the client: their space stays taken, and requests
+        # that no longer fit still complete
+        held = []
+        for k, w in enumerate(ws[8:]):
+            r = srv.poll(srv.submit(image=w.image, width=w.width, height=w.height, threshold=w.threshold))
+            held.append((w, r))
+        st = srv.serve_stats()
+        say(f"  stats with {len(held)} results held: {st}")
+        assert st["slab_used"] > 0
+        for w, r in held:
+            one = plain.detect(image=w.image, width=w.width, height=w.height, threshold=w.threshold)
+            assert_same(view(r), view(one), "held request")
+            one.free()
+        for _, r in held:
+            r.free()
+        assert srv.serve_stats()["slab_used"] == 0
