@@ -307,11 +307,12 @@ def solution_bytes(r):
 
 
 def bench_solution(seed, reps=5):
-    """solution() with point removal (hough_hier_solution) on the benchmark
-    image and on the 512-image batch: the walk's kernel time from HIP events
-    in the library, its algorithmic bandwidth, and the whole call (voter id
-    conversion included) once the context has its buffers.  The walk is
-    sequential per pass (one workgroup per tree)."""
+    """solution() with point removal (hough_hier_solution) on the 1024x1024
+    image and on the 512-image batch: the walk's device time from HIP events
+    in the library (its rounds of segment walks, the host's checks between
+    them included), its algorithmic bandwidth, and the whole call (voter id
+    conversion included) once the context has its buffers; beside it, the
+    detection of the same image."""
     import numpy as np
     import torch
 
@@ -323,10 +324,13 @@ def bench_solution(seed, reps=5):
     w = synth.workload("seg1024", seed)
     img = torch.from_numpy(w.image).to(dev)
     ctx = hh.HoughHier(threshold=w.threshold, max_depth=w.max_depth, device=0, stream=stream)
-    ms, call = [], []
+    ms, call, det = [], [], []
     for k in range(reps + 1):
+        torch.cuda.synchronize(dev)
+        td = time.perf_counter()
         r = ctx.detect(image=img, width=w.width, height=w.height)
         torch.cuda.synchronize(dev)
+        det.append((time.perf_counter() - td) * 1e3)
         t0 = time.perf_counter()
         m = hh.solution(r)
         t1 = time.perf_counter()
@@ -340,7 +344,8 @@ def bench_solution(seed, reps=5):
     ctx.close()
     walk = float(np.median(ms))
     one = {"workload": f"seg1024: 1024x1024, seed {seed}, T={w.threshold}, depth {w.max_depth}, both passes",
-           "walk_ms": walk, "call_ms": float(np.median(call)), "member_entries": members,
+           "walk_ms": walk, "call_ms": float(np.median(call)), "rounds": sol[0]["rounds"],
+           "detect_ms": float(np.median(det[1:])), "member_entries": members,
            "kept": [s["kept"] for s in sol], "plotted": [s["plotted_points"] for s in sol],
            "alg_bytes": nbytes, "GB/s": nbytes / (walk / 1e3) / 1e9,
            "frac": nbytes / (walk / 1e3) / 1e9 / HBM_PEAK_GBS, "workgroups": 2}

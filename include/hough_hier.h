@@ -418,10 +418,15 @@ HH_API hh_status hough_hier_result_timing(const hh_result* res, hh_timing* timin
  * visiting order) iff more than T of its voters were not plotted by an earlier
  * kept cell, and then plots its voters; the plotted points are the output
  * image.  Passes are independent (each has its own plotted set).
- * hough_hier_solution computes this on the device for n results (one launch
- * for all their passes; results of a serving context are walked on the lane
- * that made them); a result already solved is skipped.  *kernel_ms (may be
- * NULL) receives the summed duration of the walk kernels.  While it runs the
+ * hough_hier_solution computes this on the device for n results (all their
+ * passes together; results of a serving context are walked on the lane that
+ * made them); a result already solved is skipped.  The walk of a pass is cut
+ * into segments of consecutive cells, each walked by one workgroup from the
+ * points the segments before it plotted in the previous round; rounds repeat
+ * until no segment's starting points change, which gives exactly the
+ * sequential walk.  *kernel_ms (may be NULL) receives the device time from
+ * the first round to the outputs, the host's checks between rounds
+ * included.  While it runs the
  * call holds device memory for the voter ids of all its results (4 bytes per
  * voter, kept in the context's pool for later calls); the flags (a byte per
  * cell, and per point and pass) stay with the results until they are freed.
@@ -437,6 +442,7 @@ typedef struct {
     int64_t n_points;
     int64_t kept;             /* number of kept cells                                              */
     int64_t plotted_points;   /* number of plotted points                                          */
+    int64_t rounds;           /* rounds of segment walks of the hough_hier_solution call           */
 } hh_solution;
 
 /* on_device = 1 returns device arrays, on_device = 0 host copies owned by the

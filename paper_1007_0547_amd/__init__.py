@@ -101,7 +101,8 @@ class _Launch(C.Structure):
 
 class _Solution(C.Structure):
     _fields_ = [("keep", C.c_void_p), ("n_cells", C.c_int64), ("plotted", C.c_void_p), ("n_points", C.c_int64),
-                ("kept", C.c_int64), ("plotted_points", C.c_int64)]
+                ("kept", C.c_int64), ("plotted_points", C.c_int64),
+                ("rounds", C.c_int64)]
 
 
 CELL_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("votes", np.int32), ("pass", np.int32),
@@ -266,7 +267,8 @@ class Result:
         if out.n_points and out.plotted:
             plotted = np.frombuffer((C.c_uint8 * out.n_points).from_address(out.plotted),
                                     dtype=np.uint8).astype(bool)
-        return {"keep": keep, "plotted": plotted, "kept": out.kept, "plotted_points": out.plotted_points}
+        return {"keep": keep, "plotted": plotted, "kept": out.kept, "plotted_points": out.plotted_points,
+                "rounds": out.rounds}
 
     def solution_image(self, out=None) -> np.ndarray:
         """The output image of :func:`solution` (255 at plotted points of any

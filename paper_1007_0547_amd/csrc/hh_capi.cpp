@@ -314,6 +314,7 @@ hh_status hough_hier_result_solution(hh_result* res, int32_t pass, int32_t on_de
     out->n_points = res->info.n_points;
     out->kept = res->sol_kept[pass];
     out->plotted_points = res->sol_plotted[pass];
+    out->rounds = res->sol_rounds;
     if (on_device) {
         out->keep = res->sol + res->sol_keep_off[pass];
         out->plotted = res->sol + res->sol_plot_off[pass];

@@ -1508,8 +1508,7 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
     auto flags = std::make_shared<DevBuf>(&ctx->pool, (size_t)flag_bytes);
     if (!ids || !cells || !table || !*flags) throw Error{HH_ENOMEM, "solution buffers"};
     std::vector<SolTree> lds, dev;
-    int64_t max_lds_points = 0, dev_words = 0;
-    std::vector<int64_t> dev_word_off;
+    int64_t max_lds_points = 0;
     for (size_t k = 0; k < nr; ++k) {
         hh_result* r = todo[k];
         const int64_t E = r->info.n_points, slots = r->info.member_slots;
@@ -1553,33 +1552,114 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
                 max_lds_points = std::max(max_lds_points, E);
                 lds.push_back(t);
             } else {
-                dev_word_off.push_back(dev_words);
-                dev_words += (((E + 31) >> 5) + 63) & ~(int64_t)63;
                 dev.push_back(t);
             }
         }
     }
-    // longest walks first: workgroups start in launch order, so a long walk
-    // started last would run on alone
-    std::stable_sort(lds.begin(), lds.end(), [](const SolTree& a, const SolTree& b) { return a.n_slots > b.n_slots; });
-    const int32_t n_lds = (int32_t)lds.size(), n_dev = (int32_t)dev.size();
-    DevBuf bitmap;
-    if (n_dev > 0) {
-        bitmap = DevBuf(&ctx->pool, (size_t)dev_words * 4);
-        if (!bitmap) throw Error{HH_ENOMEM, "solution bitmaps"};
-        check(hipMemsetAsync(bitmap.get(), 0, (size_t)dev_words * 4, st), "clear bitmaps");
-        for (int32_t k = 0; k < n_dev; ++k) dev[(size_t)k].bitmap = bitmap.as<uint32_t>() + dev_word_off[(size_t)k];
-    }
+    // Segments: consecutive cells of about kSolSegSlots voter entries (cut by
+    // cell count), at most kSolMaxSegs per tree, and only as many as it takes
+    // for two segments per compute unit over all trees (a batch of many
+    // trees walks each in one segment, in one round); LDS trees first.
+    // Bitmaps per segment: in, out (and a work bitmap for device-bitmap
+    // trees); per tree: all.
+    constexpr int64_t kSolSegSlots = 1 << 16;
     std::vector<SolTree> all(lds);
     all.insert(all.end(), dev.begin(), dev.end());
-    const size_t table_bytes = (size_t)align256((int64_t)(std::max<size_t>(all.size(), 1) * sizeof(SolTree)));
-    DevBuf d(&ctx->pool, table_bytes + 256);
+    const int32_t n_trees = (int32_t)all.size(), n_lds_trees = (int32_t)lds.size();
+    const int64_t seg_cap = std::max<int64_t>(1, 2 * (int64_t)ctx->cu_count / std::max<int32_t>(n_trees, 1));
+    std::vector<SolSeg> segs;
+    std::vector<int64_t> seg_words;   // bitmap word offsets of each segment: in, out, work
+    int64_t words_total = 0, max_words = 1, max_segs = 1;
+    int32_t n_lds = 0;
+    std::vector<int64_t> all_off((size_t)n_trees);
+    for (int32_t k = 0; k < n_trees; ++k) {
+        SolTree& t = all[(size_t)k];
+        const int64_t words = ((t.n_points + 31) >> 5 | 1) + 63 & ~(int64_t)63;
+        max_words = std::max(max_words, (t.n_points + 31) >> 5);
+        all_off[(size_t)k] = words_total;
+        words_total += words;
+        const int64_t K = t.n_cells == 0 ? 0
+                          : std::min({(int64_t)kSolMaxSegs, seg_cap, t.n_cells,
+                                      std::max<int64_t>(1, (t.n_slots + kSolSegSlots - 1) / kSolSegSlots)});
+        max_segs = std::max(max_segs, K);
+        t.seg0 = (int32_t)segs.size();
+        t.n_segs = (int32_t)K;
+        for (int64_t q = 0; q < K; ++q) {
+            SolSeg g{};
+            g.tree = k;
+            g.c0 = t.n_cells * q / K;
+            g.c1 = t.n_cells * (q + 1) / K;
+            segs.push_back(g);
+            seg_words.push_back(words_total);
+            words_total += (k < n_lds_trees ? 2 : 3) * words;
+        }
+        if (k < n_lds_trees) n_lds = (int32_t)segs.size();
+    }
+    const int32_t n_segs = (int32_t)segs.size(), n_dev = n_segs - n_lds;
+    DevBuf bitmaps(&ctx->pool, (size_t)std::max<int64_t>(words_total, 1) * 4);
+    if (!bitmaps) throw Error{HH_ENOMEM, "solution bitmaps"};
+    check(hipMemsetAsync(bitmaps.get(), 0, (size_t)std::max<int64_t>(words_total, 1) * 4, st), "clear bitmaps");
+    uint32_t* const bw = bitmaps.as<uint32_t>();
+    for (int32_t k = 0; k < n_trees; ++k) all[(size_t)k].all = bw + all_off[(size_t)k];
+    for (int32_t q = 0; q < n_segs; ++q) {
+        SolSeg& g = segs[(size_t)q];
+        const SolTree& t = all[(size_t)g.tree];
+        const int64_t words = ((t.n_points + 31) >> 5 | 1) + 63 & ~(int64_t)63;
+        g.in = bw + seg_words[(size_t)q];
+        g.out = g.in + words;
+        g.work = q >= n_lds ? g.out + words : nullptr;
+        g.counts = nullptr;   // set below, in the table buffer
+    }
+    const size_t trees_bytes = (size_t)align256((int64_t)(std::max<int32_t>(n_trees, 1) * sizeof(SolTree)));
+    const size_t segs_bytes = (size_t)align256((int64_t)(std::max<int32_t>(n_segs, 1) * sizeof(SolSeg)));
+    const size_t cnt_bytes = (size_t)align256((int64_t)std::max<int32_t>(n_segs, 1) * 16);
+    const size_t list_bytes = (size_t)align256((int64_t)std::max<int32_t>(n_segs, 1) * 4);
+    const size_t tree_int_bytes = (size_t)align256((int64_t)std::max<int32_t>(n_trees, 1) * 4);
+    const size_t flag_seg_bytes = (size_t)align256((int64_t)std::max<int32_t>(n_segs, 1));
+    DevBuf d(&ctx->pool, trees_bytes + segs_bytes + cnt_bytes + 4 * list_bytes + tree_int_bytes + flag_seg_bytes + 256);
     if (!d) throw Error{HH_ENOMEM, "solution table"};
-    uint32_t* d_err = reinterpret_cast<uint32_t*>(d.as<char>() + table_bytes);
-    if (!all.empty())
-        check(hipMemcpyAsync(d.get(), all.data(), all.size() * sizeof(SolTree), hipMemcpyHostToDevice, st),
-              "copy table");
-    check(hipMemsetAsync(d_err, 0, 4, st), "clear error");
+    char* dp = d.as<char>();
+    SolTree* const d_trees = reinterpret_cast<SolTree*>(dp);
+    dp += trees_bytes;
+    SolSeg* const d_segs = reinterpret_cast<SolSeg*>(dp);
+    dp += segs_bytes;
+    int64_t* const d_cnt = reinterpret_cast<int64_t*>(dp);
+    dp += cnt_bytes;
+    int32_t* lists[4];   // two rounds' lists: LDS, device, LDS, device
+    for (auto& l : lists) {
+        l = reinterpret_cast<int32_t*>(dp);
+        dp += list_bytes;
+    }
+    int32_t* const d_first = reinterpret_cast<int32_t*>(dp);
+    dp += tree_int_bytes;
+    uint8_t* const d_changed = reinterpret_cast<uint8_t*>(dp);
+    dp += flag_seg_bytes;
+    uint32_t* const d_err = reinterpret_cast<uint32_t*>(dp);   // error, then the list sizes of both rounds
+    int32_t* const d_nlist = reinterpret_cast<int32_t*>(dp + 16);
+    for (int32_t q = 0; q < n_segs; ++q) segs[(size_t)q].counts = d_cnt + 2 * q;
+    // the first round walks every segment
+    std::vector<int32_t> first_list((size_t)std::max<int32_t>(n_segs, 1));
+    for (int32_t q = 0; q < n_segs; ++q) first_list[(size_t)q] = q;
+    const std::vector<int32_t> no_walk((size_t)std::max<int32_t>(n_trees, 1), INT32_MAX);
+    const int32_t first_n[4] = {n_lds, n_dev, 0, 0};
+    if (n_trees > 0) {
+        check(hipMemcpyAsync(d_trees, all.data(), (size_t)n_trees * sizeof(SolTree), hipMemcpyHostToDevice, st),
+              "copy trees");
+        check(hipMemcpyAsync(d_first, no_walk.data(), (size_t)n_trees * 4, hipMemcpyHostToDevice, st), "copy marks");
+    }
+    if (n_segs > 0) {
+        check(hipMemcpyAsync(d_segs, segs.data(), (size_t)n_segs * sizeof(SolSeg), hipMemcpyHostToDevice, st),
+              "copy segments");
+        if (n_lds > 0)
+            check(hipMemcpyAsync(lists[0], first_list.data(), (size_t)n_lds * 4, hipMemcpyHostToDevice, st),
+                  "copy list");
+        if (n_dev > 0)
+            check(hipMemcpyAsync(lists[1], first_list.data() + n_lds, (size_t)n_dev * 4, hipMemcpyHostToDevice, st),
+                  "copy list");
+        check(hipMemsetAsync(d_changed, 0, (size_t)n_segs, st), "clear marks");
+    }
+    check(hipMemsetAsync(d_err, 0, 16, st), "clear error");
+    check(hipMemcpyAsync(d_nlist, first_n, sizeof(first_n), hipMemcpyHostToDevice, st), "copy list sizes");
     hipEvent_t ev[2];
     check(hipEventCreate(&ev[0]), "event");
     if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -1594,16 +1674,48 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
             (void)hipEventDestroy(e[1]);
         }
     } guard{ev};
+    // Rounds until no segment's input changes (at most one per segment, plus
+    // one), queued 2, 4, 8, 8, ... at a time between checks on the host; a
+    // round with empty lists costs only its launches.
+    SolRound rd{};
+    rd.trees = d_trees;
+    rd.segs = d_segs;
+    rd.n_trees = n_trees;
+    rd.n_segs = n_segs;
+    rd.n_lds = n_lds;
+    rd.grid = 2 * ctx->cu_count;
+    rd.max_lds_points = max_lds_points;
+    rd.max_words = max_words;
+    rd.first_walked = d_first;
+    rd.changed = d_changed;
+    rd.error = d_err;
     check(hipEventRecord(ev[0], st), "event");
-    check(launch_solution(d.as<SolTree>(), n_lds, max_lds_points, n_dev, d_err, st), "solution");
+    int rounds = 0, parity = 0;
+    for (int batch = 2;; batch = std::min(batch * 2, 8)) {
+        for (int b = 0; b < batch; ++b) {
+            rd.list_lds = lists[2 * parity];
+            rd.list_dev = lists[2 * parity + 1];
+            rd.n_list = d_nlist + 2 * parity;
+            rd.next_lds = lists[2 * (1 - parity)];
+            rd.next_dev = lists[2 * (1 - parity) + 1];
+            rd.n_next = d_nlist + 2 * (1 - parity);
+            check(launch_solution_round(rd, st), "solution round");
+            parity = 1 - parity;
+            ++rounds;
+        }
+        uint32_t h[4] = {0, 0, 0, 0};   // error, pad, list sizes of the next round
+        check(hipMemcpyAsync(h, d_err, 4, hipMemcpyDeviceToHost, st), "copy error");
+        check(hipMemcpyAsync(h + 2, d_nlist + 2 * parity, 8, hipMemcpyDeviceToHost, st), "copy list sizes");
+        sync(ctx);
+        if (h[0]) throw Error{HH_EINTERNAL, "solution: malformed cells or member ids"};
+        if (h[2] == 0 && h[3] == 0) break;
+        if (rounds > max_segs + 16) throw Error{HH_EINTERNAL, "solution: the segment rounds did not settle"};
+    }
+    check(launch_solution_finish(d_trees, n_trees, d_segs, st), "solution finish");
     check(hipEventRecord(ev[1], st), "event");
-    // errors and counts of every result come back in two copies
+    // the counts of every result come back in one copy each
     std::vector<int64_t> counts(4 * nr, 0);
-    std::vector<char> hflags;
-    uint32_t err = 0;
-    check(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, st), "copy error");
     sync(ctx);
-    if (err) throw Error{HH_EINTERNAL, "solution: malformed cells or member ids"};
     float ms = 0.f;
     check(hipEventElapsedTime(&ms, ev[0], ev[1]), "event time");
     if (kernel_ms) *kernel_ms = ms;
@@ -1619,6 +1731,7 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
             r->sol_kept[p] = counts[4 * k + 2 * p];
             r->sol_plotted[p] = counts[4 * k + 2 * p + 1];
         }
+        r->sol_rounds = rounds;
         r->sol_ready = true;
     }
     return HH_OK;

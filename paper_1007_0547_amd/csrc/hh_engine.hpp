@@ -199,6 +199,7 @@ struct hh_result {
     int64_t sol_counts_off = 0;
     int64_t sol_kept[2] = {0, 0};
     int64_t sol_plotted[2] = {0, 0};
+    int64_t sol_rounds = 0;
     bool host_sol_ready[2] = {false, false};
     std::vector<uint8_t> host_keep[2];
     std::vector<uint8_t> host_plotted[2];

@@ -10,8 +10,20 @@
 // key order, that keeps a cell iff more than T of its voters are not yet
 // plotted and then plots them.
 //
-// The walk is sequential by definition; one workgroup walks one tree.  It
-// streams the tree's voter ids in windows of kSolCh entries held in registers
+// The walk is sequential by definition.  It runs here as a fixpoint of
+// independent walks: a tree's cells are cut into segments of consecutive
+// cells, one workgroup each, and every segment walks its cells starting from
+// an input set of points taken as plotted before it.  After a round, each
+// segment's input becomes the union of the points the segments before it
+// plotted in that round; when no input changes, every segment walked from
+// exactly the points the cells before it plot, so the rounds reproduce the
+// sequential walk (the first segment's input is always empty, so after r
+// rounds the first r segments are exact, and at most one round per segment
+// plus one is needed).  Kept cells are few and each one's influence reaches
+// few segments, so a handful of rounds suffice in practice.
+//
+// One workgroup walks one segment.  It
+// streams the segment's voter ids in windows of kSolCh entries held in registers
 // (kSolR consecutive entries per lane, the next window's loaded while this one
 // is processed).  Each lane tests its entries against the plotted set and
 // stores its live bits into the window's live bitmap in LDS; the lane of each
@@ -23,9 +35,9 @@
 // else in device memory behind atomics at workgroup scope (performed in L2,
 // one copy for all waves of the workgroup).
 //
-// The walk of one tree runs on one compute unit and is bound by its vector ALU
-// issue (the live test, the window setup) and by the latency of each window's
-// loads; many trees (a batch) fill the device.
+// The walk of one segment runs on one compute unit and is bound by its vector
+// ALU issue (the live test, the window setup) and by the latency of each
+// window's loads; many segments fill the device.
 
 #include <hip/hip_runtime.h>
 
@@ -128,20 +140,21 @@ __device__ inline void load_ids(const int32_t* ids, int64_t n_slots, int64_t ab,
 }
 
 // Voter range of cell c (off, votes) and the start of the cell after it
-// (next; -1: c is the last cell).  Kept as loaded, so that a prefetch is not
-// waited for before the values are used.
+// (next; -1: c is the last cell of the segment, which ends before c_end).
+// Kept as loaded, so that a prefetch is not waited for before the values are
+// used.
 struct SolCell {
     int64_t off, next;
     int32_t votes;
 };
 
-__device__ inline SolCell load_cell(const SolTree& t, int64_t c)
+__device__ inline SolCell load_cell(const SolTree& t, int64_t c, int64_t c_end)
 {
     SolCell r{0, -1, 0};
-    if (c < t.n_cells) {
+    if (c < c_end) {
         r.off = ldg(&t.cells[c].member_off);
         r.votes = ldg(&t.cells[c].votes);
-        if (c + 1 < t.n_cells) r.next = ldg(&t.cells[c + 1].member_off);
+        if (c + 1 < c_end) r.next = ldg(&t.cells[c + 1].member_off);
     }
     return r;
 }
@@ -186,8 +199,13 @@ __device__ inline int32_t live_in(const uint32_t* live, int32_t cs, int32_t ce)
     return n;
 }
 
+// The walks of the segments in list[0 .. *n_list), a workgroup taking list
+// entries blockIdx.x, blockIdx.x + gridDim.x, ...; each walked segment
+// lowers its tree's first_walked to its index.
 template <bool kLds>
-__global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, uint32_t* error)
+__global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, const SolSeg* segs, const int32_t* list,
+                                                           const int32_t* n_list, int32_t* first_walked,
+                                                           uint32_t* error)
 {
     extern __shared__ uint32_t s_bits[];
     __shared__ uint32_t s_live[kSolCh / 32];     // the window's live bitmap, kSolR bits per lane
@@ -197,12 +215,19 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
     __shared__ int64_t s_wend, s_off0;
     __shared__ int32_t s_nw, s_carry, s_last_done, s_bad_cells, s_bad_ids, s_bad_mark, s_plotted;
 
-    const SolTree t = trees[blockIdx.x];
+    const int32_t n_walk = ldg(n_list);
+    for (int32_t li = blockIdx.x; li < n_walk; li += gridDim.x) {
+    const int32_t si = ldg(list + li);
+    const SolSeg sg = segs[si];
+    const SolTree t = trees[sg.tree];
+    const int64_t c_end = sg.c1;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    uint32_t* bits = kLds ? s_bits : t.bitmap;
-    if constexpr (kLds) {
-        const int64_t words = (t.n_points + 31) >> 5;
-        for (int64_t w = tid; w < words; w += kSolThreads) s_bits[w] = 0;
+    uint32_t* bits = kLds ? s_bits : sg.work;
+    const int64_t words = (t.n_points + 31) >> 5;
+    // the points plotted before the segment
+    for (int64_t w = tid; w < words; w += kSolThreads) {
+        if constexpr (kLds) s_bits[w] = ldg(sg.in + w);
+        else stg(sg.work + w, ldg(sg.in + w));
     }
     if (tid == 0) {
         s_bad_cells = 0;
@@ -217,16 +242,16 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
     const uint32_t n_points = (uint32_t)t.n_points;              // ids are 32-bit
     LaneBits* live_byte = reinterpret_cast<LaneBits*>(s_live) + tid;
     const int x0 = kSolR * tid;                                   // this lane's first window position
-    int64_t c_cur = 0;                                            // first undecided cell
-    int64_t pos = t.n_cells > 0 ? ldg(&t.cells[0].member_off) : 0;   // its first untested voter
+    int64_t c_cur = sg.c0;                                        // first undecided cell
+    int64_t pos = c_cur < c_end ? ldg(&t.cells[c_cur].member_off) : 0;   // its first untested voter
     int64_t kept = 0;
     int32_t plotted = 0;                                          // bits this lane set
     bool bad = false;
     // this window's and the next window's cells and ids, loaded one window ahead
-    SolCell cell = tid < kSolMaxCells ? load_cell(t, c_cur + tid) : SolCell{0, -1, 0};
+    SolCell cell = tid < kSolMaxCells ? load_cell(t, c_cur + tid, c_end) : SolCell{0, -1, 0};
     int32_t id[kSolR], nid[kSolR];
-    if (t.n_cells > 0) load_ids(t.ids, t.n_slots, pos & ~(int64_t)3, tid, nid);
-    while (c_cur < t.n_cells) {
+    if (c_cur < c_end) load_ids(t.ids, t.n_slots, pos & ~(int64_t)3, tid, nid);
+    while (c_cur < c_end) {
         const int64_t ab = pos & ~(int64_t)3;   // window base, aligned for 16-byte loads
         const int64_t limit = ab + kSolCh;
         // The window's cells: c_cur and the cells that start before limit.  The
@@ -235,12 +260,12 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         const int64_t c = c_cur + tid;
         const int64_t off = cell.off, end = cell.off + cell.votes;
         const int64_t next = cell.next < 0 ? end : cell.next;
-        if (tid < kSolMaxCells && c < t.n_cells) {
+        if (tid < kSolMaxCells && c < c_end) {
             const bool in = tid == 0 || off < limit;
             const bool ok = end > off && off >= 0 && end <= t.n_slots && next == end &&
                             (tid > 0 || (pos >= off && pos < end));
             if (in && !ok) s_bad_cells = 1;
-            if (in && (tid == kSolMaxCells - 1 || c + 1 >= t.n_cells || next >= limit)) {
+            if (in && (tid == kSolMaxCells - 1 || c + 1 >= c_end || next >= limit)) {
                 s_nw = tid + 1;
                 s_wend = end < limit ? end : limit;
                 s_last_done = end <= limit;
@@ -280,8 +305,8 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         }
         // Prefetch the next window (its first cell and base are known now).
         const int64_t c_next = last_done ? c_cur + n_w : c_cur + n_w - 1;
-        if (c_next < t.n_cells) {
-            if (tid < kSolMaxCells) cell = load_cell(t, c_next + tid);
+        if (c_next < c_end) {
+            if (tid < kSolMaxCells) cell = load_cell(t, c_next + tid, c_end);
             load_ids(t.ids, t.n_slots, w_end & ~(int64_t)3, tid, nid);
         }
         // Take the first cell above T, plot it, test again; until none is left.
@@ -348,21 +373,107 @@ __global__ __launch_bounds__(kSolThreads) void k_solution(const SolTree* trees, 
         pos = w_end;
     }
 
-    // Output: plotted flags per point id, the kept cells and plotted points.
+    // Output: the points this segment plotted (beyond its input), its kept
+    // cells and plotted points.
     for (int d = kWave / 2; d > 0; d >>= 1) plotted += __shfl_xor(plotted, d, kWave);
     if (lane == 0) atomicAdd(&s_plotted, plotted);
     sol_barrier<kLds>();
-    const int64_t words = (t.n_points + 31) >> 5;
-    for (int64_t w = tid; w < words; w += kSolThreads) {
-        const uint32_t x = bit_word<kLds>(bits, w);
-        const int64_t k0 = w * 32;
-        const int nb = t.n_points - k0 < 32 ? (int)(t.n_points - k0) : 32;
-        for (int b = 0; b < nb; ++b) stg(t.plotted + k0 + b, (uint8_t)((x >> b) & 1u));
-    }
+    for (int64_t w = tid; w < words; w += kSolThreads) stg(sg.out + w, bit_word<kLds>(bits, w) & ~ldg(sg.in + w));
     if (tid == 0) {
-        stg(t.counts, kept);
-        stg(t.counts + 1, (int64_t)s_plotted);
+        stg(sg.counts, kept);
+        stg(sg.counts + 1, (int64_t)s_plotted);
+        atomicMin(first_walked + sg.tree, si);
         if (bad) __hip_atomic_fetch_or(G(error), kErrInternal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    sol_barrier<kLds>();   // the next segment sets up the workgroup's tables again
+    }
+}
+
+// After a round: in each tree with a walked segment, the input of every
+// segment becomes the union of what the segments before it plotted (an
+// exclusive OR-scan over the tree's segments, one thread per segment, for
+// kMergeWords bitmap words per workgroup), and the tree's `all` the union of
+// every segment's; a segment whose input changed is marked in changed[].
+constexpr int kMergeThreads = kSolMaxSegs;   // one thread per segment of a tree
+constexpr int kMergeWords = 4;
+
+__global__ __launch_bounds__(kMergeThreads) void k_solution_merge(const SolTree* trees, const SolSeg* segs,
+                                                                  int64_t blocks_per_tree,
+                                                                  const int32_t* first_walked, uint8_t* changed)
+{
+    __shared__ uint32_t s_wave[kMergeThreads / kWave];
+    const int32_t k = (int32_t)(blockIdx.x / blocks_per_tree);
+    const int64_t w0 = (blockIdx.x - (int64_t)k * blocks_per_tree) * kMergeWords;
+    const SolTree& t = trees[k];
+    const int32_t f = ldg(first_walked + k);
+    const int64_t words = (t.n_points + 31) >> 5;
+    if (f < t.seg0 || f >= t.seg0 + t.n_segs || w0 >= words) return;   // uniform: nothing walked here
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const bool mine = tid < t.n_segs;
+    const SolSeg* sg = segs + t.seg0 + (mine ? tid : 0);
+    bool moved = false;
+    for (int64_t w = w0; w < w0 + kMergeWords && w < words; ++w) {
+        const uint32_t o = mine ? ldg(sg->out + w) : 0u;
+        // inclusive OR-scan within the wave, then across the waves
+        uint32_t x = o;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+            if (lane >= d) x |= y;
+        }
+        if (lane == kWave - 1) s_wave[wave] = x;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int v = 0; v < kMergeThreads / kWave; ++v) {
+            if (v < wave) before |= s_wave[v];
+            total |= s_wave[v];
+        }
+        __syncthreads();   // s_wave is rewritten for the next word
+        const uint32_t below = (uint32_t)__shfl_up((int)x, 1, kWave);   // inclusive scan of the lane before
+        const uint32_t in_new = before | (lane > 0 ? below : 0u);
+        if (mine && ldg(sg->in + w) != in_new) {
+            stg(sg->in + w, in_new);
+            moved = true;
+        }
+        if (tid == 0) stg(t.all + w, total);
+    }
+    if (moved) stg(changed + t.seg0 + tid, (uint8_t)1);
+}
+
+// The next round's lists: the segments marked changed (marks cleared), LDS
+// segments (index < n_lds) and device-bitmap ones apart, appended at the
+// counters n_next[0] and n_next[1] (zero before); every tree's first_walked
+// goes back to INT_MAX.
+__global__ void k_solution_collect(int32_t n_segs, int32_t n_lds, uint8_t* changed, int32_t* next_lds,
+                                   int32_t* next_dev, int32_t* n_next, int32_t* first_walked, int32_t n_trees)
+{
+    const int64_t n = n_segs > n_trees ? n_segs : n_trees;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        if (q < n_trees) stg(first_walked + q, (int32_t)INT_MAX);
+        if (q < n_segs && ldg(changed + q)) {
+            stg(changed + q, (uint8_t)0);
+            if (q < n_lds) next_lds[atomicAdd(n_next, 1)] = (int32_t)q;
+            else next_dev[atomicAdd(n_next + 1, 1)] = (int32_t)q;
+        }
+    }
+}
+
+// Once no input changes: per tree, the plotted flag of every point and the
+// kept cells and plotted points over its segments.
+__global__ void k_solution_finish(const SolTree* trees, int32_t n_trees, const SolSeg* segs)
+{
+    const SolTree& t = trees[blockIdx.x];
+    for (int64_t k = threadIdx.x; k < t.n_points; k += blockDim.x)
+        stg(t.plotted + k, (uint8_t)((ldg(t.all + (k >> 5)) >> (k & 31)) & 1u));
+    if (threadIdx.x == 0) {
+        int64_t kept = 0, plotted = 0;
+        for (int32_t s = t.seg0; s < t.seg0 + t.n_segs; ++s) {
+            kept += ldg(segs[s].counts);
+            plotted += ldg(segs[s].counts + 1);
+        }
+        stg(t.counts, kept);
+        stg(t.counts + 1, plotted);
     }
 }
 
@@ -437,15 +548,34 @@ hipError_t launch_ids_by_pixel(const uint32_t* xy, int64_t n_points, int32_t wid
 
 int64_t solution_lds_points() { return kSolLdsPoints; }
 
-hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_points, int32_t n_dev,
-                           uint32_t* error, hipStream_t s)
+hipError_t launch_solution_round(const SolRound& r, hipStream_t s)
 {
-    if (max_lds_points > kSolLdsPoints) return hipErrorInvalidValue;
-    if (n_lds > 0) {
-        const size_t lds = (size_t)((max_lds_points + 31) >> 5) * 4;
-        k_solution<true><<<n_lds, kSolThreads, lds, s>>>(trees, error);
+    if (r.max_lds_points > kSolLdsPoints) return hipErrorInvalidValue;
+    if (r.n_lds > 0) {
+        const size_t lds = (size_t)((r.max_lds_points + 31) >> 5) * 4;
+        k_solution<true><<<std::min(r.n_lds, r.grid), kSolThreads, lds, s>>>(r.trees, r.segs, r.list_lds, r.n_list,
+                                                                            r.first_walked, r.error);
     }
-    if (n_dev > 0) k_solution<false><<<n_dev, kSolThreads, 0, s>>>(trees + n_lds, error);
+    if (r.n_segs > r.n_lds)
+        k_solution<false><<<std::min(r.n_segs - r.n_lds, r.grid), kSolThreads, 0, s>>>(
+            r.trees, r.segs, r.list_dev, r.n_list + 1, r.first_walked, r.error);
+    const int64_t per_tree = (r.max_words + kMergeWords - 1) / kMergeWords;
+    if (r.n_trees > 0 && per_tree > 0)
+        k_solution_merge<<<(unsigned)(r.n_trees * per_tree), kMergeThreads, 0, s>>>(r.trees, r.segs, per_tree,
+                                                                                    r.first_walked, r.changed);
+    hipError_t e = hipMemsetAsync(r.n_next, 0, 8, s);
+    if (e != hipSuccess) return e;
+    const int64_t m = std::max<int64_t>(r.n_segs, r.n_trees);
+    if (m > 0)
+        k_solution_collect<<<(int)std::min<int64_t>((m + 255) / 256, 4096), 256, 0, s>>>(
+            r.n_segs, r.n_lds, r.changed, r.next_lds, r.next_dev, r.n_next, r.first_walked, r.n_trees);
+    return hipGetLastError();
+}
+
+hipError_t launch_solution_finish(const SolTree* trees, int32_t n_trees, const SolSeg* segs, hipStream_t s)
+{
+    if (n_trees <= 0) return hipSuccess;
+    k_solution_finish<<<n_trees, 256, 0, s>>>(trees, n_trees, segs);
     return hipGetLastError();
 }
 

@@ -16,20 +16,60 @@ struct SolTree {
     int64_t n_slots;        // length of ids
     uint8_t* keep;          // [n_cells] 1 = the cell survives removal
     uint8_t* plotted;       // [n_points] 1 = the point was plotted
-    uint32_t* bitmap;       // n_points bits of zeroed device memory, or null: the walk keeps them in LDS
+    uint32_t* all;          // n_points bits: every point plotted by the tree's segments (after a merge)
     int64_t* counts;        // [2] kept cells, plotted points
     int32_t threshold;
+    int32_t seg0, n_segs;   // its segments: segs[seg0 .. seg0 + n_segs)
     int32_t pad;
 };
 
-// Point ids a walk keeps in LDS; trees with more points need a device bitmap.
+// One segment of a tree: cells [c0, c1), walked from the points in `in`.
+struct SolSeg {
+    int32_t tree;
+    int32_t pad;
+    int64_t c0, c1;
+    uint32_t* in;           // n_points bits: points taken as plotted before the segment
+    uint32_t* out;          // n_points bits: points the segment plotted beyond `in`
+    uint32_t* work;         // n_points bits of device memory for the walk, or null: it keeps them in LDS
+    int64_t* counts;        // [2] kept cells, plotted points of the segment
+};
+
+// Point ids a walk keeps in LDS; trees with more points need device bitmaps.
 int64_t solution_lds_points();
-// The walk of n_lds trees with LDS bitmaps (trees[0 .. n_lds)) and n_dev
-// trees with device bitmaps (trees[n_lds ...]); max_lds_points is the
-// largest n_points among the first.  A malformed tree (cells not back to back,
-// an id out of range) raises kErrInternal in *error.
-hipError_t launch_solution(const SolTree* trees, int32_t n_lds, int64_t max_lds_points, int32_t n_dev,
-                           uint32_t* error, hipStream_t s);
+
+constexpr int kSolMaxSegs = 128;   // segments of one tree (the walk settled in fewer rounds than with 256 or 64 on the 1024x1024 image)
+
+// One round of segment walks and what follows them.  Segments of a tree are
+// consecutive in segs, in cell order; segs[0 .. n_lds) are of trees that keep
+// their bitmap in LDS (at most max_lds_points points), the rest use device
+// bitmaps.
+struct SolRound {
+    const SolTree* trees;
+    const SolSeg* segs;
+    int32_t n_trees, n_segs, n_lds;
+    int32_t grid;                 // most workgroups of a walk launch
+    int64_t max_lds_points;
+    int64_t max_words;            // the largest bitmap, in 32-bit words
+    const int32_t* list_lds;      // this round's segments: LDS ones, device ones,
+    const int32_t* list_dev;
+    const int32_t* n_list;        // and their numbers ([0], [1])
+    int32_t* next_lds;            // the next round's, made by this one
+    int32_t* next_dev;
+    int32_t* n_next;
+    int32_t* first_walked;        // [n_trees] INT_MAX between rounds
+    uint8_t* changed;             // [n_segs] zero between rounds
+    uint32_t* error;              // kErrInternal: a malformed tree (cells not back to back, an id out of range)
+};
+
+// The walks of the round's segments, then per tree with a walked segment the
+// inputs of the segments from it on (the union of the outputs before each;
+// `all`, the union of every output), and the next round's lists: the
+// segments whose input changed.  No segment in the next lists: every input
+// stands, and the walk is done.
+hipError_t launch_solution_round(const SolRound& r, hipStream_t s);
+// Once a merge changed nothing: per tree, plotted flags from `all` and the
+// counts summed over its segments.
+hipError_t launch_solution_finish(const SolTree* trees, int32_t n_trees, const SolSeg* segs, hipStream_t s);
 
 // Point ids of packed-point voter entries (binary-image inputs, whose ids are
 // the row-major ranks of their edge points xy[0 .. n_points)): a W x H table
