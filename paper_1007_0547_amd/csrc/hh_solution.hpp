@@ -37,7 +37,7 @@ struct SolSeg {
 // Point ids a walk keeps in LDS; trees with more points need device bitmaps.
 int64_t solution_lds_points();
 
-constexpr int kSolMaxSegs = 128;   // segments of one tree (the walk settled in fewer rounds than with 256 or 64 on the 1024x1024 image)
+constexpr int kSolMaxSegs = 128;   // segments of one tree (the fastest of 64, 128 and 256 on the 1024x1024 image)
 
 // One round of segment walks and what follows them.  Segments of a tree are
 // consecutive in segs, in cell order; segs[0 .. n_lds) are of trees that keep
