@@ -236,7 +236,7 @@ typedef struct {
  * hands out queue_batch consecutive tasks at a time.  Results do not depend
  * on the launch shape; only the time does. */
 typedef struct {
-    int32_t task_steps;       /* 512-entry steps per task, 1..64 (0: default 4)       */
+    int32_t task_steps;       /* 512-entry steps per task, 1..64 (0: default 8)       */
     int32_t queue_batch;      /* 0: fixed share; 1..1024: tasks per take from the queue */
     int32_t wg_per_cu;        /* resident workgroups per compute unit, 0: as many as fit */
     int32_t reserved;

@@ -74,7 +74,7 @@ void hough_hier_destroy(hh_ctx* ctx)
 hh_status hough_hier_set_launch(hh_ctx* ctx, const hh_launch* launch)
 {
     if (!ctx || !launch) return HH_EINVAL;
-    const int32_t steps = launch->task_steps ? launch->task_steps : 4;
+    const int32_t steps = launch->task_steps ? launch->task_steps : 8;
     if (steps < 1 || steps > hh::kMaxTaskSteps || launch->queue_batch < 0 || launch->queue_batch > 1024 ||
         launch->wg_per_cu < 0 || launch->wg_per_cu > 64)
         return fail(ctx, HH_EINVAL, "launch shape out of range");

@@ -505,6 +505,26 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
     return p;
 }
 
+// The message of an internal error: the checks that failed and their levels.
+std::string internal_error_text(uint32_t err)
+{
+    std::string m = "a kernel index failed its range check";
+    const std::pair<uint32_t, const char*> at[] = {
+        {kErrAtCountTask, "k_count: a task's region or range out of bounds"},
+        {kErrAtWriteTask, "k_write: a task's region or range out of bounds"},
+        {kErrAtWriteVotes, "k_write: a kept child's votes differ from its count"},
+        {kErrAtEmit, "emit: a region or task index past the level's totals"},
+    };
+    std::string what;
+    for (const auto& a : at)
+        if (err & a.first) what += (what.empty() ? "" : "; ") + std::string(a.second);
+    std::string levels;
+    for (int l = 0; l < kMaxLevels && kErrLevelShift + l < 32; ++l)
+        if (err & (1u << (kErrLevelShift + l))) levels += (levels.empty() ? "" : ",") + std::to_string(l);
+    if (!what.empty()) m += " (" + what + (levels.empty() ? "" : "; level " + levels) + ")";
+    return m;
+}
+
 // The stage of a call whose sizes did not fit the caps c, from the level
 // records the call left (the same checks the kernels make): -1 the root setup
 // (level 0), l >= 0 the split decision of level l (its children's sizes are
@@ -1140,7 +1160,7 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             ctx->group_points = std::max<int64_t>(1, sum / 2);
             continue;
         }
-        if (g.err & kErrInternal) throw Error{HH_EINTERNAL, "a kernel index failed its range check"};
+        if (g.err & kErrInternal) throw Error{HH_EINTERNAL, internal_error_text(g.err)};
         if (*h_err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
         counts_known = true;
 

@@ -248,7 +248,7 @@ struct hh_ctx {
     // launch shape of the list kernels: steps (512 entries) per task, tasks a
     // wavefront takes from the level's queue at once (0: a fixed share), and
     // resident workgroups per compute unit (0: as many as fit)
-    int32_t task_steps = 4;
+    int32_t task_steps = 8;
     int32_t queue_batch = 0;
     int32_t wg_per_cu = 0;
     int64_t arena_hint_bytes = 0;   // > 0: size of a call's first level arena (serving lanes set it per batch)

@@ -83,6 +83,17 @@ __device__ inline uint32_t lanes_below(uint64_t b)
 
 __device__ inline uint64_t bits_below(int p) { return ((uint64_t)1 << p) - 1; }   // p in 0..63
 
+// acc + (this lane's bit of mask): one vector add with the mask as its
+// carry-in (the compiler makes a select and an add of `acc + bit`); no
+// memory access in the asm
+__device__ __forceinline__ int32_t add_lane_bit(int32_t acc, uint64_t mask)
+{
+    int32_t out;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(out), "=s"(carry) : "v"(acc), "s"(mask));
+    return out;
+}
+
 // This lane's bit of a wavefront-uniform lane mask, as a lane predicate: the
 // mask itself serves as the execution mask, with no vector instruction.
 __device__ inline bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
@@ -436,7 +447,7 @@ __device__ inline uint64_t row_mask(int32_t rem, int k)
 // One read of every entry: per task, the votes of its lines for each child
 // of its region (the 4-bit code of Sec. 2 and the vote rule of Sec. 3 as
 // lane masks).  Each lane counts its own votes per child, one vector add
-// per row and child, and the task's four counts are summed over the
+// with carry-in per row and child, and the task's four counts are summed over the
 // wavefront at its end: this keeps the per-row work on the vector unit,
 // which issues as often as the scalar unit but had slack.  A task stores its
 // four counts (for the ranks of the compaction pass) and adds them to its
@@ -454,7 +465,7 @@ __device__ __forceinline__ void count_rows(const RegionTest<kVariant, CT>& rt, c
         uint64_t cm[4];
         rt.masks(vm, EntryOps<Entry>::point(ent[k]), lc, cm);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lacc[q] += lane_bit(cm[q]) ? 1 : 0;
+        for (int q = 0; q < 4; ++q) lacc[q] = add_lane_bit(lacc[q], cm[q]);
     }
 }
 
@@ -519,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
         const int64_t t = feed.take();
         if (t < 0) return;
         if (!view_task(tasks, regions, P, L, task_len, t, cur)) {
-            if (lane == 0) raise_error(ar.error, kErrInternal);
+            if (lane == 0) raise_error(ar.error, kErrInternal | kErrAtCountTask | (1u << (kErrLevelShift + l)));
             return;
         }
     }
@@ -546,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_count(LevelArgs a)
             const int64_t t = feed.take();
             if (t >= 0) {
                 if (!view_task(tasks, regions, P, L, task_len, t, nxt)) {
-                    if (lane == 0) raise_error(ar.error, kErrInternal);
+                    if (lane == 0) raise_error(ar.error, kErrInternal | kErrAtCountTask | (1u << (kErrLevelShift + l)));
                     return;
                 }
                 have_next = true;
@@ -713,8 +724,10 @@ __device__ __forceinline__ void write_row(const RegionTest<kVariant, CT>& rt, En
 }
 
 // A full chunk of a task with room runs unrolled without bounds; any other
-// chunk (the last, partial one of a task, or a task without room) runs row
-// by row with checks in a rolled loop (rare, so kept small).
+// chunk (the last, partial one of a task, or any chunk of a task without
+// room) runs row by row with checks in a rolled loop (rare, so kept small).
+// rem = the entries left in the task from this chunk on: the chunk's rows
+// are the first min(R, rem / 64 rounded up) of them.
 template <int R, typename Entry, int kVariant, typename CT>
 __device__ __forceinline__ void write_chunk(const RegionTest<kVariant, CT>& rt, const Entry (&ent)[R], int32_t rem,
                                             int lc, int lane, Kids<Entry>& k)
@@ -724,7 +737,7 @@ __device__ __forceinline__ void write_chunk(const RegionTest<kVariant, CT>& rt, 
         for (int r = 0; r < R; ++r) write_row<false, Entry, kVariant, CT>(rt, ent[r], ~0ull, lc, k);
     } else {
 #pragma nounroll
-        for (int r = 0; r * kWave < rem; ++r)
+        for (int r = 0; r < R && r * kWave < rem; ++r)
             write_row<true, Entry, kVariant, CT>(rt, ent[r], kVariant == 0 ? ~0ull : row_mask(rem, r), lc, k);
     }
 }
@@ -760,14 +773,14 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
 
     TaskFeed feed;
     feed.init(&info->queue[1], NT, a.queue_batch, (int64_t)blockIdx.x * kWaves + wave, (int64_t)gridDim.x * kWaves);
-    bool bad = false;
+    uint32_t bad = 0;   // kErrAt* bits of the checks that failed
     // the next task whose region keeps a child, false at the end
     auto next_task = [&](TaskView& v) -> bool {
         for (;;) {
             const int64_t t = feed.take();
             if (t < 0) return false;
             if (!view_task(tasks, regions, P, L, task_len, t, v)) {
-                bad = true;
+                bad |= kErrAtWriteTask;
                 return false;
             }
             if (keep_bits(dsti, v.r)) return true;
@@ -805,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             if (more) {
                 ++s;
             } else {
-                if (cur.last && !kids_complete(cur, cvi, kc)) bad = true;
+                if (cur.last && !kids_complete(cur, cvi, kc)) bad |= kErrAtWriteVotes;
                 if (!have_next) break;
                 cur = nxt;
                 enter();
@@ -815,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             for (int k = 0; k < R; ++k) ent[k] = nent[k];
         }
     }
-    if (bad && lane == 0) raise_error(ar.error, kErrInternal);
+    if (bad && lane == 0) raise_error(ar.error, kErrInternal | bad | (1u << (kErrLevelShift + l)));
 }
 
 // ------------------------------------------------------------------ k_decide / k_emit
@@ -1083,7 +1096,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                     } else {
                         const int64_t nt = region_tasks(cv[q], a.task_steps);
                         if (ri >= P2 || tk + nt > NT2) {
-                            raise_error(ar.error, kErrInternal);
+                            raise_error(ar.error, kErrInternal | kErrAtEmit | (1u << (kErrLevelShift + l)));
                             continue;
                         }
                         Region C;

@@ -28,7 +28,7 @@ namespace hh {
 namespace {
 
 struct Choice {
-    int32_t task_steps = 4, queue_batch = 0, wg_per_cu = 0;
+    int32_t task_steps = 8, queue_batch = 0, wg_per_cu = 0;
     double ms = 0.0;
 };
 

@@ -27,6 +27,13 @@ constexpr uint32_t kErrPointRange = 2u;     // an input point lies outside [0,W)
 constexpr uint32_t kErrInternal = 4u;       // an index failed a range check
 constexpr uint32_t kErrArena = 8u;          // a level did not fit its arena; rerun larger
 constexpr uint32_t kErrStop = kErrArena | kErrInternal;   // later kernels do nothing
+// With kErrInternal, the check that failed (bits 8..11) and the level it
+// failed at (bit 16 + level), so that the error message names them.
+constexpr uint32_t kErrAtCountTask = 1u << 8;    // k_count: a task's region or range out of bounds
+constexpr uint32_t kErrAtWriteTask = 1u << 9;    // k_write: a task's region or range out of bounds
+constexpr uint32_t kErrAtWriteVotes = 1u << 10;  // k_write: a kept child's votes differ from its count
+constexpr uint32_t kErrAtEmit = 1u << 11;        // emit: a region or task index past the level's totals
+constexpr int kErrLevelShift = 16;
 
 // Edge points are stored packed: x in bits 0..15, y in bits 16..31, so the
 // packed value orders points row-major (y, then x).

@@ -241,6 +241,25 @@ def test_levels_outgrowing_the_arena(hh, membership):
         r.free()
 
 
+@pytest.mark.parametrize("steps", [2, 16, 64])
+def test_long_tasks_without_room(hh, steps):
+    """Long tasks in a context whose arena starts tiny: each level's lists get
+    little more room than they need, so the last tasks of a level have no
+    room for all their entries and run checked, chunk after chunk, through
+    tasks of several chunks; results equal the oracle's for every task
+    size."""
+    w = synth.workload("line256", 2)
+    x, y = oracle.edge_points(w.image)
+    ref = oracle.detect(x, y, w.width, w.height, 40, 8)
+    say(f"case line256 seed 2, tiny arena, {steps} steps per task")
+    with hh.HoughHier(threshold=40, max_depth=8, arena_hint=4096) as ctx:
+        ctx.set_launch(steps, 0, 0)
+        for rep in range(2):
+            r = ctx.detect(image=w.image, width=w.width, height=w.height)
+            check_against_oracle(host_view(r), ref)
+            r.free()
+
+
 def test_batch_in_groups_under_a_memory_limit(hh):
     """An arena limit far below what the whole batch needs: the call runs in
     groups of images (the limit is learnt for the next call), every result
