@@ -516,13 +516,18 @@ def bench_serving(seed, seconds, pool_size=384, lanes=3, max_batch=4):
     torch.cuda.synchronize(dev)
     inputs = [dict(image=d, width=w.width, height=w.height, threshold=w.threshold) for d, w in zip(imgs, pool)]
 
+    warm_failures = []
+
     def server(n_lanes, max_batch):
         srv = HoughHier(threshold=0, membership=True, device=0)
         srv.serve_start(lanes=n_lanes, max_batch=max_batch, queue_capacity=1 << 16)
         for _ in range(2):   # warm the lanes: arena sizes, group limits, the footprint model
             for k in range(0, len(inputs), 16):   # a window at a time: results are freed as they come
                 for t in [srv.submit(**inp) for inp in inputs[k:k + 16]]:
-                    srv.poll(t).free()
+                    try:
+                        srv.poll(t).free()
+                    except Exception as e:   # reported with the results, not raised
+                        warm_failures.append(str(e))
         return srv
 
     def run(srv, arrivals):
@@ -588,6 +593,8 @@ def bench_serving(seed, seconds, pool_size=384, lanes=3, max_batch=4):
         note(f"serving {f}x capacity: per-request launches done")
         out["rates"][f"{f}x"] = {"arrival_rate_hz": rate, "continuous_batching": cb, "per_request": pr}
     out["slab"] = {"continuous_batching": batching.serve_stats(), "per_request": plain.serve_stats()}
+    if warm_failures:
+        out["warmup_failures"] = {"count": len(warm_failures), "first": warm_failures[0]}
     batching.close()
     plain.close()
     return out
@@ -829,31 +836,32 @@ def main():
                                     "GB/s": kb[k] / (kt[f"{k}_ms"] / 1e3) / 1e9 if kt[f"{k}_ms"] > 0 else 0.0}
                          for k in ("count", "write")}}},
     }
+    def extra(key, fn, done):
+        # an extra that fails is reported in its place; the headline stands
+        try:
+            out[key] = fn()
+        except Exception as e:
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+        note(done)
+
     if not args.no_extras:
         if args.workload != "seg1024":
-            out["seg1024"] = single_summary(bench_single("seg1024", args.seed, 30, 3))
-            note("seg1024 done")
-        out["line256"] = single_summary(bench_single("line256", args.seed, 100, 10))
-        out["line256_graph"] = bench_small_graph(args.seed)
-        note("line256 done")
+            extra("seg1024", lambda: single_summary(bench_single("seg1024", args.seed, 30, 3)), "seg1024 done")
+        extra("line256", lambda: single_summary(bench_single("line256", args.seed, 100, 10)), "line256 done")
+        extra("line256_graph", lambda: bench_small_graph(args.seed), "line256 graph done")
         if bits == 32:
-            out["wide_compares"] = single_summary(bench_single(args.workload, args.seed, 5, 2, wide=True))
-            note("wide compares done")
+            extra("wide_compares", lambda: single_summary(bench_single(args.workload, args.seed, 5, 2, wide=True)),
+                  "wide compares done")
         if not args.no_batched:
-            out["batch512"] = bench_batched(args.seed)
-            note("batch512 done")
+            extra("batch512", lambda: bench_batched(args.seed), "batch512 done")
         if not args.no_sweep:
-            out["size_sweep"] = bench_sweep(args.seed)
-            note("size sweep done")
+            extra("size_sweep", lambda: bench_sweep(args.seed), "size sweep done")
         if not args.no_gray:
-            out["gray1024"] = bench_gray(args.seed)
-            note("gray1024 done")
+            extra("gray1024", lambda: bench_gray(args.seed), "gray1024 done")
         if not args.no_solution:
-            out["solution"] = bench_solution(args.seed)
-            note("solution done")
+            extra("solution", lambda: bench_solution(args.seed), "solution done")
         if args.serve_seconds > 0:
-            out["serving"] = bench_serving(args.seed, args.serve_seconds)
-            note("serving done")
+            extra("serving", lambda: bench_serving(args.seed, args.serve_seconds), "serving done")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -505,8 +505,10 @@ Plan make_plan(const hh_ctx* ctx, const hh_input* in)
     return p;
 }
 
-// The message of an internal error: the checks that failed and their levels.
-std::string internal_error_text(uint32_t err)
+// The message of an internal error: the checks that failed and their levels,
+// the values the first failure recorded (scratch: the arena head's scratch
+// words as read back), and the resumes the call made.
+std::string internal_error_text(uint32_t err, const int64_t* scratch, int32_t resumes)
 {
     std::string m = "a kernel index failed its range check";
     const std::pair<uint32_t, const char*> at[] = {
@@ -522,6 +524,12 @@ std::string internal_error_text(uint32_t err)
     for (int l = 0; l < kMaxLevels && kErrLevelShift + l < 32; ++l)
         if (err & (1u << (kErrLevelShift + l))) levels += (levels.empty() ? "" : ",") + std::to_string(l);
     if (!what.empty()) m += " (" + what + (levels.empty() ? "" : "; level " + levels) + ")";
+    if (scratch && scratch[0] == 1) {
+        m += "; first failure: check " + std::to_string(scratch[1] & 0xFFFFFFFF) + " at level " +
+             std::to_string(scratch[1] >> 32) + ", values";
+        for (int k = 2; k < 7; ++k) m += " " + std::to_string(scratch[k]);
+    }
+    m += "; resumes " + std::to_string(resumes);
     return m;
 }
 
@@ -1160,7 +1168,10 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
             ctx->group_points = std::max<int64_t>(1, sum / 2);
             continue;
         }
-        if (g.err & kErrInternal) throw Error{HH_EINTERNAL, internal_error_text(g.err)};
+        if (g.err & kErrInternal)
+            throw Error{HH_EINTERNAL,
+                        internal_error_text(g.err, reinterpret_cast<const int64_t*>(ctx->h_fixed + g.fl.scalar),
+                                            tm.resumes)};
         if (*h_err & kErrPointRange) throw Error{HH_EINVAL, "a device point lies outside the image"};
         counts_known = true;
 
@@ -1576,8 +1587,8 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
             }
         }
     }
-    // Segments: consecutive cells of about kSolSegSlots voter entries (cut by
-    // cell count), at most kSolMaxSegs per tree, and only as many as it takes
+    // Segments: consecutive cells of about kSolSegSlots voter entries, at most
+    // kSolMaxSegs per tree, and only as many as it takes
     // for two segments per compute unit over all trees (a batch of many
     // trees walks each in one segment, in one round); LDS trees first.
     // Bitmaps per segment: in, out (and a work bitmap for device-bitmap
@@ -1607,7 +1618,7 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
         for (int64_t q = 0; q < K; ++q) {
             SolSeg g{};
             g.tree = k;
-            g.c0 = t.n_cells * q / K;
+            g.c0 = t.n_cells * q / K;   // by cell count here; by voter entries on the device
             g.c1 = t.n_cells * (q + 1) / K;
             segs.push_back(g);
             seg_words.push_back(words_total);
@@ -1670,6 +1681,7 @@ hh_status engine_solution(hh_ctx* ctx, hh_result* const* res, int32_t n, double*
     if (n_segs > 0) {
         check(hipMemcpyAsync(d_segs, segs.data(), (size_t)n_segs * sizeof(SolSeg), hipMemcpyHostToDevice, st),
               "copy segments");
+        check(launch_solution_cut(d_trees, d_segs, n_segs, st), "segment bounds");
         if (n_lds > 0)
             check(hipMemcpyAsync(lists[0], first_list.data(), (size_t)n_lds * 4, hipMemcpyHostToDevice, st),
                   "copy list");

@@ -75,6 +75,23 @@ __device__ inline void raise_error(uint32_t* error, uint32_t bits)
     __hip_atomic_fetch_or(G(error), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The first internal failure of a call leaves its check, level and six
+// values in the arena's scratch words (slot 0 is the claim), which the host
+// reads back with the level records and puts in the error message.
+__device__ inline void record_failure(int64_t* scratch, uint32_t at, int level, int64_t a, int64_t b, int64_t c,
+                                      int64_t d, int64_t e)
+{
+    unsigned long long* const claim = reinterpret_cast<unsigned long long*>(G(scratch));
+    if (atomicCAS(claim, 0ull, 1ull) != 0ull) return;
+    int64_t* const v = G(scratch);
+    v[1] = (int64_t)at | ((int64_t)level << 32);
+    v[2] = a;
+    v[3] = b;
+    v[4] = c;
+    v[5] = d;
+    v[6] = e;
+}
+
 // set bits of b at lanes below this lane
 __device__ inline uint32_t lanes_below(uint64_t b)
 {
@@ -818,7 +835,16 @@ __global__ __launch_bounds__(kBlock) void k_write(LevelArgs a)
             if (more) {
                 ++s;
             } else {
-                if (cur.last && !kids_complete(cur, cvi, kc)) bad |= kErrAtWriteVotes;
+                if (cur.last && !kids_complete(cur, cvi, kc)) {
+                    bad |= kErrAtWriteVotes;
+                    if (lane == 0) {
+                        const int4 c4 = ld_const(reinterpret_cast<const int4*>(cvi), (int64_t)cur.r);
+                        record_failure(ar.scalar, kErrAtWriteVotes, l, cur.r, cur.t, kc.keep,
+                                       ((int64_t)kc.pos[0] << 32) | (uint32_t)kc.pos[1],
+                                       ((int64_t)c4.x << 48) | ((int64_t)(c4.y & 0xFFFF) << 32) |
+                                           ((int64_t)(c4.z & 0xFFFF) << 16) | (c4.w & 0xFFFF));
+                    }
+                }
                 if (!have_next) break;
                 cur = nxt;
                 enter();
@@ -1097,6 +1123,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(LevelArgs a)
                         const int64_t nt = region_tasks(cv[q], a.task_steps);
                         if (ri >= P2 || tk + nt > NT2) {
                             raise_error(ar.error, kErrInternal | kErrAtEmit | (1u << (kErrLevelShift + l)));
+                            record_failure(ar.scalar, kErrAtEmit, l, r, ri, P2, tk + nt, NT2);
                             continue;
                         }
                         Region C;

@@ -477,6 +477,37 @@ __global__ void k_solution_finish(const SolTree* trees, int32_t n_trees, const S
     }
 }
 
+// Segment bounds of every tree by voter entries: segment q of K starts at
+// the first cell whose voters start at or past q / K of the tree's entries
+// (cells hold very different numbers of voters, and a round lasts as long as
+// its longest walk).  One thread per segment; member_off grows from cell to
+// cell (voters are back to back), so a binary search finds each bound.  An
+// empty segment (one cell holding two bounds) walks nothing.
+__global__ void k_solution_cut(const SolTree* trees, SolSeg* segs, int32_t n_segs)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_segs) return;
+    const SolTree t = trees[segs[g].tree];
+    const int64_t q = g - t.seg0, K = t.n_segs, n = t.n_cells;
+    if (n <= 0 || K <= 0) return;
+    const int64_t first = ldg(&t.cells[0].member_off);
+    const int64_t total = ldg(&t.cells[n - 1].member_off) + ldg(&t.cells[n - 1].votes) - first;
+    auto bound = [&](int64_t k) -> int64_t {
+        if (k <= 0) return 0;
+        if (k >= K) return n;
+        const int64_t target = first + total * k / K;
+        int64_t lo = 0, hi = n;   // first cell with member_off >= target
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ldg(&t.cells[mid].member_off) < target) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    segs[g].c0 = bound(q);
+    segs[g].c1 = bound(q + 1);
+}
+
 // The rank table of an image's edge points: table[y * W + x] = k for
 // xy[k] = x | y << 16.
 __global__ void k_pixel_rank(const uint32_t* xy, int64_t n_points, int32_t width, int32_t height, int32_t* table)
@@ -569,6 +600,13 @@ hipError_t launch_solution_round(const SolRound& r, hipStream_t s)
     if (m > 0)
         k_solution_collect<<<(int)std::min<int64_t>((m + 255) / 256, 4096), 256, 0, s>>>(
             r.n_segs, r.n_lds, r.changed, r.next_lds, r.next_dev, r.n_next, r.first_walked, r.n_trees);
+    return hipGetLastError();
+}
+
+hipError_t launch_solution_cut(const SolTree* trees, SolSeg* segs, int32_t n_segs, hipStream_t s)
+{
+    if (n_segs <= 0) return hipSuccess;
+    k_solution_cut<<<(n_segs + 255) / 256, 256, 0, s>>>(trees, segs, n_segs);
     return hipGetLastError();
 }
 

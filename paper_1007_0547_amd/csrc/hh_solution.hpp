@@ -67,6 +67,10 @@ struct SolRound {
 // segments whose input changed.  No segment in the next lists: every input
 // stands, and the walk is done.
 hipError_t launch_solution_round(const SolRound& r, hipStream_t s);
+// Each tree's segment bounds (c0, c1) by voter entries: segment q of a tree
+// with K segments starts at the first cell whose voters start at or past
+// q / K of its entries.  Before the first round.
+hipError_t launch_solution_cut(const SolTree* trees, SolSeg* segs, int32_t n_segs, hipStream_t s);
 // Once a merge changed nothing: per tree, plotted flags from `all` and the
 // counts summed over its segments.
 hipError_t launch_solution_finish(const SolTree* trees, int32_t n_trees, const SolSeg* segs, hipStream_t s);

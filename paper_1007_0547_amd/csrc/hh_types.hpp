@@ -189,7 +189,7 @@ struct Arena {
     LevelInfo* info;       // [kMaxLevels + 1]
     int64_t* rec;          // [n_trees][kMaxLevels][kRecCh] tree boundary records (-1: none)
     uint32_t* error;
-    int64_t* scalar;       // [8] scratch (edge count, ...)
+    int64_t* scalar;       // [8] the first internal failure: claim, check and level, six values
     Cell* cells;
     int64_t cells_cap;
     void* members;         // voters of the detected cells, cell after cell
