@@ -42,6 +42,28 @@ def points(img):
 
 
 # --------------------------------------------------------------------------
+# Sec. 2: the edge points a binary image contributes
+
+
+def test_edge_points_row_major(orc):
+    """Edge points are the nonzero pixels, ranked in row-major order (y, then
+    x): a hand-made image, then random ones against a plain double loop."""
+    img = np.array([[0, 3, 0, 0],
+                    [1, 0, 0, 9],
+                    [0, 0, 1, 0]], np.uint8)
+    x, y = orc.edge_points(img)
+    assert x.dtype == np.int32 and y.dtype == np.int32
+    assert x.tolist() == [1, 0, 3, 2] and y.tolist() == [0, 1, 1, 2]
+    for seed in range(3):
+        im = tiny_image(seed, 13, 7, 0.3)
+        want = [(c, r) for r in range(im.shape[0]) for c in range(im.shape[1]) if im[r, c]]
+        x, y = orc.edge_points(im)
+        assert list(zip(x.tolist(), y.tolist())) == want
+    x, y = orc.edge_points(np.zeros((5, 6), np.uint8))
+    assert len(x) == 0 and len(y) == 0
+
+
+# --------------------------------------------------------------------------
 # Sec. 2: the corner test and getcode()
 
 
