@@ -70,7 +70,9 @@ typedef enum {
     HH_EDEVICE = -4,     /* HIP error, or the device is not a gfx950                  */
     HH_EBUSY = -5,       /* no free slot                                              */
     HH_ECANCELED = -6,
-    HH_EINTERNAL = -7    /* an internal consistency check failed                      */
+    HH_EINTERNAL = -7    /* an internal consistency check failed; the error text names
+                            the check, its level, the first failure's indices and
+                            totals, and the call's arena resumes                      */
 } hh_status;
 
 typedef enum {
