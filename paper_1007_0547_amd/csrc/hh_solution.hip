@@ -12,7 +12,8 @@
 //
 // The walk is sequential by definition.  It runs here as a fixpoint of
 // independent walks: a tree's cells are cut into segments of consecutive
-// cells, one workgroup each, and every segment walks its cells starting from
+// cells holding about equal numbers of voters (k_solution_cut), one
+// workgroup each, and every segment walks its cells starting from
 // an input set of points taken as plotted before it.  After a round, each
 // segment's input becomes the union of the points the segments before it
 // plotted in that round; when no input changes, every segment walked from
