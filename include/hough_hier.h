@@ -371,6 +371,11 @@ typedef struct {
     int64_t retries;           /* runs that found the slab full and ran again         */
     int64_t pending;           /* requests waiting for a lane                         */
     double bytes_per_unit;     /* the footprint model's beta (bytes per E * 2^depth)  */
+    int64_t internal_reruns;   /* batches whose kernels' consistency check failed
+                                  (HH_EINTERNAL, no result made) and that ran again  */
+    int64_t internal_failures; /* of those, reruns that failed the same way (their
+                                  requests then run one by one)                       */
+    char first_internal_error[512];   /* the first such failure's text, or ""       */
 } hh_serve_stats;
 
 /* Copy the serving counters of ctx into *out.

@@ -91,7 +91,8 @@ class _ServeConfig(C.Structure):
 class _ServeStats(C.Structure):
     _fields_ = [("slab_bytes", C.c_int64), ("slab_used", C.c_int64), ("slab_batches", C.c_int64),
                 ("outside_batches", C.c_int64), ("retries", C.c_int64), ("pending", C.c_int64),
-                ("bytes_per_unit", C.c_double)]
+                ("bytes_per_unit", C.c_double), ("internal_reruns", C.c_int64),
+                ("internal_failures", C.c_int64), ("first_internal_error", C.c_char * 512)]
 
 
 class _Launch(C.Structure):
@@ -515,12 +516,16 @@ class HoughHier:
     def serve_stats(self) -> dict:
         """Serving counters (``hough_hier_serve_stats``): the slab's size and
         use, batches run inside and outside it, reruns in a larger interval,
-        waiting requests and the footprint model's bytes per unit."""
+        waiting requests, the footprint model's bytes per unit, and batches
+        whose internal consistency check failed (rerun, failed again, the
+        first failure's text)."""
         st = _ServeStats()
         s = _lib.hough_hier_serve_stats(self._h, C.byref(st))
         if s != 0:
             raise HHError(s, self.last_error())
-        return {k: getattr(st, k) for k, _ in _ServeStats._fields_}
+        out = {k: getattr(st, k) for k, _ in _ServeStats._fields_}
+        out["first_internal_error"] = st.first_internal_error.decode(errors="replace")
+        return out
 
     def submit(self, x=None, y=None, *, image=None, gray=None, edge_threshold: int = 0, width: int,
                height: int, threshold: int = -1, max_depth: Optional[int] = None) -> int:

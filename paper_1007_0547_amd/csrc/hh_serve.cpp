@@ -21,6 +21,7 @@
 #include "hh_serve.hpp"
 
 #include <algorithm>
+#include <cstring>
 #include <exception>
 #include <new>
 
@@ -138,9 +139,22 @@ void run_lane(Server* sv, int lane)
             c->arena_hint_bytes = want;
             std::string err;
             hh_status st = HH_OK;
-            bool outside = false;
+            bool outside = false, reran = false;
             for (int attempt = 0;; ++attempt) {
                 st = lane_call(c, outside, [&] { return engine_detect_batch(c, ins.data(), n, outs.data()); }, err);
+                if (st == HH_EINTERNAL) {
+                    // a consistency check of the kernels failed (no result was
+                    // made): counted, its first text kept, and the batch run
+                    // once more
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    if (sv->first_internal_error.empty()) sv->first_internal_error = err;
+                    if (!reran) {
+                        ++sv->internal_reruns;
+                        reran = true;
+                        continue;
+                    }
+                    ++sv->internal_failures;
+                }
                 if (st != HH_ENOMEM || outside) break;
                 std::unique_lock<std::mutex> lk(sv->mu);
                 ++sv->retries;
@@ -390,6 +404,11 @@ hh_status serve_stats(hh_ctx* ctx, hh_serve_stats* out)
     out->retries = sv->retries;
     out->pending = (int64_t)sv->pending.size();
     out->bytes_per_unit = sv->beta;
+    out->internal_reruns = sv->internal_reruns;
+    out->internal_failures = sv->internal_failures;
+    const size_t nt = std::min(sv->first_internal_error.size(), sizeof(out->first_internal_error) - 1);
+    std::memcpy(out->first_internal_error, sv->first_internal_error.data(), nt);
+    out->first_internal_error[nt] = 0;
     return HH_OK;
 }
 

@@ -64,6 +64,8 @@ struct Server {
     int64_t budget = 0;
     int running = 0;                   // batches on the lanes
     int64_t slab_batches = 0, outside_batches = 0, retries = 0;
+    int64_t internal_reruns = 0, internal_failures = 0;   // batches whose internal check failed, and again
+    std::string first_internal_error;
     double beta = 12.0;
     double density = 0.03;
 };

@@ -162,6 +162,7 @@ def test_slab_holds_batches_and_held_results(hh):
         srv.serve_start(lanes=2, max_batch=4)
         st = srv.serve_stats()
         assert st["slab_bytes"] == 256 << 20 and st["slab_used"] == 0
+        assert st["internal_reruns"] == 0 and st["internal_failures"] == 0 and st["first_internal_error"] == ""
         # requests freed as they complete: all inside the slab
         for w in ws[:8]:
             r = srv.poll(srv.submit(image=w.image, width=w.width, height=w.height, threshold=w.threshold))
@@ -186,4 +187,7 @@ def test_slab_holds_batches_and_held_results(hh):
             one.free()
         for _, r in held:
             r.free()
-        assert srv.serve_stats()["slab_used"] == 0
+        st = srv.serve_stats()
+        assert st["slab_used"] == 0
+        # a batch whose internal check fails runs once more; it never fails twice here
+        assert st["internal_failures"] == 0, st
