@@ -353,28 +353,38 @@ struct Caps {
     int64_t cells, mem, half, work;   // cells, member entries, bytes per half, scratch bytes
 };
 
-int64_t arena_bytes(const FixedLayout& f, const Caps& c, int32_t entry_bytes)
+// An arena has two parts: the front (the fixed part, the cells and the
+// voters), which the results of a group keep, and the back (the two level
+// halves and the per-level scratch), which only the group's levels use.
+int64_t arena_front_bytes(const FixedLayout& f, const Caps& c, int32_t entry_bytes)
 {
-    return f.bytes + align256(c.mem * entry_bytes) + 2 * c.half + c.work;
+    return f.bytes + align256(c.mem * entry_bytes);
 }
 
-Arena carve(char* base, const FixedLayout& f, int32_t n_trees, const Caps& c, int32_t entry_bytes)
+int64_t arena_back_bytes(const Caps& c) { return 2 * c.half + c.work; }
+
+int64_t arena_bytes(const FixedLayout& f, const Caps& c, int32_t entry_bytes)
+{
+    return arena_front_bytes(f, c, entry_bytes) + arena_back_bytes(c);
+}
+
+// The parts of an arena whose front and back start at `front` and `back`
+// (one block holds both when back = front + arena_front_bytes).
+Arena carve(char* front, char* back, const FixedLayout& f, int32_t n_trees, const Caps& c, int32_t entry_bytes)
 {
     Arena a{};
-    a.info = reinterpret_cast<LevelInfo*>(base + f.info);
-    a.rec = reinterpret_cast<int64_t*>(base + f.rec);
-    a.error = reinterpret_cast<uint32_t*>(base + f.error);
-    a.scalar = reinterpret_cast<int64_t*>(base + f.scalar);
-    a.cells = reinterpret_cast<Cell*>(base + f.cells);
+    a.info = reinterpret_cast<LevelInfo*>(front + f.info);
+    a.rec = reinterpret_cast<int64_t*>(front + f.rec);
+    a.error = reinterpret_cast<uint32_t*>(front + f.error);
+    a.scalar = reinterpret_cast<int64_t*>(front + f.scalar);
+    a.cells = reinterpret_cast<Cell*>(front + f.cells);
     a.cells_cap = c.cells;
-    char* p = base + f.bytes;
-    a.members = p;
+    a.members = front + f.bytes;
     a.mem_cap = c.mem;
-    p += align256(c.mem * entry_bytes);
-    a.half[0] = p;
-    a.half[1] = p + c.half;
+    a.half[0] = back;
+    a.half[1] = back + c.half;
     a.half_cap = c.half;
-    a.work = p + 2 * c.half;
+    a.work = back + 2 * c.half;
     a.work_cap = c.work;
     a.n_trees = n_trees;
     a.entry_bytes = entry_bytes;
@@ -659,7 +669,8 @@ struct BudgetExceeded {
 // the first back_bytes of the trees' block (the trees with their point
 // counts, for the first group also the staging error word) in h_trees.
 struct GroupRun {
-    DevBuf arena;
+    DevBuf arena;   // the front part (or the whole caller-arena view)
+    DevBuf back;    // the back part (pool arenas only)
     FixedLayout fl{};
     Arena ar{};
     uint32_t err = 0;
@@ -780,7 +791,8 @@ void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, T
             const Caps want{ctx->cells_cap, members ? ctx->mem_cap : 0, ctx->half_cap, ctx->work_cap};
             const Caps caps = fit_caps(want, avail, n_trees, entry_bytes, members);
             g.fl = fixed_layout(n_trees, caps.cells);
-            g.ar = carve(whole.as<char>(), g.fl, n_trees, caps, entry_bytes);
+            g.ar = carve(whole.as<char>(), whole.as<char>() + arena_front_bytes(g.fl, caps, entry_bytes), g.fl, n_trees,
+                         caps, entry_bytes);
             g.arena = DevBuf::view(whole.get(), whole.bytes());
             bool ok;
             if (graph && attempt == 0) {
@@ -861,9 +873,10 @@ void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, T
         }
         const FixedLayout nfl = fixed_layout(n_trees, caps.cells);
         if (run == 0 && (double)arena_bytes(nfl, caps, entry_bytes) > budget) throw BudgetExceeded{budget};
-        DevBuf narena(pool, (size_t)arena_bytes(nfl, caps, entry_bytes));
+        DevBuf nfront(pool, (size_t)arena_front_bytes(nfl, caps, entry_bytes));
+        DevBuf nback(pool, (size_t)arena_back_bytes(caps));
         mem.arena_peak = std::max<int64_t>(mem.arena_peak, arena_bytes(nfl, caps, entry_bytes));
-        const Arena nar = carve(narena.as<char>(), nfl, n_trees, caps, entry_bytes);
+        const Arena nar = carve(nfront.as<char>(), nback.as<char>(), nfl, n_trees, caps, entry_bytes);
         if (from < 0) {
             check(launch_clear(nar, n_rec, st), "clear");
         } else {
@@ -882,8 +895,12 @@ void run_group(hh_ctx* ctx, CallMem& mem, const Plan& p0, int32_t entry_bytes, T
             copy(nar.work, g.ar.work, work_layout(nullptr, lv.P, lv.NT).end);
             sync(ctx);   // the old arena goes back to the pool only once it is read
         }
-        if (run > 0) g.arena.discard();   // a smaller arena is of no further use
-        g.arena = std::move(narena);
+        if (run > 0) {   // a smaller arena is of no further use
+            g.arena.discard();
+            g.back.discard();
+        }
+        g.arena = std::move(nfront);
+        g.back = std::move(nback);
         g.ar = nar;
         g.fl = nfl;
         if (launch_levels(from)) {
@@ -1191,11 +1208,14 @@ hh_status engine_detect_batch(hh_ctx* ctx, const hh_input* inputs, int32_t n, hh
         gs->call = store;
         const Cell* gcells = g.ar.cells;
         const void* gmembers = g.ar.members;
-        if (k0 == 0 && k1 == n) {
-            gs->arena = std::move(g.arena);   // one group: results point into its arena
+        if ((k0 == 0 && k1 == n) || !mem.base) {
+            // one group, or a pool arena: the results keep the front part
+            // (cells and voters) and point into it; the back part returns to
+            // the pool when the group ends
+            gs->arena = std::move(g.arena);
         } else {
-            // several groups: keep exact copies of the cells and voters, and
-            // let the next group reuse the arena
+            // several groups in the caller's arena: keep exact copies of the
+            // cells and voters, and let the next group reuse the arena
             const int64_t nc = info[dmax].cells_base + info[dmax].cells;
             const int64_t nm = p0.membership ? info[dmax].mem_base + info[dmax].mem : 0;
             gs->cells = DevBuf(pool, (size_t)std::max<int64_t>(nc, 1) * sizeof(Cell));

@@ -151,9 +151,11 @@ struct CallStore {
 };
 
 // Device memory of one group of a call's images (the images whose levels
-// ran in one arena).  A call in one group keeps the arena (its cells and
-// voters are inside); a call in several groups keeps exact copies of each
-// group's cells and voters and reuses the arena for the next group.
+// ran in one arena).  A group keeps its arena's front part (level records,
+// cells and voters; the level halves and scratch of the back part go back to
+// the pool when the group ends), except in several groups of a call in the
+// caller's arena, which reuse that arena: there each group keeps exact
+// copies of its cells and voters.
 struct GroupStore {
     std::shared_ptr<CallStore> call;
     DevBuf arena;
